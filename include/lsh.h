@@ -1,0 +1,200 @@
+/*
+ * lsh.h -- C ABI of the MI355X Lippmann--Schwinger homogenisation solver.
+ *
+ * The library solves the discrete Lippmann--Schwinger system of the periodic
+ * corrector problem (Brisard & Legoll, "Periodic homogenization using the
+ * Lippmann--Schwinger formalism", eq. (13)):
+ *
+ *   (A_beta - A0)^{-1} tau_beta + DFT^{-1}_beta[ Gamma_hat_k DFT_k[tau] ] = p,  beta in I0,
+ *   tau_beta = 0 outside I0,
+ *
+ * matrix-free on one GPU, and returns the polarisation tau, the strain
+ * estimate p - Gamma tau and the homogenised matrix A*_h p = A0 p + <tau>
+ * (Theorem 4).  Physics: scalar conduction in 2D/3D (c = d components per
+ * voxel) and 3D linear elasticity (c = 6 Mandel components
+ * (e11, e22, e33, sqrt2 e23, sqrt2 e13, sqrt2 e12)).
+ *
+ * Conventions for every entry point:
+ *  - Fields are stored [load][component][z][y][x] with x fastest (2D: nz = 1).
+ *  - Matrices (moduli, A0, effective tensors) are row-major FP64.
+ *  - "Host" pointers are read during the call and may be reused at once.
+ *    "Device" pointers must stay valid until the work queued on the
+ *    context's stream has finished; the library never frees them.
+ *  - The library never allocates device memory: the caller binds one
+ *    workspace buffer (lsh_workspace_bytes / lsh_bind_workspace).
+ *  - Every entry point returns an lsh_status; nothing is thrown across the
+ *    ABI.  Arguments are validated before any GPU work is queued; on an
+ *    error the context keeps its previous state and lsh_last_error() holds
+ *    a message.
+ *  - A context is bound to one HIP stream and is not thread-safe.
+ */
+#ifndef LSH_H
+#define LSH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lsh_ctx lsh_ctx;
+
+typedef enum {
+  LSH_OK = 0,
+  LSH_MAXIT = 1,        /* warning: results valid but a load did not converge */
+  LSH_EINVAL = -1,      /* invalid argument */
+  LSH_ENOMEM = -2,      /* workspace missing or too small */
+  LSH_EHIP = -3,        /* HIP runtime error */
+  LSH_EHYP2 = -4,       /* A_phase - A0 neither zero nor definite (hypothesis (2)) */
+  LSH_EBREAKDOWN = -5,  /* CG breakdown: p.Lp <= 0 (the system is not positive definite) */
+  LSH_ENUMERIC = -6,    /* NaN or Inf met during the solve */
+  LSH_ESTATE = -7       /* call out of order (e.g. solve before phases are set) */
+} lsh_status;
+
+enum { LSH_SCALAR = 0, LSH_ELASTIC = 1 };            /* physics */
+enum { LSH_FP64 = 0, LSH_MIXED = 1 };                /* precision */
+enum { LSH_GREEN_TRUNCATED = 0, LSH_GREEN_FILTERED = 1 };
+enum { LSH_SOLVER_BASIC = 0, LSH_SOLVER_CG = 1 };
+enum { LSH_HOST = 0, LSH_DEVICE = 1 };               /* memory space of a pointer */
+enum { LSH_F64 = 0, LSH_F32 = 1 };                   /* element type of a field buffer */
+enum { LSH_FIELD_TAU = 0, LSH_FIELD_STRAIN = 1 };
+
+/* Per-load outcome of lsh_solve. */
+typedef struct {
+  int32_t iterations;     /* operator applications spent on this load (inner + outer) */
+  int32_t status;         /* lsh_status of this load */
+  double rel_residual;    /* ||b - L tau||_2 / ||b||_2, recomputed in FP64 after the solve */
+} lsh_load_report;
+
+/* Whole-solve outcome of lsh_solve. */
+typedef struct {
+  int64_t applications_fp64;   /* FP64 operator applications (all loads, each counted once per load) */
+  int64_t applications_fp32;   /* FP32 operator applications (mixed precision inner solves) */
+  int32_t outer_iterations;    /* iterative-refinement steps (mixed precision), else 0 */
+  int32_t pad;
+  double seconds;              /* wall time of the solve on the host clock (stream synchronised) */
+} lsh_solve_report;
+
+/*
+ * Create a context for a grid of n[0] x n[1] (x n[2]) voxels along x, y (, z)
+ * (the unit cell (0,1)^dim with h_a = 1/n[a], Section 3.1).
+ *   dim        2 or 3 (elasticity needs 3).
+ *   n          voxels per axis; each a power of two, n[0] >= 4, n[1], n[2] >= 2, all <= 1024.
+ *   physics    LSH_SCALAR or LSH_ELASTIC.
+ *   precision  LSH_FP64: FP64 fields, transforms and reductions.
+ *              LSH_MIXED: FP32 fields and transforms with FP64 dot products,
+ *              FP64 A*, and FP64 iterative refinement of the residual.
+ *   max_loads  largest batch of macroscopic loads solved together (>= 1).
+ *   stream     hipStream_t the context queues its work on (NULL: the null stream).
+ * Does not touch the GPU.  *out receives the context.
+ */
+lsh_status lsh_create(lsh_ctx** out, int dim, const int64_t* n, int physics, int precision,
+                      int max_loads, void* stream);
+
+/* Release the context (host memory only; the bound workspace stays the caller's). */
+lsh_status lsh_destroy(lsh_ctx* ctx);
+
+/* Bytes of device workspace the context needs (256-byte aligned base expected). */
+lsh_status lsh_workspace_bytes(const lsh_ctx* ctx, size_t* bytes);
+
+/* Bind caller-owned device memory of at least lsh_workspace_bytes bytes.
+ * The library carves every field, spectrum, table and reduction buffer out of it. */
+lsh_status lsh_bind_workspace(lsh_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/*
+ * Reference medium A0 (Section 2.2.2): a constant symmetric positive definite
+ * c x c matrix.  Scalar: any SPD d x d matrix.  Elastic: an isotropic 6x6 Mandel
+ * stiffness (lambda0 in the upper-left 3x3 off-diagonal, 2 mu0 + lambda0 on its
+ * diagonal, 2 mu0 on the shear diagonal); other forms return LSH_EINVAL.
+ */
+lsh_status lsh_set_reference(lsh_ctx* ctx, const double* A0);
+
+/*
+ * Microstructure: one phase id per voxel (uint8, [z][y][x]) in host or device
+ * memory, and nphase (1..32) c x c moduli (conductivity, or Mandel stiffness)
+ * in host memory, phase-major.  A voxel whose phase modulus equals A0 exactly
+ * is outside I0 (its polarisation vanishes).  Voxel moduli are the phase
+ * values (no sub-voxel averaging of eq. def_ah).  Hypothesis (2) is checked
+ * at lsh_solve/lsh_apply time against the current A0: every other phase needs
+ * A_phase - A0 definite (either sign), else LSH_EHYP2.  Phase ids >= nphase are
+ * an error (checked on host data; device data must be valid).
+ */
+lsh_status lsh_set_phases(lsh_ctx* ctx, const uint8_t* phase, int mem, int nphase,
+                          const double* moduli);
+
+/* Discrete Green operator: truncated (eqs. 14/15 with the Nyquist rule of
+ * Section 3.2.1) or filtered (Section 3.2.2).  Default: filtered. */
+lsh_status lsh_set_green(lsh_ctx* ctx, int variant);
+
+/*
+ * Solve eq. (13) for nload (1..max_loads) macroscopic loads p_l (host,
+ * nload x c row-major FP64; Mandel in elasticity) with the basic fixed-point
+ * scheme or conjugate gradients, starting from tau = 0, until
+ * ||b - L tau||_2 <= tol ||b||_2 with b = p on I0 (mixed precision: the FP64
+ * refined residual), or maxit operator applications per load.
+ *   reports   host array of nload lsh_load_report (may be NULL).
+ *   summary   host lsh_solve_report (may be NULL).
+ * Returns LSH_OK, LSH_MAXIT (results valid, some load unconverged), or an error.
+ * The basic scheme converges only when A0 dominates (scalar isotropic:
+ * max|a - a0| < a0); CG needs a positive definite system (A0 softer than every
+ * phase) and reports LSH_EBREAKDOWN otherwise.
+ */
+lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, double tol,
+                     int maxit, lsh_load_report* reports, lsh_solve_report* summary);
+
+/*
+ * Copy a field of the last solve for load `load` into dst
+ * ([component][z][y][x], dtype LSH_F64 or LSH_F32, host or device memory):
+ *   LSH_FIELD_TAU     the polarisation tau;
+ *   LSH_FIELD_STRAIN  p - Gamma tau on every voxel (the estimate of p + grad w_p).
+ */
+lsh_status lsh_get_field(lsh_ctx* ctx, int load, int which, void* dst, int dtype, int mem);
+
+/* Mean stress A0 p_l + <tau_l> of the last solve, host FP64 array nload x c.
+ * With the c unit loads, row l is column l of the homogenised matrix A*_h. */
+lsh_status lsh_get_effective(lsh_ctx* ctx, double* sigma_mean);
+
+/*
+ * Matrix-free operator of eq. (13): out_l = 1_{I0} ((A - A0)^{-1} tau_l + Gamma tau_l)
+ * for nload fields tau (device, [load][component][z][y][x], element type
+ * dtype: LSH_F64 uses the FP64 kernels, LSH_F32 the FP32 ones).  out is a
+ * device buffer of the same shape and type; it may not alias tau.
+ */
+lsh_status lsh_apply(lsh_ctx* ctx, int nload, const void* tau, void* out, int dtype);
+
+/*
+ * Forward DFT of nload real fields (device, [load][component][z][y][x],
+ * dtype LSH_F64/LSH_F32) into the library's packed half spectrum, copied to
+ * `spec` (device): complex [load][component][nz][ny][nx/2] (interleaved
+ * re,im; entry kx = 0 holds the kx = 0 column) followed by the Nyquist plane
+ * complex [load][component][nz][ny] (kx = nx/2).  Unnormalised, sign -1
+ * (Section 3.1).  Exposed to test and profile the transform passes.
+ */
+lsh_status lsh_forward_dft(lsh_ctx* ctx, int nload, const void* field, void* spec, int dtype);
+
+/* Bytes of the packed spectrum of one field for dtype (see lsh_forward_dft). */
+lsh_status lsh_spectrum_bytes(const lsh_ctx* ctx, int dtype, size_t* bytes);
+
+/*
+ * Kernel timing: when enabled, every kernel launch is bracketed by HIP events
+ * on the context's stream and accumulated per kernel class.
+ * lsh_kernel_times fills up to cap entries of names (static strings),
+ * total milliseconds and launch counts since the last reset; *count receives
+ * the number of classes.  Reading synchronises the stream.
+ */
+lsh_status lsh_set_timing(lsh_ctx* ctx, int enable);
+lsh_status lsh_kernel_times(lsh_ctx* ctx, const char** names, double* total_ms, int64_t* launches,
+                            int cap, int* count);
+
+/* Message of the last error on this context ("" when none). */
+const char* lsh_last_error(const lsh_ctx* ctx);
+
+/* Library version string. */
+const char* lsh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSH_H */

@@ -195,6 +195,22 @@ def finite_difference(shape, A0, a_slice=None) -> np.ndarray:
     return out
 
 
+def at(shape, physics, A0, variant, kidx) -> np.ndarray:
+    """Table entries at the DFT index vectors ``kidx`` (rows of physical-axis
+    indices (kx, ky[, kz])), evaluated by the same definitions on a
+    one-point view of the grid.  Returns (n, c, c)."""
+    kidx = np.atleast_2d(np.asarray(kidx, dtype=np.int64))
+    d = len(shape)
+    out = []
+    for k in kidx:
+        # the entry of the full table at array index reversed(k)
+        sl = slice(int(k[d - 1]), int(k[d - 1]) + 1)
+        T = table(shape, physics, A0, variant, a_slice=sl)
+        idx = (0,) + tuple(int(k[d - 1 - ax]) for ax in range(1, d))
+        out.append(T[idx])
+    return np.stack(out)
+
+
 def table(shape, physics, A0, variant, a_slice=None) -> np.ndarray:
     if variant == "truncated":
         return truncated(shape, physics, A0, a_slice)

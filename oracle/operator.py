@@ -86,18 +86,36 @@ def _fft_axes(pb):
     return tuple(range(1, pb.d + 1))
 
 
+_TABLE_CACHE = {}
+_CACHE_LIMIT = 2.0e8   # table entries kept in memory (doubles)
+
+
+def _slab_table(pb, sl):
+    key = (pb.shape, pb.physics, np.asarray(pb.A0).tobytes(), pb.green)
+    full = _TABLE_CACHE.get(key)
+    if full is not None:
+        return full[sl]
+    if pb.nvox * pb.c * pb.c <= _CACHE_LIMIT:
+        if len(_TABLE_CACHE) > 8:
+            _TABLE_CACHE.clear()
+        full = _green.table(pb.shape, pb.physics, pb.A0, pb.green)
+        _TABLE_CACHE[key] = full
+        return full[sl]
+    return _green.table(pb.shape, pb.physics, pb.A0, pb.green, a_slice=sl)
+
+
 def gamma_apply(pb: Problem, tau: np.ndarray, slab: int = 16) -> np.ndarray:
     """DFT^{-1}[Gamma_hat_k DFT_k[tau]] for tau of shape (c, *grid).
 
-    The Green table is built slab by slab along the slowest array axis to
-    bound memory on large grids."""
+    The Green table is evaluated once per problem when it fits in memory, and
+    slab by slab along the slowest array axis otherwise."""
     axes = _fft_axes(pb)
     th = sfft.fftn(tau, axes=axes, workers=-1)
     out = np.empty_like(th)
     n0 = pb.shape[0]
     for s in range(0, n0, slab):
         sl = slice(s, min(s + slab, n0))
-        G = _green.table(pb.shape, pb.physics, pb.A0, pb.green, a_slice=sl)
+        G = _slab_table(pb, sl)
         # G: (n, ..., c, c);  th[:, sl]: (c, n, ...)
         out[:, sl] = np.einsum("...ij,j...->i...", G, th[:, sl])
     res = sfft.ifftn(out, axes=axes, workers=-1)

@@ -1,0 +1,76 @@
+"""Builds the HIP library ``_lib/liblsh.so`` for gfx950 with hipcc.
+
+Translation units compile in parallel (one hipcc per unit), then link into one
+shared library.  ``python -m paper_1411_0330_amd.build`` rebuilds it.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIBDIR = os.path.join(HERE, "_lib")
+LIB = os.path.join(LIBDIR, "liblsh.so")
+OBJDIR = os.path.join(ROOT, "_build", "obj")
+
+ARCH = "gfx950"
+FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
+         # keep packed FP32 instructions out of the generated code
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-I", CSRC, "-I", INCLUDE]
+
+UNITS = [
+    ("k_x.hip", "k_x_f32.o", ["-DLSH_X_TYPE=float"]),
+    ("k_x.hip", "k_x_f64.o", ["-DLSH_X_TYPE=double"]),
+    ("k_y.hip", "k_y.o", []),
+    ("k_z.hip", "k_z_f32.o", ["-DLSH_Z_TYPE=float"]),
+    ("k_z.hip", "k_z_f64.o", ["-DLSH_Z_TYPE=double"]),
+    ("runtime.hip", "runtime.o", []),
+]
+
+
+def hipcc() -> str:
+    for cand in (shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def _compile(unit):
+    src, obj, extra = unit
+    cmd = [hipcc(), *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", os.path.join(OBJDIR, obj)]
+    proc = subprocess.run(cmd, capture_output=True, text=True)
+    if proc.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src} {extra}:\n{proc.stderr[-6000:]}")
+    return obj
+
+
+def build(verbose: bool = True, jobs: int | None = None) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+    os.makedirs(LIBDIR, exist_ok=True)
+    subprocess.run([sys.executable, os.path.join(CSRC, "gen_consts.py")], check=True)
+    jobs = jobs or min(len(UNITS), max(1, (os.cpu_count() or 2)))
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        for obj in ex.map(_compile, UNITS):
+            if verbose:
+                print(f"[build] compiled {obj}", flush=True)
+    tmp = LIB + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC",
+           *[os.path.join(OBJDIR, u[1]) for u in UNITS], "-o", tmp]
+    proc = subprocess.run(cmd, capture_output=True, text=True)
+    if proc.returncode != 0:
+        raise RuntimeError(f"link failed:\n{proc.stderr[-6000:]}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"[build] wrote {LIB}", flush=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()

@@ -1,0 +1,68 @@
+// Launchers of the transform passes, dispatched on the (power-of-two) axis
+// lengths to the compile-time kernel instances.  Each launcher returns the
+// number of workgroups along x of the grid it queued (the number of partial
+// sums a reducing kernel wrote per load), or -1 for an unsupported size.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace lsh {
+
+// ---------------------------------------------------------------------------
+// tile configuration (compile time)
+// ---------------------------------------------------------------------------
+template <typename T> constexpr int min_tx() { return sizeof(T) == 4 ? 16 : 8; }  // 128-byte rows
+
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// points per thread
+template <typename T> constexpr int p_xfwd(int mx) { return cmin(8, mx); }
+template <typename T, int C> constexpr int p_xinv(int mx) {
+  return cmin((C == 6 && sizeof(T) == 8) ? 4 : 8, mx);
+}
+template <typename T> constexpr int p_y(int n) { return cmin(sizeof(T) == 4 ? 16 : 8, n); }
+template <typename T, int C> constexpr int p_z(int n) {
+  return cmin(C == 6 ? (sizeof(T) == 4 ? 8 : 4) : (sizeof(T) == 4 ? 16 : 8), n);
+}
+
+// pencils per workgroup for strided passes: >= 128-byte rows, about 256 threads,
+// at most 64 KiB of exchange space and 1024 threads
+template <typename T> constexpr int tx_strided(int n, int p) {
+  const int threads_per_pencil = n / p;
+  int tx = cmax(min_tx<T>(), 256 / threads_per_pencil);
+  tx = cmin(tx, 64);
+  while (tx > 1 && (long)tx * n * 2 * (int)sizeof(T) > 65536) tx /= 2;
+  while (tx > 1 && tx * threads_per_pencil > 1024) tx /= 2;
+  return tx;
+}
+
+template <typename T>
+struct XfwdArgs {
+  Geo g;
+  int mode;
+  const T* src;
+  T* pdir;
+  const float* dsrc;
+  cpx<T>* smain;
+  cpx<T>* snyq;
+  const cpx<T>* twx;
+  const LoadState* st;
+};
+
+template <typename T> int launch_xfwd(hipStream_t s, const XfwdArgs<T>& a, int nload);
+template <typename T> int launch_y(hipStream_t s, const Geo& g, int dir, cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw,
+                                   const LoadState* st, int nload);
+template <typename T> int launch_zg(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb,
+                                    int zmode, cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw, const LoadState* st,
+                                    int nload);
+template <typename T> int launch_xinv(hipStream_t s, const XinvArgs<T>& a, int nload);
+
+// number of workgroups per load of the reducing passes (partials sizing)
+inline long long xinv_blocks(const Geo& g, int p) {
+  const int tr = g.mx / p;
+  const int rpw = 256 / tr;
+  return ((long long)g.nz * g.ny + rpw - 1) / rpw;
+}
+
+}  // namespace lsh

@@ -1,0 +1,286 @@
+// Device evaluation of the discrete Green operators applied to one
+// wave-vector's c-vector of polarisation spectra.
+//
+// Gamma0_hat(xi) = xi xi^T / (xi^T A0 xi) (Section 2.2.1; zero at xi = 0).
+// Truncated (eqs. 14/15): xi = centred index; if any axis of even length sits
+// at N/2 the operator is A0^{-1} (Nyquist rule of Section 3.2.1).
+// Filtered (Section 3.2.2): sum over the 2^d aliases k_a and k_a - N_a with
+// weights prod cos^2(pi k_a/(2N_a)) / sin^2(pi k_a/(2N_a)), k_a in [0, N_a).
+// Physical frequencies are used (alias k + nN); Gamma0_hat has degree 0.
+//
+// Elasticity with an isotropic reference (lambda0, mu0): for a unit direction
+// n, Gamma0_hat tau = (n (x) tau n + tau n (x) n)/(2 mu0)
+//                    - kappa (n.tau.n) n (x) n,  kappa = (lambda0+mu0)/(mu0 (lambda0+2 mu0)),
+// which follows from the acoustic tensor mu0 |xi|^2 I + (lambda0+mu0) xi xi^T.
+// A sum of such terms with weights w is carried by B = sum w n n^T and the
+// fully symmetric D = sum w n n n n:  out = (B tau + tau B)/(2 mu0) - kappa D:tau.
+#pragma once
+
+#include "fft_dev.hpp"
+
+namespace lsh {
+
+enum : int { kGreenTruncated = 0, kGreenFiltered = 1 };
+
+// Parameters shared by all wave-vectors (kernel argument, by value).
+struct GreenParams {
+  int variant;
+  int n[3];          // grid along x, y, z (n[2] = 1 in 2D)
+  double a0[9];      // scalar reference, row-major 3x3 (2D uses the top-left 2x2)
+  double a0inv[9];
+  double mu0, kappa; // elastic reference
+  double s0_diag;    // Mandel compliance: 1/(2 mu0) on the diagonal ...
+  double s0_vol;     // ... plus s0_vol on the 3x3 normal block
+};
+
+// Per-axis filter weights: wtab[a*wstride + k] = (cos^2, sin^2)(pi k/(2 N_a)).
+template <typename T>
+struct GreenTabs {
+  const cpx<T>* w;
+  int wstride;
+};
+
+// ----------------------------------------------------------------------------
+// scalar conduction, D = 2 or 3 components, general symmetric A0
+// ----------------------------------------------------------------------------
+template <typename T, int D>
+__device__ __forceinline__ void green_scalar(const GreenParams& gp, const GreenTabs<T>& tb, const int (&k)[3],
+                                             cpx<T> (&v)[D]) {
+  T A[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) A[i][j] = static_cast<T>(gp.a0[3 * i + j]);
+
+  if (gp.variant == kGreenTruncated) {
+    bool nyq = false, zero = true;
+    T xi[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int n = gp.n[a];
+      const int kc = (k[a] <= n / 2) ? k[a] : k[a] - n;
+      xi[a] = static_cast<T>(kc);
+      nyq |= ((n & 1) == 0) && (k[a] == n / 2);
+      zero &= (k[a] == 0);
+    }
+    if (nyq) {
+      cpx<T> o[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        o[i] = cpx<T>{0, 0};
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          const T m = static_cast<T>(gp.a0inv[3 * i + j]);
+          o[i].x += m * v[j].x;
+          o[i].y += m * v[j].y;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < D; ++i) v[i] = o[i];
+      return;
+    }
+    if (zero) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) v[i] = cpx<T>{0, 0};
+      return;
+    }
+    T den = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) den += xi[i] * A[i][j] * xi[j];
+    cpx<T> s{0, 0};
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      s.x += xi[i] * v[i].x;
+      s.y += xi[i] * v[i].y;
+    }
+    const T inv = T(1) / den;
+#pragma unroll
+    for (int i = 0; i < D; ++i) v[i] = cpx<T>{xi[i] * s.x * inv, xi[i] * s.y * inv};
+    return;
+  }
+
+  // filtered: M = sum_aliases w xi xi^T / (xi^T A0 xi)
+  T M[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) M[i][j] = 0;
+  cpx<T> wa[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) wa[a] = tb.w[a * tb.wstride + k[a]];
+#pragma unroll
+  for (int alias = 0; alias < (1 << D); ++alias) {
+    T w = 1;
+    T xi[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const bool lo = (alias >> a) & 1;  // alias k_a - N_a
+      w *= lo ? wa[a].y : wa[a].x;
+      xi[a] = static_cast<T>(lo ? k[a] - gp.n[a] : k[a]);
+    }
+    T den = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) den += xi[i] * A[i][j] * xi[j];
+    if (w != T(0) && den > T(0)) {
+      const T f = w / den;
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) M[i][j] += f * xi[i] * xi[j];
+    }
+  }
+  cpx<T> o[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    o[i] = cpx<T>{0, 0};
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      o[i].x += M[i][j] * v[j].x;
+      o[i].y += M[i][j] * v[j].y;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) v[i] = o[i];
+}
+
+// ----------------------------------------------------------------------------
+// isotropic elasticity, Mandel 6-vectors
+// ----------------------------------------------------------------------------
+template <typename T>
+struct BD {
+  T b11, b22, b33, b23, b13, b12;
+  T d1111, d2222, d3333, d1122, d1133, d2233;
+  T d1112, d1113, d2221, d2223, d3331, d3332, d1123, d2213, d3312;
+};
+
+template <typename T>
+__device__ __forceinline__ void bd_zero(BD<T>& s) {
+  s.b11 = s.b22 = s.b33 = s.b23 = s.b13 = s.b12 = 0;
+  s.d1111 = s.d2222 = s.d3333 = s.d1122 = s.d1133 = s.d2233 = 0;
+  s.d1112 = s.d1113 = s.d2221 = s.d2223 = s.d3331 = s.d3332 = s.d1123 = s.d2213 = s.d3312 = 0;
+}
+
+// accumulate weight w along frequency xi (any length; normalised here)
+template <typename T>
+__device__ __forceinline__ void bd_add(BD<T>& s, T w, T a, T b, T c) {
+  const T n2 = a * a + b * b + c * c;
+  if (!(n2 > T(0)) || w == T(0)) return;
+  const T q = w / n2;      // w / |xi|^2
+  const T u = q / n2;      // w / |xi|^4
+  s.b11 += q * a * a; s.b22 += q * b * b; s.b33 += q * c * c;
+  s.b23 += q * b * c; s.b13 += q * a * c; s.b12 += q * a * b;
+  const T aa = a * a, bb = b * b, cc = c * c;
+  s.d1111 += u * aa * aa; s.d2222 += u * bb * bb; s.d3333 += u * cc * cc;
+  s.d1122 += u * aa * bb; s.d1133 += u * aa * cc; s.d2233 += u * bb * cc;
+  s.d1112 += u * aa * a * b; s.d1113 += u * aa * a * c;
+  s.d2221 += u * bb * b * a; s.d2223 += u * bb * b * c;
+  s.d3331 += u * cc * c * a; s.d3332 += u * cc * c * b;
+  s.d1123 += u * aa * b * c; s.d2213 += u * bb * a * c; s.d3312 += u * cc * a * b;
+}
+
+// out = (B t + t B)/(2 mu0) - kappa D:t on one real symmetric tensor (Mandel in/out)
+template <typename T>
+__device__ __forceinline__ void bd_apply_real(const BD<T>& s, T inv2mu, T kappa, const T (&m)[6], T (&o)[6]) {
+  constexpr T r2 = T(1.4142135623730950488);
+  constexpr T ir2 = T(0.70710678118654752440);
+  const T t11 = m[0], t22 = m[1], t33 = m[2], t23 = m[3] * ir2, t13 = m[4] * ir2, t12 = m[5] * ir2;
+  // symmetric part of B t (doubled)
+  const T s11 = 2 * (s.b11 * t11 + s.b12 * t12 + s.b13 * t13);
+  const T s22 = 2 * (s.b12 * t12 + s.b22 * t22 + s.b23 * t23);
+  const T s33 = 2 * (s.b13 * t13 + s.b23 * t23 + s.b33 * t33);
+  const T s23 = s.b12 * t13 + s.b22 * t23 + s.b23 * t33 + s.b13 * t12 + s.b23 * t22 + s.b33 * t23;
+  const T s13 = s.b11 * t13 + s.b12 * t23 + s.b13 * t33 + s.b13 * t11 + s.b23 * t12 + s.b33 * t13;
+  const T s12 = s.b11 * t12 + s.b12 * t22 + s.b13 * t23 + s.b12 * t11 + s.b22 * t12 + s.b23 * t13;
+  // D : t
+  const T e23 = 2 * t23, e13 = 2 * t13, e12 = 2 * t12;
+  const T d11 = s.d1111 * t11 + s.d1122 * t22 + s.d1133 * t33 + s.d1123 * e23 + s.d1113 * e13 + s.d1112 * e12;
+  const T d22 = s.d1122 * t11 + s.d2222 * t22 + s.d2233 * t33 + s.d2223 * e23 + s.d2213 * e13 + s.d2221 * e12;
+  const T d33 = s.d1133 * t11 + s.d2233 * t22 + s.d3333 * t33 + s.d3332 * e23 + s.d3331 * e13 + s.d3312 * e12;
+  const T d23 = s.d1123 * t11 + s.d2223 * t22 + s.d3332 * t33 + s.d2233 * e23 + s.d3312 * e13 + s.d2213 * e12;
+  const T d13 = s.d1113 * t11 + s.d2213 * t22 + s.d3331 * t33 + s.d3312 * e23 + s.d1133 * e13 + s.d1123 * e12;
+  const T d12 = s.d1112 * t11 + s.d2221 * t22 + s.d3312 * t33 + s.d2213 * e23 + s.d1123 * e13 + s.d1122 * e12;
+  o[0] = s11 * inv2mu - kappa * d11;
+  o[1] = s22 * inv2mu - kappa * d22;
+  o[2] = s33 * inv2mu - kappa * d33;
+  o[3] = r2 * (s23 * inv2mu - kappa * d23);
+  o[4] = r2 * (s13 * inv2mu - kappa * d13);
+  o[5] = r2 * (s12 * inv2mu - kappa * d12);
+}
+
+template <typename T>
+__device__ __forceinline__ void green_elastic(const GreenParams& gp, const GreenTabs<T>& tb, const int (&k)[3],
+                                              cpx<T> (&v)[6]) {
+  const T inv2mu = static_cast<T>(0.5 / gp.mu0);
+  const T kappa = static_cast<T>(gp.kappa);
+  BD<T> s;
+  bd_zero(s);
+  if (gp.variant == kGreenTruncated) {
+    bool nyq = false, zero = true;
+    T xi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int n = gp.n[a];
+      const int kc = (k[a] <= n / 2) ? k[a] : k[a] - n;
+      xi[a] = static_cast<T>(kc);
+      nyq |= ((n & 1) == 0) && (k[a] == n / 2);
+      zero &= (k[a] == 0);
+    }
+    if (nyq) {
+      const T dg = static_cast<T>(gp.s0_diag), vol = static_cast<T>(gp.s0_vol);
+      const cpx<T> tr{v[0].x + v[1].x + v[2].x, v[0].y + v[1].y + v[2].y};
+#pragma unroll
+      for (int i = 0; i < 6; ++i) v[i] = cpx<T>{dg * v[i].x, dg * v[i].y};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) v[i] = cpx<T>{v[i].x + vol * tr.x, v[i].y + vol * tr.y};
+      return;
+    }
+    if (zero) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) v[i] = cpx<T>{0, 0};
+      return;
+    }
+    bd_add(s, T(1), xi[0], xi[1], xi[2]);
+  } else {
+    cpx<T> wa[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) wa[a] = tb.w[a * tb.wstride + k[a]];
+#pragma unroll
+    for (int alias = 0; alias < 8; ++alias) {
+      T w = 1;
+      T xi[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const bool lo = (alias >> a) & 1;
+        w *= lo ? wa[a].y : wa[a].x;
+        xi[a] = static_cast<T>(lo ? k[a] - gp.n[a] : k[a]);
+      }
+      bd_add(s, w, xi[0], xi[1], xi[2]);
+    }
+  }
+  T re[6], im[6], ore[6], oim[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    re[i] = v[i].x;
+    im[i] = v[i].y;
+  }
+  bd_apply_real(s, inv2mu, kappa, re, ore);
+  bd_apply_real(s, inv2mu, kappa, im, oim);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) v[i] = cpx<T>{ore[i], oim[i]};
+}
+
+template <typename T, int C>
+__device__ __forceinline__ void green_apply(const GreenParams& gp, const GreenTabs<T>& tb, const int (&k)[3],
+                                            cpx<T> (&v)[C]) {
+  if constexpr (C == 6) {
+    green_elastic<T>(gp, tb, k, v);
+  } else {
+    green_scalar<T, C>(gp, tb, k, v);
+  }
+}
+
+}  // namespace lsh

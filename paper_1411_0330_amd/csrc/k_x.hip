@@ -1,0 +1,74 @@
+// x passes (R2C / C2R with the local term), FP32 and FP64 instances.
+#include "dispatch.hpp"
+
+namespace lsh {
+
+template <typename T, int MX>
+static int xfwd_one(hipStream_t s, const XfwdArgs<T>& a, int nload) {
+  constexpr int P = p_xfwd<T>(MX);
+  constexpr int TR = MX / P;
+  constexpr int RPW = 256 / TR;
+  const long long rows = (long long)a.g.c * a.g.nz * a.g.ny;
+  const int nb = (int)((rows + RPW - 1) / RPW);
+  hipLaunchKernelGGL((k_xfwd<T, MX, P>), dim3(nb, nload), dim3(256), 0, s, a.g, a.mode, a.src, a.pdir, a.dsrc,
+                     a.smain, a.snyq, a.twx, a.st);
+  return nb;
+}
+
+template <typename T>
+int launch_xfwd(hipStream_t s, const XfwdArgs<T>& a, int nload) {
+  switch (a.g.mx) {
+    case 2: return xfwd_one<T, 2>(s, a, nload);
+    case 4: return xfwd_one<T, 4>(s, a, nload);
+    case 8: return xfwd_one<T, 8>(s, a, nload);
+    case 16: return xfwd_one<T, 16>(s, a, nload);
+    case 32: return xfwd_one<T, 32>(s, a, nload);
+    case 64: return xfwd_one<T, 64>(s, a, nload);
+    case 128: return xfwd_one<T, 128>(s, a, nload);
+    case 256: return xfwd_one<T, 256>(s, a, nload);
+    case 512: return xfwd_one<T, 512>(s, a, nload);
+    default: return -1;
+  }
+}
+
+template <typename T, int MX, int C>
+static int xinv_one(hipStream_t s, const XinvArgs<T>& a, int nload) {
+  constexpr int P = p_xinv<T, C>(MX);
+  const int nb = (int)xinv_blocks(a.g, P);
+  hipLaunchKernelGGL((k_xinv<T, MX, P, C>), dim3(nb, nload), dim3(256), 0, s, a);
+  return nb;
+}
+
+template <typename T, int MX>
+static int xinv_c(hipStream_t s, const XinvArgs<T>& a, int nload) {
+  switch (a.g.c) {
+    case 2: return xinv_one<T, MX, 2>(s, a, nload);
+    case 3: return xinv_one<T, MX, 3>(s, a, nload);
+    case 6: return xinv_one<T, MX, 6>(s, a, nload);
+    default: return -1;
+  }
+}
+
+template <typename T>
+int launch_xinv(hipStream_t s, const XinvArgs<T>& a, int nload) {
+  switch (a.g.mx) {
+    case 2: return xinv_c<T, 2>(s, a, nload);
+    case 4: return xinv_c<T, 4>(s, a, nload);
+    case 8: return xinv_c<T, 8>(s, a, nload);
+    case 16: return xinv_c<T, 16>(s, a, nload);
+    case 32: return xinv_c<T, 32>(s, a, nload);
+    case 64: return xinv_c<T, 64>(s, a, nload);
+    case 128: return xinv_c<T, 128>(s, a, nload);
+    case 256: return xinv_c<T, 256>(s, a, nload);
+    case 512: return xinv_c<T, 512>(s, a, nload);
+    default: return -1;
+  }
+}
+
+#ifndef LSH_X_TYPE
+#error "define LSH_X_TYPE"
+#endif
+template int launch_xfwd<LSH_X_TYPE>(hipStream_t, const XfwdArgs<LSH_X_TYPE>&, int);
+template int launch_xinv<LSH_X_TYPE>(hipStream_t, const XinvArgs<LSH_X_TYPE>&, int);
+
+}  // namespace lsh

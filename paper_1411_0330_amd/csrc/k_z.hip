@@ -1,0 +1,58 @@
+// z pass fused with the Green operator; instances for one element type
+// (LSH_Z_TYPE) so that FP32 and FP64 compile in parallel.
+#include "dispatch.hpp"
+
+namespace lsh {
+
+template <typename T, int NZ, int C>
+static int z_one(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, int zmode, cpx<T>* sm,
+                 cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload) {
+  constexpr int P = (NZ == 1) ? 1 : p_z<T, C>(NZ);
+  constexpr int TX = (NZ == 1) ? 64 : tx_strided<T>(NZ, P);
+  constexpr int NT = TX * (NZ / P);
+  const int xtiles = (g.mx + TX - 1) / TX;
+  const int main_tiles = g.ny * xtiles;
+  const int nyq_tiles = (g.ny + TX - 1) / TX;
+  hipLaunchKernelGGL((k_zg<T, NZ, P, TX, C>), dim3(main_tiles + nyq_tiles, nload), dim3(NT), 0, s, g, gp, tb, zmode,
+                     sm, sn, tw, st, main_tiles);
+  return main_tiles + nyq_tiles;
+}
+
+template <typename T, int C>
+static int z_c(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, int zmode, cpx<T>* sm,
+               cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload) {
+  switch (g.nz) {
+    case 2: return z_one<T, 2, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    case 4: return z_one<T, 4, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    case 8: return z_one<T, 8, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    case 16: return z_one<T, 16, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    case 32: return z_one<T, 32, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    case 64: return z_one<T, 64, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    case 128: return z_one<T, 128, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    case 256: return z_one<T, 256, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    case 512: return z_one<T, 512, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    case 1024: return z_one<T, 1024, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    default: return -1;
+  }
+}
+
+template <typename T>
+int launch_zg(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, int zmode, cpx<T>* sm,
+              cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload) {
+  if (g.c == 2) {
+    if (g.nz != 1) return -1;
+    return z_one<T, 1, 2>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+  }
+  if (g.c == 3) return z_c<T, 3>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+  if (g.c == 6) return z_c<T, 6>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+  return -1;
+}
+
+#ifndef LSH_Z_TYPE
+#error "define LSH_Z_TYPE"
+#endif
+template int launch_zg<LSH_Z_TYPE>(hipStream_t, const Geo&, const GreenParams&, const GreenTabs<LSH_Z_TYPE>&, int,
+                                   cpx<LSH_Z_TYPE>*, cpx<LSH_Z_TYPE>*, const cpx<LSH_Z_TYPE>*, const LoadState*,
+                                   int);
+
+}  // namespace lsh

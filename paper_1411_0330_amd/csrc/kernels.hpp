@@ -1,0 +1,648 @@
+// Kernel templates of the Lippmann--Schwinger operator and its solvers.
+//
+// Data layout (all HBM-resident, one load after another):
+//   real field      T     [load][c][nz][ny][nx]              (x fastest)
+//   main spectrum   cpx<T>[load][c][nz][ny][mx], mx = nx/2    kx = 0..mx-1
+//   Nyquist plane   cpx<T>[load][c][nz][ny]                   kx = nx/2
+// The main spectrum of one load occupies exactly the bytes of its real field,
+// so the last pass writes its real output over the spectrum it has read.
+//
+// One application of eq. (13) is five passes:
+//   xfwd  real rows -> half spectrum (R2C through an nx/2-point complex FFT),
+//         optionally fused with the CG direction update p = r + beta p;
+//   y     strided y-pencils (and contiguous rows of the Nyquist plane);
+//   zg    strided z-pencils: forward z FFT, Gamma_hat on the c components of
+//         every wave-vector, inverse z FFT (the Nyquist plane too);
+//   y     inverse;
+//   xinv  C2R, 1/N^d, and the local term (A - A0)^{-1} tau with the solver's
+//         epilogue (CG q and p.q, basic-scheme update, FP64 residual, ...).
+#pragma once
+
+#include "green_dev.hpp"
+
+namespace lsh {
+
+// Per-load solver state, updated on the device between passes.
+struct LoadState {
+  double rr;     // r.r of the current residual
+  double pq;     // p.Lp
+  double alpha;  // CG step
+  double beta;   // CG direction update
+  double bb;     // ||b||^2
+  double res2;   // last residual norm^2 (basic scheme, refinement)
+  double tol2;   // tol^2 ||b||^2
+  int active;    // 1 while the load iterates
+  int iters;     // operator applications spent
+  int status;    // lsh_status of the load
+  int first;     // next CG direction is p = r
+};
+
+struct Geo {
+  int nx, ny, nz, mx, c, pad;
+  long long nvox;  // nx*ny*nz
+};
+
+__host__ __device__ inline long long field_elems(const Geo& g) { return (long long)g.c * g.nvox; }
+__host__ __device__ inline long long main_cpx(const Geo& g) { return (long long)g.c * g.nz * g.ny * g.mx; }
+__host__ __device__ inline long long nyq_cpx(const Geo& g) { return (long long)g.c * g.nz * g.ny; }
+
+enum : int { XF_PLAIN = 0, XF_CG = 1, XF_IRX = 2 };
+enum : int { XI_APPLY = 0, XI_CG = 1, XI_BASIC = 2, XI_IRRES = 3, XI_RESNORM = 4, XI_STRAIN = 5 };
+enum : int { Z_GAMMA = 0, Z_FWD = 1 };
+enum : int { SC_INIT = 0, SC_ALPHA = 1, SC_BETA = 2, SC_BASIC = 3, SC_OUTER = 4, SC_SUM = 5 };
+
+constexpr int kMaxPhases = 32;
+constexpr int kStatusOk = 0, kStatusBreakdown = -5, kStatusNumeric = -6;
+
+// ----------------------------------------------------------------------------
+// workgroup reduction of one double (wave64 shuffles, then LDS), fixed order
+// ----------------------------------------------------------------------------
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  constexpr int NW = (NT + 63) / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NW; ++i) s += red[i];
+  }
+  return s;
+}
+
+// ----------------------------------------------------------------------------
+// x forward: R2C along rows
+// ----------------------------------------------------------------------------
+template <typename T, int MX, int P>
+__global__ __launch_bounds__(256) void k_xfwd(const Geo g, const int mode, const T* __restrict__ src,
+                                              T* __restrict__ pdir, const float* __restrict__ dsrc,
+                                              cpx<T>* __restrict__ smain, cpx<T>* __restrict__ snyq,
+                                              const cpx<T>* __restrict__ twx, const LoadState* __restrict__ st) {
+  constexpr int TR = MX / P;
+  constexpr int RPW = 256 / TR;
+  __shared__ cpx<T> lds[RPW * MX];
+  const int l = blockIdx.y;
+  if (st != nullptr && !st[l].active) return;
+  const int tid = threadIdx.x;
+  const int slot = tid / TR, t = tid % TR;
+  const long long rows = (long long)g.c * g.nz * g.ny;
+  const long long row = (long long)blockIdx.x * RPW + slot;
+  const bool valid = row < rows;
+  const long long roff = (long long)l * field_elems(g) + row * (2 * MX);
+
+  cpx<T> v[P];
+  if (mode == XF_CG) {
+    const cpx<T>* r2 = reinterpret_cast<const cpx<T>*>(src + roff);
+    cpx<T>* p2 = reinterpret_cast<cpx<T>*>(pdir + roff);
+    const bool first = st[l].first != 0;
+    const T beta = static_cast<T>(st[l].beta);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int n = t + TR * i;
+      cpx<T> pv{0, 0};
+      if (valid) {
+        const cpx<T> rv = r2[n];
+        if (first) {
+          pv = rv;
+        } else {
+          const cpx<T> po = p2[n];
+          pv = cpx<T>{rv.x + beta * po.x, rv.y + beta * po.y};
+        }
+        p2[n] = pv;
+      }
+      v[i] = pv;
+    }
+  } else if (mode == XF_IRX) {
+    cpx<T>* x2 = reinterpret_cast<cpx<T>*>(pdir + roff);
+    const float2* d2 = reinterpret_cast<const float2*>(dsrc + roff);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int n = t + TR * i;
+      cpx<T> xv{0, 0};
+      if (valid) {
+        const cpx<T> xo = x2[n];
+        const float2 dv = d2[n];
+        xv = cpx<T>{xo.x + static_cast<T>(dv.x), xo.y + static_cast<T>(dv.y)};
+        x2[n] = xv;
+      }
+      v[i] = xv;
+    }
+  } else {
+    const cpx<T>* s2 = reinterpret_cast<const cpx<T>*>(src + roff);
+#pragma unroll
+    for (int i = 0; i < P; ++i) v[i] = valid ? s2[t + TR * i] : cpx<T>{0, 0};
+  }
+
+  cpx<T>* lrow = lds + slot * MX;
+  fft_pencil<MX, P, -1, T>(v, t, lrow, 1, twx, 2);
+
+  // unpack the half-length transform: X[k] = E[k] + W_nx^k O[k]
+#pragma unroll
+  for (int i = 0; i < P; ++i) lrow[t + TR * i] = v[i];
+  __syncthreads();
+  const long long so = (long long)l * main_cpx(g) + row * MX;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int k = t + TR * i;
+    const cpx<T> z = v[i];
+    if (k == 0) {
+      if (valid) {
+        smain[so] = cpx<T>{z.x + z.y, T(0)};
+        snyq[(long long)l * nyq_cpx(g) + row] = cpx<T>{z.x - z.y, T(0)};
+      }
+    } else {
+      const cpx<T> zm = lrow[MX - k];
+      const cpx<T> a = cpx<T>{z.x + zm.x, z.y - zm.y};   // Z + conj(Zm)
+      const cpx<T> b = cpx<T>{z.x - zm.x, z.y + zm.y};   // Z - conj(Zm)
+      const cpx<T> wo = cmul(twx[k], mul_neg_i(b));
+      if (valid) smain[so + k] = cpx<T>{T(0.5) * (a.x + wo.x), T(0.5) * (a.y + wo.y)};
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// y pass: strided pencils of the main spectrum, contiguous rows of the Nyquist plane
+// ----------------------------------------------------------------------------
+template <typename T, int NY, int P, int TX, int DIR>
+__global__ __launch_bounds__(TX*(NY / P)) void k_y(const Geo g, cpx<T>* __restrict__ smain,
+                                                  cpx<T>* __restrict__ snyq, const cpx<T>* __restrict__ twy,
+                                                  const LoadState* __restrict__ st, const int main_tiles) {
+  constexpr int TY = NY / P;
+  __shared__ cpx<T> lds[TX * NY];
+  const int l = blockIdx.y;
+  if (st != nullptr && !st[l].active) return;
+  const int tid = threadIdx.x;
+  cpx<T>* base;
+  long long es_g;
+  cpx<T>* lp;
+  int es_l, t;
+  bool valid;
+  if ((int)blockIdx.x < main_tiles) {
+    const int xtiles = (g.mx + TX - 1) / TX;
+    const int xc = blockIdx.x % xtiles;
+    const long long jz = blockIdx.x / xtiles;
+    const int xl = tid % TX;
+    t = tid / TX;
+    const int kx = xc * TX + xl;
+    valid = kx < g.mx;
+    base = smain + (long long)l * main_cpx(g) + jz * g.ny * g.mx + (valid ? kx : 0);
+    es_g = g.mx;
+    lp = lds + xl;
+    es_l = TX;
+  } else {
+    const int slot = tid / TY;
+    t = tid % TY;
+    const long long row = (long long)(blockIdx.x - main_tiles) * TX + slot;
+    valid = row < (long long)g.c * g.nz;
+    base = snyq + (long long)l * nyq_cpx(g) + (valid ? row : 0) * g.ny;
+    es_g = 1;
+    lp = lds + slot * NY;
+    es_l = 1;
+  }
+  cpx<T> v[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) v[i] = valid ? base[(long long)(t + TY * i) * es_g] : cpx<T>{0, 0};
+  fft_pencil<NY, P, DIR, T>(v, t, lp, es_l, twy, 1);
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) base[(long long)(t + TY * i) * es_g] = v[i];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// z pass fused with the Green operator: forward z FFT, Gamma_hat, inverse z FFT
+// ----------------------------------------------------------------------------
+template <typename T, int NZ, int P, int TX, int C>
+__global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenParams gp, const GreenTabs<T> tb,
+                                                   const int zmode, cpx<T>* __restrict__ smain,
+                                                   cpx<T>* __restrict__ snyq, const cpx<T>* __restrict__ twz,
+                                                   const LoadState* __restrict__ st, const int main_tiles) {
+  constexpr int TZ = NZ / P;
+  __shared__ cpx<T> lds[TX * NZ];
+  const int l = blockIdx.y;
+  if (st != nullptr && !st[l].active) return;
+  const int tid = threadIdx.x;
+  const int xl = tid % TX, t = tid / TX;
+  cpx<T>* base;
+  long long es_g, cstride;
+  int kx, ky;
+  bool valid;
+  if ((int)blockIdx.x < main_tiles) {
+    const int xtiles = (g.mx + TX - 1) / TX;
+    const int xc = blockIdx.x % xtiles;
+    ky = blockIdx.x / xtiles;
+    kx = xc * TX + xl;
+    valid = kx < g.mx;
+    base = smain + (long long)l * main_cpx(g) + (long long)ky * g.mx + (valid ? kx : 0);
+    es_g = (long long)g.ny * g.mx;
+    cstride = (long long)g.nz * g.ny * g.mx;
+  } else {
+    ky = (blockIdx.x - main_tiles) * TX + xl;
+    kx = g.mx;
+    valid = ky < g.ny;
+    base = snyq + (long long)l * nyq_cpx(g) + (valid ? ky : 0);
+    es_g = g.ny;
+    cstride = (long long)g.nz * g.ny;
+  }
+  cpx<T>* lp = lds + xl;
+
+  cpx<T> v[C][P];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+      v[j][i] = valid ? base[j * cstride + (long long)(t + TZ * i) * es_g] : cpx<T>{0, 0};
+    fft_pencil<NZ, P, -1, T>(v[j], t, lp, TX, twz, 1);
+  }
+  if (zmode == Z_GAMMA) {
+    if (valid) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int k[3] = {kx, ky, t + TZ * i};
+        cpx<T> w[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) w[j] = v[j][i];
+        green_apply<T, C>(gp, tb, k, w);
+#pragma unroll
+        for (int j = 0; j < C; ++j) v[j][i] = w[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j) fft_pencil<NZ, P, 1, T>(v[j], t, lp, TX, twz, 1);
+  }
+  if (valid) {
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+#pragma unroll
+      for (int i = 0; i < P; ++i) base[j * cstride + (long long)(t + TZ * i) * es_g] = v[j][i];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// x inverse: C2R, scaling, local term and solver epilogue
+// ----------------------------------------------------------------------------
+template <typename T>
+struct XinvArgs {
+  Geo g;
+  int mode;
+  int nphase;
+  const cpx<T>* smain;    // input spectrum (may alias out)
+  const cpx<T>* snyq;
+  const cpx<T>* twx;
+  const T* tau;           // field the spectrum was taken of (p, tau, x)
+  T* out;                 // real output (q, new tau, strain); may alias smain
+  float* rout;            // FP32 residual (refinement)
+  const T* ptab;          // [nphase][2 c c + 1]: (A-A0)^{-1}, (A-A0), in-I0 flag
+  const uint8_t* phase;
+  const double* loads;    // [load][c]
+  const LoadState* st;
+  double* partials;
+  int pstride;
+  T scale;                // 1/N^d times the factor of the half-length route
+};
+
+template <typename T, int MX, int P, int C>
+__global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
+  constexpr int TR = MX / P;
+  constexpr int RPW = 256 / TR;
+  constexpr int TABW = 2 * C * C + 1;
+  __shared__ cpx<T> lds[RPW * MX];
+  __shared__ T tab[kMaxPhases * TABW];
+  __shared__ double red[4];
+  const Geo& g = a.g;
+  const int l = blockIdx.y;
+  if (a.st != nullptr && !a.st[l].active) return;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < a.nphase * TABW; i += 256) tab[i] = a.ptab[i];
+  const int slot = tid / TR, t = tid % TR;
+  const long long vrows = (long long)g.nz * g.ny;
+  const long long vr = (long long)blockIdx.x * RPW + slot;
+  const bool valid = vr < vrows;
+  const long long vrc = valid ? vr : 0;
+  cpx<T>* lrow = lds + slot * MX;
+
+  cpx<T> gam[C][P];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const long long srow = (long long)j * vrows + vrc;
+    const cpx<T>* sm = a.smain + (long long)l * main_cpx(g) + srow * MX;
+    cpx<T> v[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) v[i] = sm[t + TR * i];
+    const cpx<T> nq = a.snyq[(long long)l * nyq_cpx(g) + srow];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < P; ++i) lrow[t + TR * i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int k = t + TR * i;
+      const cpx<T> xk = v[i];
+      const cpx<T> xm = (k == 0) ? nq : lrow[MX - k];
+      const cpx<T> e = cpx<T>{xk.x + xm.x, xk.y - xm.y};          // 2E = X + conj(Xm)
+      const cpx<T> d = cpx<T>{xk.x - xm.x, xk.y + xm.y};          // X - conj(Xm)
+      const cpx<T> o = cmulc(d, a.twx[k]);                        // 2O = (X - conj Xm) W^{-k}
+      v[i] = cadd(e, mul_i(o));                                   // 2Z = 2E + i 2O
+    }
+    __syncthreads();
+    fft_pencil<MX, P, 1, T>(v, t, lrow, 1, a.twx, 2);
+#pragma unroll
+    for (int i = 0; i < P; ++i) gam[j][i] = v[i];
+  }
+
+  // scale: the half-length route returns 2 * (M N_y N_z) / 2 ... folded in a.scale (includes the 1/2 of 2Z)
+  const T sc = a.scale;
+  const long long fo = (long long)l * field_elems(g);
+  double part = 0.0;
+  T pl[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) pl[j] = static_cast<T>(a.loads[l * C + j]);
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int n = t + TR * i;
+    const long long vox = vrc * (2 * MX) + 2 * n;   // voxel index of the pair
+    cpx<T> tv[C];
+    if (a.mode != XI_STRAIN) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) tv[j] = *reinterpret_cast<const cpx<T>*>(a.tau + fo + (long long)j * g.nvox + vox);
+    }
+    const uint16_t ph2 = *reinterpret_cast<const uint16_t*>(a.phase + vox);
+    const int ph0 = ph2 & 0xff, ph1 = ph2 >> 8;
+    const T* tb0 = tab + ph0 * TABW;
+    const T* tb1 = tab + ph1 * TABW;
+    const T in0 = tb0[2 * C * C], in1 = tb1[2 * C * C];
+    cpx<T> res[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const T gx = gam[j][i].x * sc, gy = gam[j][i].y * sc;
+      if (a.mode == XI_APPLY || a.mode == XI_CG) {
+        T lx = 0, ly = 0;
+#pragma unroll
+        for (int m = 0; m < C; ++m) {
+          lx += tb0[j * C + m] * tv[m].x;
+          ly += tb1[j * C + m] * tv[m].y;
+        }
+        res[j] = cpx<T>{in0 * (lx + gx), in1 * (ly + gy)};
+      } else if (a.mode == XI_BASIC) {
+        // new tau = (A - A0)(p - Gamma tau); residual (p - Gamma tau) - (A - A0)^{-1} tau
+        T ux[C], uy[C];
+#pragma unroll
+        for (int m = 0; m < C; ++m) {
+          ux[m] = pl[m] - gam[m][i].x * sc;
+          uy[m] = pl[m] - gam[m][i].y * sc;
+        }
+        T nx = 0, ny = 0, lx = 0, ly = 0;
+#pragma unroll
+        for (int m = 0; m < C; ++m) {
+          nx += tb0[C * C + j * C + m] * ux[m];
+          ny += tb1[C * C + j * C + m] * uy[m];
+          lx += tb0[j * C + m] * tv[m].x;
+          ly += tb1[j * C + m] * tv[m].y;
+        }
+        res[j] = cpx<T>{in0 * nx, in1 * ny};
+        const double rx = in0 * (ux[j] - lx), ry = in1 * (uy[j] - ly);
+        part += rx * rx + ry * ry;
+      } else if (a.mode == XI_IRRES || a.mode == XI_RESNORM) {
+        T lx = 0, ly = 0;
+#pragma unroll
+        for (int m = 0; m < C; ++m) {
+          lx += tb0[j * C + m] * tv[m].x;
+          ly += tb1[j * C + m] * tv[m].y;
+        }
+        res[j] = cpx<T>{in0 * (pl[j] - lx - gx), in1 * (pl[j] - ly - gy)};
+        part += (double)res[j].x * res[j].x + (double)res[j].y * res[j].y;
+      } else {  // XI_STRAIN
+        res[j] = cpx<T>{pl[j] - gx, pl[j] - gy};
+      }
+    }
+    if (a.mode == XI_APPLY || a.mode == XI_CG) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) part += (double)tv[j].x * res[j].x + (double)tv[j].y * res[j].y;
+    }
+    if (valid) {
+      if (a.mode == XI_IRRES) {
+#pragma unroll
+        for (int j = 0; j < C; ++j)
+          *reinterpret_cast<float2*>(a.rout + fo + (long long)j * g.nvox + vox) =
+              float2{static_cast<float>(res[j].x), static_cast<float>(res[j].y)};
+      } else if (a.mode != XI_RESNORM) {
+#pragma unroll
+        for (int j = 0; j < C; ++j) *reinterpret_cast<cpx<T>*>(a.out + fo + (long long)j * g.nvox + vox) = res[j];
+      }
+    }
+  }
+  if (!valid) part = 0.0;
+  if (a.partials != nullptr) {
+    const double s = block_sum<256>(part, red);
+    if (tid == 0) a.partials[(long long)l * a.pstride + blockIdx.x] = s;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// elementwise kernels
+// ----------------------------------------------------------------------------
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
+template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+
+template <typename V> __device__ __forceinline__ double vdot(const V& a, const V& b);
+template <> __device__ __forceinline__ double vdot<float4>(const float4& a, const float4& b) {
+  return (double)a.x * b.x + (double)a.y * b.y + (double)a.z * b.z + (double)a.w * b.w;
+}
+template <> __device__ __forceinline__ double vdot<double2>(const double2& a, const double2& b) {
+  return a.x * b.x + a.y * b.y;
+}
+__device__ __forceinline__ float4 vaxpy(float4 x, float s, float4 y) {
+  return float4{x.x + s * y.x, x.y + s * y.y, x.z + s * y.z, x.w + s * y.w};
+}
+__device__ __forceinline__ double2 vaxpy(double2 x, double s, double2 y) {
+  return double2{x.x + s * y.x, x.y + s * y.y};
+}
+
+constexpr int kEwUnroll = 4;
+
+// x += alpha p;  r -= alpha q;  partial r.r      (per load, 16-byte vectors)
+template <typename T>
+__global__ __launch_bounds__(256) void k_cgupd(const long long nvec, T* __restrict__ x, const T* __restrict__ p,
+                                               T* __restrict__ r, const T* __restrict__ q,
+                                               const LoadState* __restrict__ st, double* __restrict__ partials,
+                                               const int pstride) {
+  using V = typename Vec16<T>::type;
+  __shared__ double red[4];
+  const int l = blockIdx.y;
+  if (!st[l].active) return;
+  const T al = static_cast<T>(st[l].alpha);
+  const long long off = (long long)l * nvec;
+  V* xv = reinterpret_cast<V*>(x) + off;
+  const V* pv = reinterpret_cast<const V*>(p) + off;
+  V* rv = reinterpret_cast<V*>(r) + off;
+  const V* qv = reinterpret_cast<const V*>(q) + off;
+  double part = 0.0;
+  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kEwUnroll; ++u) {
+    const long long i = b0 + (long long)u * 256;
+    if (i < nvec) {
+      const V xo = xv[i], po = pv[i], ro = rv[i], qo = qv[i];
+      xv[i] = vaxpy(xo, al, po);
+      const V rn = vaxpy(ro, -al, qo);
+      rv[i] = rn;
+      part += vdot(rn, rn);
+    }
+  }
+  const double s = block_sum<256>(part, red);
+  if (threadIdx.x == 0) partials[(long long)l * pstride + blockIdx.x] = s;
+}
+
+// x = 0;  r = 1_{I0} p_l;  partial ||r||^2
+template <typename T>
+__global__ __launch_bounds__(256) void k_cginit(const Geo g, T* __restrict__ x, T* __restrict__ r,
+                                                const uint8_t* __restrict__ phase, const uint8_t* __restrict__ i0,
+                                                const double* __restrict__ loads, double* __restrict__ partials,
+                                                const int pstride) {
+  __shared__ double red[4];
+  const int l = blockIdx.y;
+  const long long F = field_elems(g);
+  double part = 0.0;
+  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kEwUnroll; ++u) {
+    const long long e = b0 + (long long)u * 256;
+    if (e < F) {
+      const int j = (int)(e / g.nvox);
+      const long long vox = e - (long long)j * g.nvox;
+      const T val = i0[phase[vox]] ? static_cast<T>(loads[l * g.c + j]) : T(0);
+      if (x != nullptr) x[(long long)l * F + e] = T(0);
+      if (r != nullptr) r[(long long)l * F + e] = val;
+      part += (double)val * val;
+    }
+  }
+  const double s = block_sum<256>(part, red);
+  if (threadIdx.x == 0) partials[(long long)l * pstride + blockIdx.x] = s;
+}
+
+// d = 0 and partial ||r||^2 for the loads still refined (inner solve start)
+template <typename T>
+__global__ __launch_bounds__(256) void k_innerinit(const long long F, T* __restrict__ d, const T* __restrict__ r,
+                                                   const LoadState* __restrict__ outer,
+                                                   double* __restrict__ partials, const int pstride) {
+  __shared__ double red[4];
+  const int l = blockIdx.y;
+  if (!outer[l].active) return;
+  double part = 0.0;
+  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kEwUnroll; ++u) {
+    const long long e = b0 + (long long)u * 256;
+    if (e < F) {
+      d[(long long)l * F + e] = T(0);
+      const double rv = r[(long long)l * F + e];
+      part += rv * rv;
+    }
+  }
+  const double s = block_sum<256>(part, red);
+  if (threadIdx.x == 0) partials[(long long)l * pstride + blockIdx.x] = s;
+}
+
+// partial sums of one component of one load: group (l, j)
+template <typename T>
+__global__ __launch_bounds__(256) void k_mean(const Geo g, const T* __restrict__ x, double* __restrict__ partials,
+                                              const int pstride) {
+  __shared__ double red[4];
+  const int grp = blockIdx.y;   // l * c + j
+  const T* xp = x + (long long)grp * g.nvox;
+  double part = 0.0;
+  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kEwUnroll; ++u) {
+    const long long e = b0 + (long long)u * 256;
+    if (e < g.nvox) part += (double)xp[e];
+  }
+  const double s = block_sum<256>(part, red);
+  if (threadIdx.x == 0) partials[(long long)grp * pstride + blockIdx.x] = s;
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_convert(const long long n, const TI* __restrict__ in, TO* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = static_cast<TO>(in[i]);
+}
+
+// Deterministic final reduction of the partials of group blockIdx.x, then the
+// scalar update of the solver (one workgroup per group).
+static __global__ __launch_bounds__(256) void k_scal(const int mode, const double* __restrict__ partials, const int pstride,
+                                              const int nparts, LoadState* __restrict__ st,
+                                              double* __restrict__ sums, const double tol) {
+  __shared__ double red[256];
+  const int grp = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 256) s += partials[(long long)grp * pstride + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double S = red[0];
+  if (mode == SC_SUM) {
+    sums[grp] = S;
+    return;
+  }
+  LoadState& L = st[grp];
+  if (mode == SC_INIT) {
+    L.bb = S;
+    L.rr = S;
+    L.res2 = S;
+    L.tol2 = tol * tol * S;
+    L.alpha = 0.0;
+    L.beta = 0.0;
+    L.pq = 0.0;
+    L.iters = 0;
+    L.first = 1;
+    L.status = isfinite(S) ? kStatusOk : kStatusNumeric;
+    L.active = (S > 0.0 && isfinite(S)) ? 1 : 0;
+    return;
+  }
+  if (!L.active) return;
+  if (mode == SC_ALPHA) {
+    L.pq = S;
+    // p.Lp may be negative when A0 lies between the phases (indefinite
+    // system): CG proceeds; it breaks down only when p.Lp vanishes.
+    if (!isfinite(S)) {
+      L.status = kStatusNumeric;
+      L.active = 0;
+    } else if (S == 0.0) {
+      L.status = kStatusBreakdown;
+      L.active = 0;
+    } else {
+      L.alpha = L.rr / S;
+      L.first = 0;
+    }
+  } else if (mode == SC_BETA) {
+    L.iters += 1;
+    if (!isfinite(S)) {
+      L.status = kStatusNumeric;
+      L.active = 0;
+      return;
+    }
+    L.beta = S / L.rr;
+    L.rr = S;
+    L.res2 = S;
+    if (S <= L.tol2) L.active = 0;
+  } else if (mode == SC_BASIC || mode == SC_OUTER) {
+    L.iters += 1;
+    L.res2 = S;
+    if (!isfinite(S)) {
+      L.status = kStatusNumeric;
+      L.active = 0;
+    } else if (S <= L.tol2) {
+      L.active = 0;
+    }
+  }
+}
+
+}  // namespace lsh

@@ -1,0 +1,1121 @@
+// Host runtime of the C ABI declared in include/lsh.h: validation, workspace
+// carving, tables, and the solver loops (conjugate gradients, basic scheme,
+// FP32/FP64 iterative refinement) driving the transform kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dispatch.hpp"
+#include "lsh.h"
+
+using namespace lsh;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// ---------------------------------------------------------------------------
+// small dense linear algebra on the host (c <= 6)
+// ---------------------------------------------------------------------------
+// Inverse by Gauss-Jordan with partial pivoting; false when singular.
+bool invert(int n, const double* a, double* inv) {
+  double m[6][12];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < 2 * n; ++j) m[i][j] = j < n ? a[i * n + j] : (j - n == i ? 1.0 : 0.0);
+  double scale = 0.0;
+  for (int i = 0; i < n * n; ++i) scale = std::max(scale, std::fabs(a[i]));
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(m[r][col]) > std::fabs(m[piv][col])) piv = r;
+    if (!(std::fabs(m[piv][col]) > 1e-13 * scale)) return false;
+    if (piv != col)
+      for (int j = 0; j < 2 * n; ++j) std::swap(m[col][j], m[piv][j]);
+    const double d = m[col][col];
+    for (int j = 0; j < 2 * n; ++j) m[col][j] /= d;
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double f = m[r][col];
+      if (f != 0.0)
+        for (int j = 0; j < 2 * n; ++j) m[r][j] -= f * m[col][j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) inv[i * n + j] = m[i][n + j];
+  return true;
+}
+
+// Eigenvalues of a symmetric matrix (cyclic Jacobi).
+void sym_eigvals(int n, const double* a, double* ev) {
+  double m[6][6];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) m[i][j] = 0.5 * (a[i * n + j] + a[j * n + i]);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += m[i][j] * m[i][j];
+    if (off < 1e-30) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        if (std::fabs(m[p][q]) < 1e-300) continue;
+        const double th = 0.5 * (m[q][q] - m[p][p]) / m[p][q];
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double mkp = m[k][p], mkq = m[k][q];
+          m[k][p] = c * mkp - s * mkq;
+          m[k][q] = s * mkp + c * mkq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double mpk = m[p][k], mqk = m[q][k];
+          m[p][k] = c * mpk - s * mqk;
+          m[q][k] = s * mpk + c * mqk;
+        }
+      }
+  }
+  for (int i = 0; i < n; ++i) ev[i] = m[i][i];
+}
+
+bool symmetric(int n, const double* a) {
+  double scale = 0.0;
+  for (int i = 0; i < n * n; ++i) scale = std::max(scale, std::fabs(a[i]));
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j)
+      if (std::fabs(a[i * n + j] - a[j * n + i]) > 1e-12 * scale) return false;
+  return true;
+}
+
+struct KTimer {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+const char* kClassNames[] = {"xfwd", "y", "zgamma", "xinv", "cg_update", "scalars", "init", "mean", "copy"};
+enum KClass { K_XFWD, K_Y, K_ZG, K_XINV, K_CGUPD, K_SCAL, K_INIT, K_MEAN, K_COPY, K_NCLASS };
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct lsh_ctx {
+  int dim = 0, physics = 0, precision = 0, max_loads = 0, c = 0;
+  int n[3] = {1, 1, 1};
+  hipStream_t stream = nullptr;
+  Geo geo{};
+  long long F = 0;  // reals per load field
+
+  // host-side problem definition
+  bool have_ref = false, have_phase = false;
+  std::vector<double> A0;
+  int green = LSH_GREEN_FILTERED;
+  int nphase = 0;
+  std::vector<double> moduli;
+  std::vector<uint8_t> phase_host;
+  const uint8_t* phase_dev_src = nullptr;
+  bool tables_dirty = true, phase_dirty = true, consts_ready = false;
+  GreenParams gp{};
+
+  // workspace
+  char* ws = nullptr;
+  size_t ws_need = 0, ws_size = 0;
+  struct {
+    size_t x64, r64, p64, d32, r32, p32, s64m, s64n, s32m, s32n, phase, i0, ptab64, ptab32, tw64, tw32, wt64, wt32,
+        loads, st_out, st_in, partials, sums, end;
+  } off{};
+  long long pstride = 0, nsums = 0;
+  int twoff[3] = {0, 0, 0};
+  int wstride = 0;
+
+  // host staging kept alive across asynchronous copies
+  std::vector<double> h_ptab64, h_loads;
+  std::vector<float> h_ptab32;
+  std::vector<uint8_t> h_i0;
+  std::vector<double> h_tw64, h_wt64;
+  std::vector<float> h_tw32, h_wt32;
+
+  // last solve
+  int last_nload = 0;
+  bool have_solution = false;
+  std::vector<double> last_loads, sigma;
+
+  // timing
+  bool timing = false;
+  std::vector<KTimer> pending;
+  std::vector<hipEvent_t> pool;
+  double tsum[K_NCLASS] = {0};
+  long long tcount[K_NCLASS] = {0};
+
+  std::string err;
+
+  template <typename T> T* ptr(size_t o) const { return reinterpret_cast<T*>(ws + o); }
+};
+
+namespace {
+
+lsh_status fail(lsh_ctx* ctx, lsh_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(ctx, LSH_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+#define STCHK(expr)                       \
+  do {                                    \
+    lsh_status s_ = (expr);               \
+    if (s_ != LSH_OK) return s_;          \
+  } while (0)
+
+// ------------------------- kernel timing ---------------------------------
+hipEvent_t take_event(lsh_ctx* ctx) {
+  if (!ctx->pool.empty()) {
+    hipEvent_t e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct Scope {
+  lsh_ctx* ctx;
+  int cls;
+  hipEvent_t a = nullptr;
+  Scope(lsh_ctx* c, int k) : ctx(c), cls(k) {
+    if (ctx->timing) {
+      a = take_event(ctx);
+      if (a) (void)hipEventRecord(a, ctx->stream);
+    }
+  }
+  ~Scope() {
+    if (ctx->timing && a) {
+      hipEvent_t b = take_event(ctx);
+      if (b) {
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->pending.push_back({kClassNames[cls], a, b});
+        ctx->pending.back().name = kClassNames[cls];
+      }
+    }
+  }
+};
+
+void drain_timers(lsh_ctx* ctx) {
+  if (ctx->pending.empty()) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& t : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      for (int k = 0; k < K_NCLASS; ++k)
+        if (std::strcmp(kClassNames[k], t.name) == 0) {
+          ctx->tsum[k] += ms;
+          ctx->tcount[k] += 1;
+        }
+    }
+    ctx->pool.push_back(t.a);
+    ctx->pool.push_back(t.b);
+  }
+  ctx->pending.clear();
+}
+
+// ------------------------- layout ----------------------------------------
+void compute_layout(lsh_ctx* ctx) {
+  const long long L = ctx->max_loads, F = ctx->F, c = ctx->c;
+  const long long V = ctx->geo.nvox;
+  const long long nyq = (long long)c * ctx->n[2] * ctx->n[1];
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const bool mixed = ctx->precision == LSH_MIXED;
+  ctx->off.x64 = take(sizeof(double) * L * F);
+  ctx->off.r64 = mixed ? 0 : take(sizeof(double) * L * F);
+  ctx->off.p64 = mixed ? 0 : take(sizeof(double) * L * F);
+  ctx->off.d32 = mixed ? take(sizeof(float) * L * F) : 0;
+  ctx->off.r32 = mixed ? take(sizeof(float) * L * F) : 0;
+  ctx->off.p32 = mixed ? take(sizeof(float) * L * F) : 0;
+  ctx->off.s64m = take(sizeof(double) * L * F);
+  ctx->off.s64n = take(2 * sizeof(double) * L * nyq);
+  ctx->off.s32m = mixed ? take(sizeof(float) * L * F) : 0;
+  ctx->off.s32n = mixed ? take(2 * sizeof(float) * L * nyq) : 0;
+  ctx->off.phase = take(V + 16);
+  ctx->off.i0 = take(256);
+  const int tabw = 2 * ctx->c * ctx->c + 1;
+  ctx->off.ptab64 = take(sizeof(double) * kMaxPhases * tabw);
+  ctx->off.ptab32 = take(sizeof(float) * kMaxPhases * tabw);
+  const int ntw = ctx->n[0] + ctx->n[1] + ctx->n[2];
+  ctx->twoff[0] = 0;
+  ctx->twoff[1] = ctx->n[0];
+  ctx->twoff[2] = ctx->n[0] + ctx->n[1];
+  ctx->off.tw64 = take(2 * sizeof(double) * ntw);
+  ctx->off.tw32 = take(2 * sizeof(float) * ntw);
+  ctx->wstride = std::max(ctx->n[0], std::max(ctx->n[1], ctx->n[2]));
+  ctx->off.wt64 = take(2 * sizeof(double) * 3 * ctx->wstride);
+  ctx->off.wt32 = take(2 * sizeof(float) * 3 * ctx->wstride);
+  ctx->off.loads = take(sizeof(double) * L * c);
+  ctx->off.st_out = take(sizeof(LoadState) * L);
+  ctx->off.st_in = take(sizeof(LoadState) * L);
+  // partial sums: the largest grid of any reducing kernel, per group
+  long long pmax = xinv_blocks(ctx->geo, 2);
+  pmax = std::max(pmax, (F + 1023) / 1024 + 1);
+  ctx->pstride = pmax;
+  ctx->off.partials = take(sizeof(double) * L * c * pmax);
+  ctx->nsums = L * c;
+  ctx->off.sums = take(sizeof(double) * L * c);
+  ctx->off.end = o;
+  ctx->ws_need = o;
+}
+
+// twiddles W_N^m = exp(-2 pi i m / N) and filter weights per axis
+void build_consts(lsh_ctx* ctx) {
+  const int ntw = ctx->n[0] + ctx->n[1] + ctx->n[2];
+  ctx->h_tw64.assign(2 * ntw, 0.0);
+  ctx->h_tw32.assign(2 * ntw, 0.f);
+  for (int a = 0; a < 3; ++a) {
+    const int N = ctx->n[a];
+    for (int m = 0; m < N; ++m) {
+      const long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)N;
+      double cr = (double)cosl(ang), ci = (double)(-sinl(ang));
+      if (4 * m == N) { cr = 0.0; ci = -1.0; }
+      if (2 * m == N) { cr = -1.0; ci = 0.0; }
+      if (4 * m == 3 * N) { cr = 0.0; ci = 1.0; }
+      const int i = ctx->twoff[a] + m;
+      ctx->h_tw64[2 * i] = cr;
+      ctx->h_tw64[2 * i + 1] = ci;
+      ctx->h_tw32[2 * i] = (float)cr;
+      ctx->h_tw32[2 * i + 1] = (float)ci;
+    }
+  }
+  const int W = ctx->wstride;
+  ctx->h_wt64.assign(2 * 3 * W, 0.0);
+  ctx->h_wt32.assign(2 * 3 * W, 0.f);
+  for (int a = 0; a < 3; ++a) {
+    const int N = ctx->n[a];
+    for (int k = 0; k < N; ++k) {
+      const long double t = 3.14159265358979323846264338327950288L * (long double)k / (2.0L * N);
+      const long double cc = cosl(t), ss = sinl(t);
+      const int i = a * W + k;
+      ctx->h_wt64[2 * i] = (double)(cc * cc);
+      ctx->h_wt64[2 * i + 1] = (double)(ss * ss);
+      ctx->h_wt32[2 * i] = (float)(cc * cc);
+      ctx->h_wt32[2 * i + 1] = (float)(ss * ss);
+    }
+  }
+}
+
+lsh_status upload_consts(lsh_ctx* ctx) {
+  build_consts(ctx);
+  HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.tw64, ctx->h_tw64.data(), ctx->h_tw64.size() * sizeof(double),
+                        hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.tw32, ctx->h_tw32.data(), ctx->h_tw32.size() * sizeof(float),
+                        hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.wt64, ctx->h_wt64.data(), ctx->h_wt64.size() * sizeof(double),
+                        hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.wt32, ctx->h_wt32.data(), ctx->h_wt32.size() * sizeof(float),
+                        hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->consts_ready = true;
+  return LSH_OK;
+}
+
+// Phase tables against the current A0: (A-A0)^{-1}, (A-A0), I0 flag; checks hypothesis (2).
+lsh_status build_tables(lsh_ctx* ctx) {
+  const int c = ctx->c;
+  const int tabw = 2 * c * c + 1;
+  ctx->h_ptab64.assign((size_t)kMaxPhases * tabw, 0.0);
+  ctx->h_ptab32.assign((size_t)kMaxPhases * tabw, 0.f);
+  ctx->h_i0.assign(256, 0);
+  for (int p = 0; p < ctx->nphase; ++p) {
+    double D[36], Dinv[36];
+    bool zero = true;
+    double scale = 0.0;
+    for (int i = 0; i < c * c; ++i) {
+      D[i] = ctx->moduli[(size_t)p * c * c + i] - ctx->A0[i];
+      zero &= (D[i] == 0.0);
+      scale = std::max(scale, std::fabs(ctx->moduli[(size_t)p * c * c + i]) + std::fabs(ctx->A0[i]));
+    }
+    double* row = &ctx->h_ptab64[(size_t)p * tabw];
+    if (zero) continue;  // outside I0: all zero, flag 0
+    double ev[6];
+    sym_eigvals(c, D, ev);
+    double lo = ev[0], hi = ev[0];
+    for (int i = 1; i < c; ++i) {
+      lo = std::min(lo, ev[i]);
+      hi = std::max(hi, ev[i]);
+    }
+    const double eps = 1e-12 * scale;
+    if (!((lo > eps) || (hi < -eps)))
+      return fail(ctx, LSH_EHYP2,
+                  "phase " + std::to_string(p) + ": A - A0 is neither zero nor definite (hypothesis (2))");
+    if (!invert(c, D, Dinv)) return fail(ctx, LSH_EHYP2, "phase " + std::to_string(p) + ": A - A0 is singular");
+    for (int i = 0; i < c * c; ++i) {
+      row[i] = Dinv[i];
+      row[c * c + i] = D[i];
+    }
+    row[2 * c * c] = 1.0;
+    ctx->h_i0[p] = 1;
+  }
+  for (size_t i = 0; i < ctx->h_ptab64.size(); ++i) ctx->h_ptab32[i] = (float)ctx->h_ptab64[i];
+
+  // Green parameters
+  GreenParams& gp = ctx->gp;
+  std::memset(&gp, 0, sizeof(gp));
+  gp.variant = ctx->green == LSH_GREEN_TRUNCATED ? kGreenTruncated : kGreenFiltered;
+  for (int a = 0; a < 3; ++a) gp.n[a] = ctx->n[a];
+  if (ctx->physics == LSH_SCALAR) {
+    double inv[9];
+    invert(c, ctx->A0.data(), inv);
+    for (int i = 0; i < c; ++i)
+      for (int j = 0; j < c; ++j) {
+        gp.a0[3 * i + j] = ctx->A0[i * c + j];
+        gp.a0inv[3 * i + j] = inv[i * c + j];
+      }
+  } else {
+    const double lam0 = ctx->A0[1], mu0 = 0.5 * ctx->A0[3 * 6 + 3];
+    const double K0 = lam0 + 2.0 * mu0 / 3.0;
+    gp.mu0 = mu0;
+    gp.kappa = (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0));
+    gp.s0_diag = 1.0 / (2.0 * mu0);
+    gp.s0_vol = 1.0 / (9.0 * K0) - 1.0 / (6.0 * mu0);
+  }
+  HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.ptab64, ctx->h_ptab64.data(), ctx->h_ptab64.size() * sizeof(double),
+                        hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.ptab32, ctx->h_ptab32.data(), ctx->h_ptab32.size() * sizeof(float),
+                        hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.i0, ctx->h_i0.data(), 256, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->tables_dirty = false;
+  return LSH_OK;
+}
+
+// Hypothesis (2) on the host, before anything touches the GPU.
+lsh_status validate_phases(lsh_ctx* ctx) {
+  const int c = ctx->c;
+  for (int p = 0; p < ctx->nphase; ++p) {
+    double D[36], Dinv[36];
+    bool zero = true;
+    double scale = 0.0;
+    for (int i = 0; i < c * c; ++i) {
+      D[i] = ctx->moduli[(size_t)p * c * c + i] - ctx->A0[i];
+      zero &= (D[i] == 0.0);
+      scale = std::max(scale, std::fabs(ctx->moduli[(size_t)p * c * c + i]) + std::fabs(ctx->A0[i]));
+    }
+    if (zero) continue;
+    double ev[6];
+    sym_eigvals(c, D, ev);
+    double lo = ev[0], hi = ev[0];
+    for (int i = 1; i < c; ++i) {
+      lo = std::min(lo, ev[i]);
+      hi = std::max(hi, ev[i]);
+    }
+    const double eps = 1e-12 * scale;
+    if (!((lo > eps) || (hi < -eps)) || !invert(c, D, Dinv))
+      return fail(ctx, LSH_EHYP2,
+                  "phase " + std::to_string(p) + ": A - A0 is neither zero nor definite (hypothesis (2))");
+  }
+  return LSH_OK;
+}
+
+lsh_status prepare(lsh_ctx* ctx) {
+  if (!ctx->have_ref) return fail(ctx, LSH_ESTATE, "reference medium not set");
+  if (!ctx->have_phase) return fail(ctx, LSH_ESTATE, "phases not set");
+  if (ctx->tables_dirty) STCHK(validate_phases(ctx));
+  if (!ctx->ws) return fail(ctx, LSH_ESTATE, "no workspace bound");
+  if (!ctx->consts_ready) {
+    lsh_status s = upload_consts(ctx);
+    if (s != LSH_OK) return s;
+  }
+  if (ctx->phase_dirty) {
+    const size_t V = (size_t)ctx->geo.nvox;
+    if (ctx->phase_dev_src) {
+      HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.phase, ctx->phase_dev_src, V, hipMemcpyDeviceToDevice, ctx->stream));
+    } else {
+      HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.phase, ctx->phase_host.data(), V, hipMemcpyHostToDevice,
+                            ctx->stream));
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->phase_dev_src = nullptr;
+    ctx->phase_dirty = false;
+  }
+  if (ctx->tables_dirty) {
+    lsh_status s = build_tables(ctx);
+    if (s != LSH_OK) return s;
+  }
+  return LSH_OK;
+}
+
+// ------------------------- operator pieces -------------------------------
+template <typename T> struct Sel;
+template <> struct Sel<double> {
+  static cpx<double>* sm(lsh_ctx* c) { return c->ptr<cpx<double>>(c->off.s64m); }
+  static cpx<double>* sn(lsh_ctx* c) { return c->ptr<cpx<double>>(c->off.s64n); }
+  static const cpx<double>* tw(lsh_ctx* c, int a) { return c->ptr<cpx<double>>(c->off.tw64) + c->twoff[a]; }
+  static const cpx<double>* wt(lsh_ctx* c) { return c->ptr<cpx<double>>(c->off.wt64); }
+  static const double* ptab(lsh_ctx* c) { return c->ptr<double>(c->off.ptab64); }
+};
+template <> struct Sel<float> {
+  static cpx<float>* sm(lsh_ctx* c) { return c->ptr<cpx<float>>(c->off.s32m); }
+  static cpx<float>* sn(lsh_ctx* c) { return c->ptr<cpx<float>>(c->off.s32n); }
+  static const cpx<float>* tw(lsh_ctx* c, int a) { return c->ptr<cpx<float>>(c->off.tw32) + c->twoff[a]; }
+  static const cpx<float>* wt(lsh_ctx* c) { return c->ptr<cpx<float>>(c->off.wt32); }
+  static const float* ptab(lsh_ctx* c) { return c->ptr<float>(c->off.ptab32); }
+};
+
+lsh_status check_launch(lsh_ctx* ctx, int r, const char* what) {
+  if (r < 0) return fail(ctx, LSH_EINVAL, std::string("unsupported grid size for ") + what);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, LSH_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return LSH_OK;
+}
+
+
+// Forward passes on load slots [l0, l0+nload): x (mode), y, z (+Gamma and inverse z), y inverse.
+template <typename T>
+lsh_status forward_part(lsh_ctx* ctx, int l0, int nload, int xmode, const T* src, T* pdir, const float* dsrc,
+                        const LoadState* st, bool gamma) {
+  const Geo& g = ctx->geo;
+  cpx<T>* sm = Sel<T>::sm(ctx) + (long long)l0 * main_cpx(g);
+  cpx<T>* sn = Sel<T>::sn(ctx) + (long long)l0 * nyq_cpx(g);
+  XfwdArgs<T> xa{g, xmode, src, pdir, dsrc, sm, sn, Sel<T>::tw(ctx, 0), st};
+  {
+    Scope sc(ctx, K_XFWD);
+    STCHK(check_launch(ctx, launch_xfwd<T>(ctx->stream, xa, nload), "x forward"));
+  }
+  {
+    Scope sc(ctx, K_Y);
+    STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, -1, sm, sn, Sel<T>::tw(ctx, 1), st, nload), "y forward"));
+  }
+  {
+    Scope sc(ctx, K_ZG);
+    GreenTabs<T> tb{Sel<T>::wt(ctx), ctx->wstride};
+    STCHK(check_launch(ctx,
+                       launch_zg<T>(ctx->stream, g, ctx->gp, tb, gamma ? Z_GAMMA : Z_FWD, sm, sn, Sel<T>::tw(ctx, 2),
+                                    st, nload),
+                       "z/Green"));
+  }
+  if (gamma) {
+    Scope sc(ctx, K_Y);
+    STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, 1, sm, sn, Sel<T>::tw(ctx, 1), st, nload), "y inverse"));
+  }
+  return LSH_OK;
+}
+
+template <typename T>
+lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T* out, float* rout,
+                     const LoadState* st, double* partials, int* nparts) {
+  const Geo& g = ctx->geo;
+  XinvArgs<T> a{};
+  a.g = g;
+  a.mode = mode;
+  a.nphase = ctx->nphase;
+  a.smain = Sel<T>::sm(ctx) + (long long)l0 * main_cpx(g);
+  a.snyq = Sel<T>::sn(ctx) + (long long)l0 * nyq_cpx(g);
+  a.twx = Sel<T>::tw(ctx, 0);
+  a.tau = tau;
+  a.out = out;
+  a.rout = rout;
+  a.ptab = Sel<T>::ptab(ctx);
+  a.phase = ctx->ptr<uint8_t>(ctx->off.phase);
+  a.loads = ctx->ptr<double>(ctx->off.loads) + (long long)l0 * ctx->c;
+  a.st = st;
+  a.partials = partials;
+  a.pstride = (int)ctx->pstride;
+  a.scale = static_cast<T>(1.0 / (double)g.nvox);
+  Scope sc(ctx, K_XINV);
+  const int nb = launch_xinv<T>(ctx->stream, a, nload);
+  STCHK(check_launch(ctx, nb, "x inverse"));
+  if (nparts) *nparts = nb;
+  return LSH_OK;
+}
+
+lsh_status scal(lsh_ctx* ctx, int mode, int ngroups, int nparts, LoadState* st, double tol) {
+  Scope sc(ctx, K_SCAL);
+  hipLaunchKernelGGL(k_scal, dim3(ngroups), dim3(256), 0, ctx->stream, mode, ctx->ptr<double>(ctx->off.partials),
+                     (int)ctx->pstride, nparts, st, ctx->ptr<double>(ctx->off.sums), tol);
+  return check_launch(ctx, 0, "scalars");
+}
+
+template <typename T>
+lsh_status cg_init(lsh_ctx* ctx, int nload, T* x, T* r, LoadState* st, double tol) {
+  const Geo& g = ctx->geo;
+  const int nb = (int)((ctx->F + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
+  {
+    Scope sc(ctx, K_INIT);
+    hipLaunchKernelGGL((k_cginit<T>), dim3(nb, nload), dim3(256), 0, ctx->stream, g, x, r,
+                       ctx->ptr<uint8_t>(ctx->off.phase), ctx->ptr<uint8_t>(ctx->off.i0),
+                       ctx->ptr<double>(ctx->off.loads), ctx->ptr<double>(ctx->off.partials), (int)ctx->pstride);
+    STCHK(check_launch(ctx, 0, "init"));
+  }
+  return scal(ctx, SC_INIT, nload, nb, st, tol);
+}
+
+template <typename T>
+lsh_status cg_update(lsh_ctx* ctx, int nload, T* x, const T* p, T* r, const T* q, LoadState* st) {
+  const long long nvec = ctx->F / Vec16<T>::n;
+  const int nb = (int)((nvec + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
+  {
+    Scope sc(ctx, K_CGUPD);
+    hipLaunchKernelGGL((k_cgupd<T>), dim3(nb, nload), dim3(256), 0, ctx->stream, nvec, x, p, r, q, st,
+                       ctx->ptr<double>(ctx->off.partials), (int)ctx->pstride);
+    STCHK(check_launch(ctx, 0, "cg update"));
+  }
+  return scal(ctx, SC_BETA, nload, nb, st, 0.0);
+}
+
+lsh_status read_states(lsh_ctx* ctx, size_t off, int nload, std::vector<LoadState>& h) {
+  h.resize(nload);
+  HIPCHK(hipMemcpyAsync(h.data(), ctx->ws + off, sizeof(LoadState) * nload, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return LSH_OK;
+}
+
+int check_period(lsh_ctx* ctx, int nload) {
+  const long long work = ctx->geo.nvox * (long long)nload * ctx->c;
+  return work >= (1LL << 22) ? 1 : 8;
+}
+
+// CG iterations on (x, r, p) with q held in the spectrum buffer; returns after
+// convergence of every load, or maxit iterations.
+template <typename T>
+lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, size_t st_off, int maxit,
+                   std::vector<LoadState>& hst) {
+  const int period = check_period(ctx, nload);
+  T* q = reinterpret_cast<T*>(Sel<T>::sm(ctx));
+  STCHK(read_states(ctx, st_off, nload, hst));
+  bool any = false;
+  for (auto& s : hst) any |= s.active != 0;
+  if (!any) return LSH_OK;
+  for (int it = 0; it < maxit; ++it) {
+    STCHK(forward_part<T>(ctx, 0, nload, XF_CG, r, p, nullptr, st, true));
+    int np = 0;
+    STCHK(inverse_x<T>(ctx, 0, nload, XI_CG, p, q, nullptr, st, ctx->ptr<double>(ctx->off.partials), &np));
+    STCHK(scal(ctx, SC_ALPHA, nload, np, st, 0.0));
+    STCHK(cg_update<T>(ctx, nload, x, p, r, q, st));
+    if ((it + 1) % period == 0 || it + 1 == maxit) {
+      STCHK(read_states(ctx, st_off, nload, hst));
+      any = false;
+      for (auto& s : hst) any |= s.active != 0;
+      if (!any) break;
+    }
+  }
+  return LSH_OK;
+}
+
+lsh_status basic_loop(lsh_ctx* ctx, int nload, double* x, LoadState* st, size_t st_off, int maxit,
+                      std::vector<LoadState>& hst) {
+  const int period = check_period(ctx, nload);
+  STCHK(read_states(ctx, st_off, nload, hst));
+  bool any = false;
+  for (auto& s : hst) any |= s.active != 0;
+  if (!any) return LSH_OK;
+  for (int it = 0; it < maxit; ++it) {
+    STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, x, nullptr, nullptr, st, true));
+    int np = 0;
+    STCHK(inverse_x<double>(ctx, 0, nload, XI_BASIC, x, x, nullptr, st, ctx->ptr<double>(ctx->off.partials), &np));
+    STCHK(scal(ctx, SC_BASIC, nload, np, st, 0.0));
+    if ((it + 1) % period == 0 || it + 1 == maxit) {
+      STCHK(read_states(ctx, st_off, nload, hst));
+      any = false;
+      for (auto& s : hst) any |= s.active != 0;
+      if (!any) break;
+    }
+  }
+  return LSH_OK;
+}
+
+// ||b - L x||^2 per load into sums[0..nload) (FP64 application on x64)
+lsh_status true_residual(lsh_ctx* ctx, int nload) {
+  double* x = ctx->ptr<double>(ctx->off.x64);
+  STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, x, nullptr, nullptr, nullptr, true));
+  int np = 0;
+  STCHK(inverse_x<double>(ctx, 0, nload, XI_RESNORM, x, nullptr, nullptr, nullptr,
+                          ctx->ptr<double>(ctx->off.partials), &np));
+  return scal(ctx, SC_SUM, nload, np, nullptr, 0.0);
+}
+
+lsh_status effective(lsh_ctx* ctx, int nload) {
+  const Geo& g = ctx->geo;
+  const int nb = (int)((g.nvox + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
+  {
+    Scope sc(ctx, K_MEAN);
+    hipLaunchKernelGGL((k_mean<double>), dim3(nb, nload * ctx->c), dim3(256), 0, ctx->stream, g,
+                       ctx->ptr<double>(ctx->off.x64), ctx->ptr<double>(ctx->off.partials), (int)ctx->pstride);
+    STCHK(check_launch(ctx, 0, "mean"));
+  }
+  STCHK(scal(ctx, SC_SUM, nload * ctx->c, nb, nullptr, 0.0));
+  std::vector<double> sums((size_t)nload * ctx->c);
+  HIPCHK(hipMemcpyAsync(sums.data(), ctx->ws + ctx->off.sums, sums.size() * sizeof(double), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  const int c = ctx->c;
+  ctx->sigma.assign((size_t)nload * c, 0.0);
+  for (int l = 0; l < nload; ++l)
+    for (int i = 0; i < c; ++i) {
+      double a = 0.0;
+      for (int j = 0; j < c; ++j) a += ctx->A0[i * c + j] * ctx->last_loads[(size_t)l * c + j];
+      ctx->sigma[(size_t)l * c + i] = a + sums[(size_t)l * c + i] / (double)g.nvox;
+    }
+  return LSH_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* lsh_version(void) { return "lsh 0.1.0 (gfx950)"; }
+
+const char* lsh_last_error(const lsh_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+lsh_status lsh_create(lsh_ctx** out, int dim, const int64_t* n, int physics, int precision, int max_loads,
+                      void* stream) {
+  if (!out || !n) return LSH_EINVAL;
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return LSH_EINVAL;
+  if (physics != LSH_SCALAR && physics != LSH_ELASTIC) return LSH_EINVAL;
+  if (physics == LSH_ELASTIC && dim != 3) return LSH_EINVAL;
+  if (precision != LSH_FP64 && precision != LSH_MIXED) return LSH_EINVAL;
+  if (max_loads < 1 || max_loads > 65535) return LSH_EINVAL;
+  for (int a = 0; a < dim; ++a) {
+    if (!is_pow2(n[a]) || n[a] > 1024) return LSH_EINVAL;
+    if (a == 0 && n[a] < 4) return LSH_EINVAL;
+    if (a > 0 && n[a] < 2) return LSH_EINVAL;
+  }
+  lsh_ctx* ctx = new lsh_ctx();
+  ctx->dim = dim;
+  ctx->physics = physics;
+  ctx->precision = precision;
+  ctx->max_loads = max_loads;
+  ctx->c = physics == LSH_ELASTIC ? 6 : dim;
+  for (int a = 0; a < dim; ++a) ctx->n[a] = (int)n[a];
+  ctx->stream = reinterpret_cast<hipStream_t>(stream);
+  ctx->geo.nx = ctx->n[0];
+  ctx->geo.ny = ctx->n[1];
+  ctx->geo.nz = ctx->n[2];
+  ctx->geo.mx = ctx->n[0] / 2;
+  ctx->geo.c = ctx->c;
+  ctx->geo.nvox = (long long)ctx->n[0] * ctx->n[1] * ctx->n[2];
+  ctx->F = (long long)ctx->c * ctx->geo.nvox;
+  ctx->A0.assign((size_t)ctx->c * ctx->c, 0.0);
+  compute_layout(ctx);
+  *out = ctx;
+  return LSH_OK;
+}
+
+lsh_status lsh_destroy(lsh_ctx* ctx) {
+  if (!ctx) return LSH_EINVAL;
+  drain_timers(ctx);
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return LSH_OK;
+}
+
+lsh_status lsh_workspace_bytes(const lsh_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return LSH_EINVAL;
+  *bytes = ctx->ws_need;
+  return LSH_OK;
+}
+
+lsh_status lsh_bind_workspace(lsh_ctx* ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return LSH_EINVAL;
+  if (!dev_ptr) return fail(ctx, LSH_EINVAL, "null workspace");
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % kAlign != 0) return fail(ctx, LSH_EINVAL, "workspace not 256-byte aligned");
+  if (bytes < ctx->ws_need)
+    return fail(ctx, LSH_ENOMEM, "workspace too small: need " + std::to_string(ctx->ws_need) + " bytes");
+  if (ctx->have_phase && ctx->phase_host.empty())
+    return fail(ctx, LSH_ESTATE, "device phase map must be set again after rebinding the workspace");
+  ctx->ws = static_cast<char*>(dev_ptr);
+  ctx->ws_size = bytes;
+  ctx->consts_ready = false;
+  ctx->tables_dirty = true;
+  ctx->phase_dirty = ctx->have_phase;
+  ctx->have_solution = false;
+  return LSH_OK;
+}
+
+lsh_status lsh_set_reference(lsh_ctx* ctx, const double* A0) {
+  if (!ctx) return LSH_EINVAL;
+  if (!A0) return fail(ctx, LSH_EINVAL, "null A0");
+  const int c = ctx->c;
+  for (int i = 0; i < c * c; ++i)
+    if (!std::isfinite(A0[i])) return fail(ctx, LSH_EINVAL, "A0 has a non-finite entry");
+  if (!symmetric(c, A0)) return fail(ctx, LSH_EINVAL, "A0 is not symmetric");
+  double ev[6];
+  sym_eigvals(c, A0, ev);
+  for (int i = 0; i < c; ++i)
+    if (!(ev[i] > 0.0)) return fail(ctx, LSH_EINVAL, "A0 is not positive definite");
+  if (ctx->physics == LSH_ELASTIC) {
+    const double lam = A0[1], mu2 = A0[3 * 6 + 3];
+    double scale = 0.0;
+    for (int i = 0; i < 36; ++i) scale = std::max(scale, std::fabs(A0[i]));
+    const double tol = 1e-12 * scale;
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) {
+        double expect = 0.0;
+        if (i < 3 && j < 3) expect = lam + (i == j ? mu2 : 0.0);
+        else if (i == j) expect = mu2;
+        if (std::fabs(A0[i * 6 + j] - expect) > tol)
+          return fail(ctx, LSH_EINVAL, "elastic A0 must be isotropic (lambda0, mu0) in Mandel form");
+      }
+  }
+  ctx->A0.assign(A0, A0 + c * c);
+  ctx->have_ref = true;
+  ctx->tables_dirty = true;
+  ctx->have_solution = false;
+  return LSH_OK;
+}
+
+lsh_status lsh_set_phases(lsh_ctx* ctx, const uint8_t* phase, int mem, int nphase, const double* moduli) {
+  if (!ctx) return LSH_EINVAL;
+  if (!phase || !moduli) return fail(ctx, LSH_EINVAL, "null phase map or moduli");
+  if (nphase < 1 || nphase > kMaxPhases) return fail(ctx, LSH_EINVAL, "nphase must be in 1..32");
+  if (mem != LSH_HOST && mem != LSH_DEVICE) return fail(ctx, LSH_EINVAL, "bad memory space");
+  const int c = ctx->c;
+  for (int p = 0; p < nphase; ++p) {
+    for (int i = 0; i < c * c; ++i)
+      if (!std::isfinite(moduli[(size_t)p * c * c + i]))
+        return fail(ctx, LSH_EINVAL, "non-finite modulus in phase " + std::to_string(p));
+    if (!symmetric(c, moduli + (size_t)p * c * c))
+      return fail(ctx, LSH_EINVAL, "phase " + std::to_string(p) + " modulus is not symmetric");
+  }
+  const size_t V = (size_t)ctx->geo.nvox;
+  if (mem == LSH_HOST) {
+    for (size_t i = 0; i < V; ++i)
+      if (phase[i] >= nphase) return fail(ctx, LSH_EINVAL, "phase id out of range at voxel " + std::to_string(i));
+    ctx->phase_host.assign(phase, phase + V);
+    ctx->phase_dev_src = nullptr;
+  } else {
+    if (!ctx->ws) return fail(ctx, LSH_ESTATE, "bind the workspace before passing a device phase map");
+    ctx->phase_host.clear();
+    ctx->phase_dev_src = phase;
+  }
+  ctx->nphase = nphase;
+  ctx->moduli.assign(moduli, moduli + (size_t)nphase * c * c);
+  ctx->have_phase = true;
+  ctx->phase_dirty = true;
+  ctx->tables_dirty = true;
+  ctx->have_solution = false;
+  return LSH_OK;
+}
+
+lsh_status lsh_set_green(lsh_ctx* ctx, int variant) {
+  if (!ctx) return LSH_EINVAL;
+  if (variant != LSH_GREEN_TRUNCATED && variant != LSH_GREEN_FILTERED)
+    return fail(ctx, LSH_EINVAL, "unknown Green operator");
+  ctx->green = variant;
+  ctx->tables_dirty = true;
+  ctx->have_solution = false;
+  return LSH_OK;
+}
+
+lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, double tol, int maxit,
+                     lsh_load_report* reports, lsh_solve_report* summary) {
+  if (!ctx) return LSH_EINVAL;
+  if (solver != LSH_SOLVER_BASIC && solver != LSH_SOLVER_CG) return fail(ctx, LSH_EINVAL, "unknown solver");
+  if (nload < 1 || nload > ctx->max_loads) return fail(ctx, LSH_EINVAL, "nload out of range");
+  if (!loads) return fail(ctx, LSH_EINVAL, "null loads");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(ctx, LSH_EINVAL, "tol must be positive");
+  if (maxit < 1) return fail(ctx, LSH_EINVAL, "maxit must be >= 1");
+  const int c = ctx->c;
+  for (int i = 0; i < nload * c; ++i)
+    if (!std::isfinite(loads[i])) return fail(ctx, LSH_EINVAL, "non-finite load");
+  STCHK(prepare(ctx));
+  const auto t0 = std::chrono::steady_clock::now();
+  ctx->have_solution = false;
+  ctx->last_nload = nload;
+  ctx->last_loads.assign(loads, loads + (size_t)nload * c);
+  ctx->h_loads = ctx->last_loads;
+  HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.loads, ctx->h_loads.data(), ctx->h_loads.size() * sizeof(double),
+                        hipMemcpyHostToDevice, ctx->stream));
+
+  LoadState* sto = ctx->ptr<LoadState>(ctx->off.st_out);
+  LoadState* sti = ctx->ptr<LoadState>(ctx->off.st_in);
+  double* x64 = ctx->ptr<double>(ctx->off.x64);
+  std::vector<LoadState> hst, hin;
+  std::vector<long long> iters(nload, 0);
+  long long apps64 = 0, apps32 = 0;
+  int outer = 0;
+  bool residual_known = false;
+  std::vector<double> res2(nload, 0.0), bb(nload, 0.0);
+
+  if (solver == LSH_SOLVER_BASIC) {
+    STCHK(cg_init<double>(ctx, nload, x64, nullptr, sto, tol));
+    STCHK(basic_loop(ctx, nload, x64, sto, ctx->off.st_out, maxit, hst));
+    STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
+    for (int l = 0; l < nload; ++l) iters[l] = hst[l].iters, apps64 += hst[l].iters;
+  } else if (ctx->precision == LSH_FP64) {
+    double* r = ctx->ptr<double>(ctx->off.r64);
+    double* p = ctx->ptr<double>(ctx->off.p64);
+    STCHK(cg_init<double>(ctx, nload, x64, r, sto, tol));
+    STCHK(cg_loop<double>(ctx, nload, x64, r, p, sto, ctx->off.st_out, maxit, hst));
+    STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
+    for (int l = 0; l < nload; ++l) iters[l] = hst[l].iters, apps64 += hst[l].iters;
+  } else {
+    // mixed precision: FP32 CG on the correction, FP64 residual refinement
+    float* d = ctx->ptr<float>(ctx->off.d32);
+    float* r = ctx->ptr<float>(ctx->off.r32);
+    float* p = ctx->ptr<float>(ctx->off.p32);
+    STCHK(cg_init<double>(ctx, nload, x64, nullptr, sto, tol));  // x64 = 0, outer ||b||^2
+    STCHK(cg_init<float>(ctx, nload, d, r, sti, 1e-4));          // d = 0, r = b
+    STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
+    double eta = 1e-4;
+    int budget = maxit;
+    while (true) {
+      // inner FP32 solve, then refresh the residual in FP64 (x64 += d inside)
+      STCHK(cg_loop<float>(ctx, nload, d, r, p, sti, ctx->off.st_in, budget, hin));
+      STCHK(read_states(ctx, ctx->off.st_in, nload, hin));
+      int used = 0;
+      for (int l = 0; l < nload; ++l) {
+        iters[l] += hin[l].iters;
+        apps32 += hin[l].iters;
+        used = std::max(used, hin[l].iters);
+      }
+      budget -= used;
+      STCHK(forward_part<double>(ctx, 0, nload, XF_IRX, nullptr, x64, d, sto, true));
+      int np = 0;
+      STCHK(inverse_x<double>(ctx, 0, nload, XI_IRRES, x64, nullptr, r, sto, ctx->ptr<double>(ctx->off.partials),
+                              &np));
+      STCHK(scal(ctx, SC_OUTER, nload, np, sto, 0.0));
+      ++outer;
+      STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
+      bool any = false;
+      double worst = 0.0;
+      for (int l = 0; l < nload; ++l) {
+        if (hst[l].active) {
+          any = true;
+          worst = std::max(worst, std::sqrt(hst[l].res2 / hst[l].bb));
+        }
+      }
+      if (!any || budget <= 0) break;
+      eta = std::max(1e-4, 0.5 * tol / std::max(worst, 1e-300));
+      eta = std::min(eta, 0.5);
+      // restart the inner solve on the loads still refining
+      const int nb = (int)((ctx->F + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
+      {
+        Scope sc(ctx, K_INIT);
+        hipLaunchKernelGGL((k_innerinit<float>), dim3(nb, nload), dim3(256), 0, ctx->stream, (long long)ctx->F, d, r,
+                           sto, ctx->ptr<double>(ctx->off.partials), (int)ctx->pstride);
+        STCHK(check_launch(ctx, 0, "inner init"));
+      }
+      STCHK(scal(ctx, SC_INIT, nload, nb, sti, eta));
+      // loads already refined stay frozen in the inner solve
+      STCHK(read_states(ctx, ctx->off.st_in, nload, hin));
+      bool patched = false;
+      for (int l = 0; l < nload; ++l)
+        if (!hst[l].active && hin[l].active) {
+          hin[l].active = 0;
+          patched = true;
+        }
+      if (patched) {
+        HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.st_in, hin.data(), sizeof(LoadState) * nload,
+                              hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+      }
+    }
+    for (int l = 0; l < nload; ++l) {
+      iters[l] += hst[l].iters;
+      apps64 += hst[l].iters;
+      res2[l] = hst[l].res2;
+      bb[l] = hst[l].bb;
+    }
+    residual_known = true;
+  }
+
+  // FP64 true residual of the result (CG and basic), A*
+  if (!residual_known) {
+    STCHK(true_residual(ctx, nload));
+    std::vector<double> s(nload);
+    HIPCHK(hipMemcpyAsync(s.data(), ctx->ws + ctx->off.sums, sizeof(double) * nload, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
+    for (int l = 0; l < nload; ++l) {
+      res2[l] = s[l];
+      bb[l] = hst[l].bb;
+    }
+    for (int l = 0; l < nload; ++l) apps64 += 1;
+  }
+  STCHK(effective(ctx, nload));
+  const auto t1 = std::chrono::steady_clock::now();
+
+  lsh_status overall = LSH_OK;
+  for (int l = 0; l < nload; ++l) {
+    lsh_status ls = LSH_OK;
+    if (hst[l].status == kStatusBreakdown) ls = LSH_EBREAKDOWN;
+    else if (hst[l].status == kStatusNumeric) ls = LSH_ENUMERIC;
+    else if (hst[l].active) ls = LSH_MAXIT;
+    if (reports) {
+      reports[l].iterations = (int32_t)iters[l];
+      reports[l].status = ls;
+      reports[l].rel_residual = bb[l] > 0 ? std::sqrt(res2[l] / bb[l]) : 0.0;
+    }
+    if (ls < 0 && overall >= 0) overall = ls;
+    if (ls == LSH_MAXIT && overall == LSH_OK) overall = LSH_MAXIT;
+  }
+  if (summary) {
+    summary->applications_fp64 = apps64;
+    summary->applications_fp32 = apps32;
+    summary->outer_iterations = outer;
+    summary->pad = 0;
+    summary->seconds = std::chrono::duration<double>(t1 - t0).count();
+  }
+  ctx->have_solution = true;
+  if (overall == LSH_EBREAKDOWN) ctx->err = "CG breakdown: the system is not positive definite for this A0";
+  if (overall == LSH_ENUMERIC) ctx->err = "NaN or Inf during the solve";
+  return overall;
+}
+
+lsh_status lsh_get_effective(lsh_ctx* ctx, double* sigma_mean) {
+  if (!ctx || !sigma_mean) return LSH_EINVAL;
+  if (!ctx->have_solution) return fail(ctx, LSH_ESTATE, "no solution");
+  std::memcpy(sigma_mean, ctx->sigma.data(), ctx->sigma.size() * sizeof(double));
+  return LSH_OK;
+}
+
+static lsh_status copy_field_out(lsh_ctx* ctx, const double* src, long long n, void* dst, int dtype, int mem) {
+  if (mem == LSH_DEVICE) {
+    if (dtype == LSH_F64) {
+      HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    } else {
+      Scope sc(ctx, K_COPY);
+      hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n,
+                         src, static_cast<float*>(dst));
+      STCHK(check_launch(ctx, 0, "convert"));
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return LSH_OK;
+  }
+  std::vector<double> h((size_t)n);
+  HIPCHK(hipMemcpyAsync(h.data(), src, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (dtype == LSH_F64) {
+    std::memcpy(dst, h.data(), n * sizeof(double));
+  } else {
+    float* f = static_cast<float*>(dst);
+    for (long long i = 0; i < n; ++i) f[i] = (float)h[(size_t)i];
+  }
+  return LSH_OK;
+}
+
+lsh_status lsh_get_field(lsh_ctx* ctx, int load, int which, void* dst, int dtype, int mem) {
+  if (!ctx) return LSH_EINVAL;
+  if (!dst) return fail(ctx, LSH_EINVAL, "null destination");
+  if (!ctx->have_solution) return fail(ctx, LSH_ESTATE, "no solution");
+  if (load < 0 || load >= ctx->last_nload) return fail(ctx, LSH_EINVAL, "load out of range");
+  if (dtype != LSH_F64 && dtype != LSH_F32) return fail(ctx, LSH_EINVAL, "bad dtype");
+  if (mem != LSH_HOST && mem != LSH_DEVICE) return fail(ctx, LSH_EINVAL, "bad memory space");
+  if (which != LSH_FIELD_TAU && which != LSH_FIELD_STRAIN) return fail(ctx, LSH_EINVAL, "bad field");
+  const long long F = ctx->F;
+  double* x = ctx->ptr<double>(ctx->off.x64) + (long long)load * F;
+  if (which == LSH_FIELD_TAU) return copy_field_out(ctx, x, F, dst, dtype, mem);
+  // strain p - Gamma tau, computed into the FP64 spectrum slot of this load
+  STCHK(forward_part<double>(ctx, load, 1, XF_PLAIN, x, nullptr, nullptr, nullptr, true));
+  double* out = reinterpret_cast<double*>(Sel<double>::sm(ctx) + (long long)load * main_cpx(ctx->geo));
+  STCHK(inverse_x<double>(ctx, load, 1, XI_STRAIN, x, out, nullptr, nullptr, nullptr, nullptr));
+  return copy_field_out(ctx, out, F, dst, dtype, mem);
+}
+
+lsh_status lsh_apply(lsh_ctx* ctx, int nload, const void* tau, void* out, int dtype) {
+  if (!ctx) return LSH_EINVAL;
+  if (nload < 1 || nload > ctx->max_loads) return fail(ctx, LSH_EINVAL, "nload out of range");
+  if (!tau || !out || tau == out) return fail(ctx, LSH_EINVAL, "bad buffers");
+  if (dtype != LSH_F64 && dtype != LSH_F32) return fail(ctx, LSH_EINVAL, "bad dtype");
+  if (dtype == LSH_F32 && ctx->precision != LSH_MIXED)
+    return fail(ctx, LSH_EINVAL, "FP32 application needs a mixed-precision context");
+  STCHK(prepare(ctx));
+  if (dtype == LSH_F64) {
+    STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, static_cast<const double*>(tau), nullptr, nullptr, nullptr,
+                               true));
+    STCHK(inverse_x<double>(ctx, 0, nload, XI_APPLY, static_cast<const double*>(tau), static_cast<double*>(out),
+                            nullptr, nullptr, nullptr, nullptr));
+  } else {
+    STCHK(forward_part<float>(ctx, 0, nload, XF_PLAIN, static_cast<const float*>(tau), nullptr, nullptr, nullptr,
+                              true));
+    STCHK(inverse_x<float>(ctx, 0, nload, XI_APPLY, static_cast<const float*>(tau), static_cast<float*>(out), nullptr,
+                           nullptr, nullptr, nullptr));
+  }
+  ctx->have_solution = false;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return LSH_OK;
+}
+
+lsh_status lsh_spectrum_bytes(const lsh_ctx* ctx, int dtype, size_t* bytes) {
+  if (!ctx || !bytes) return LSH_EINVAL;
+  if (dtype != LSH_F64 && dtype != LSH_F32) return LSH_EINVAL;
+  const size_t s = dtype == LSH_F64 ? 16 : 8;
+  *bytes = s * (size_t)(main_cpx(ctx->geo) + nyq_cpx(ctx->geo));
+  return LSH_OK;
+}
+
+lsh_status lsh_forward_dft(lsh_ctx* ctx, int nload, const void* field, void* spec, int dtype) {
+  if (!ctx) return LSH_EINVAL;
+  if (nload < 1 || nload > ctx->max_loads) return fail(ctx, LSH_EINVAL, "nload out of range");
+  if (!field || !spec) return fail(ctx, LSH_EINVAL, "bad buffers");
+  if (dtype != LSH_F64 && dtype != LSH_F32) return fail(ctx, LSH_EINVAL, "bad dtype");
+  if (dtype == LSH_F32 && ctx->precision != LSH_MIXED)
+    return fail(ctx, LSH_EINVAL, "FP32 transforms need a mixed-precision context");
+  STCHK(prepare(ctx));
+  const long long nm = main_cpx(ctx->geo) * nload, nn = nyq_cpx(ctx->geo) * nload;
+  if (dtype == LSH_F64) {
+    STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, static_cast<const double*>(field), nullptr, nullptr, nullptr,
+                               false));
+    HIPCHK(hipMemcpyAsync(spec, Sel<double>::sm(ctx), nm * 16, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(static_cast<char*>(spec) + nm * 16, Sel<double>::sn(ctx), nn * 16, hipMemcpyDeviceToDevice,
+                          ctx->stream));
+  } else {
+    STCHK(forward_part<float>(ctx, 0, nload, XF_PLAIN, static_cast<const float*>(field), nullptr, nullptr, nullptr,
+                              false));
+    HIPCHK(hipMemcpyAsync(spec, Sel<float>::sm(ctx), nm * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(static_cast<char*>(spec) + nm * 8, Sel<float>::sn(ctx), nn * 8, hipMemcpyDeviceToDevice,
+                          ctx->stream));
+  }
+  ctx->have_solution = false;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return LSH_OK;
+}
+
+lsh_status lsh_set_timing(lsh_ctx* ctx, int enable) {
+  if (!ctx) return LSH_EINVAL;
+  drain_timers(ctx);
+  ctx->timing = enable != 0;
+  for (int k = 0; k < K_NCLASS; ++k) {
+    ctx->tsum[k] = 0.0;
+    ctx->tcount[k] = 0;
+  }
+  return LSH_OK;
+}
+
+lsh_status lsh_kernel_times(lsh_ctx* ctx, const char** names, double* total_ms, int64_t* launches, int cap,
+                            int* count) {
+  if (!ctx || !count) return LSH_EINVAL;
+  drain_timers(ctx);
+  int k = 0;
+  for (int i = 0; i < K_NCLASS; ++i) {
+    if (k < cap) {
+      if (names) names[k] = kClassNames[i];
+      if (total_ms) total_ms[k] = ctx->tsum[i];
+      if (launches) launches[k] = ctx->tcount[i];
+    }
+    ++k;
+  }
+  *count = K_NCLASS;
+  return LSH_OK;
+}
+
+}  // extern "C"

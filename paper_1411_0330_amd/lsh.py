@@ -1,0 +1,286 @@
+"""ctypes binding of the C ABI in include/lsh.h (argument marshalling only).
+
+Every step of the solver runs in the HIP library ``_lib/liblsh.so``; this
+module loads it (and fails loudly when it is missing), converts arguments and
+lets PyTorch own the device memory (the workspace and field buffers) and the
+stream.  Array conventions follow the C ABI: fields are
+``[load][component][z][y][x]`` with x fastest; grid shapes are given in array
+order ``(NY, NX)`` or ``(NZ, NY, NX)``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "liblsh.so")
+
+OK, MAXIT, EINVAL, ENOMEM, EHIP, EHYP2, EBREAKDOWN, ENUMERIC, ESTATE = 0, 1, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "OK", 1: "MAXIT", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EHYP2",
+                -5: "EBREAKDOWN", -6: "ENUMERIC", -7: "ESTATE"}
+SCALAR, ELASTIC = 0, 1
+FP64, MIXED = 0, 1
+TRUNCATED, FILTERED = 0, 1
+BASIC, CG = 0, 1
+HOST, DEVICE = 0, 1
+F64, F32 = 0, 1
+TAU, STRAIN = 0, 1
+
+GREEN = {"truncated": TRUNCATED, "filtered": FILTERED}
+SOLVERS = {"basic": BASIC, "cg": CG}
+PHYSICS = {"scalar": SCALAR, "elastic": ELASTIC}
+PRECISION = {"fp64": FP64, "mixed": MIXED}
+
+
+class LoadReport(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("status", C.c_int32), ("rel_residual", C.c_double)]
+
+
+class SolveReport(C.Structure):
+    _fields_ = [("applications_fp64", C.c_int64), ("applications_fp32", C.c_int64),
+                ("outer_iterations", C.c_int32), ("pad", C.c_int32), ("seconds", C.c_double)]
+
+
+_lib = None
+
+_SIGS = {
+    "lsh_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int64), C.c_int, C.c_int, C.c_int,
+                             C.c_void_p]),
+    "lsh_destroy": (C.c_int, [C.c_void_p]),
+    "lsh_workspace_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "lsh_bind_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "lsh_set_reference": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "lsh_set_phases": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)]),
+    "lsh_set_green": (C.c_int, [C.c_void_p, C.c_int]),
+    "lsh_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_double, C.c_int,
+                            C.POINTER(LoadReport), C.POINTER(SolveReport)]),
+    "lsh_get_field": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int]),
+    "lsh_get_effective": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "lsh_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
+    "lsh_forward_dft": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
+    "lsh_spectrum_bytes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_size_t)]),
+    "lsh_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "lsh_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int)]),
+    "lsh_last_error": (C.c_char_p, [C.c_void_p]),
+    "lsh_version": (C.c_char_p, []),
+}
+
+
+def _hip_runtimes():
+    """Distinct HIP runtime files mapped into this process."""
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln})
+    except OSError:
+        return []
+
+
+def load():
+    """Load the HIP library (raises when it has not been built).
+
+    PyTorch is imported first so that the library binds to the HIP runtime
+    PyTorch already uses (same soname): device pointers and streams from
+    PyTorch are then valid in the library.  Two runtimes in one process are
+    refused."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (loads the process's HIP runtime)
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library missing: {LIB_PATH} (build it with __graft_entry__.build())")
+        lib = C.CDLL(LIB_PATH)
+        rts = _hip_runtimes()
+        if len(rts) > 1:
+            raise RuntimeError(f"two HIP runtimes loaded in one process: {rts}")
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class LshError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _dptr(a, n=None):
+    return C.cast(a.ctypes.data, C.POINTER(C.c_double))
+
+
+class Context:
+    """One solver context on one stream (thin wrapper over lsh_ctx)."""
+
+    def __init__(self, shape, physics="scalar", precision="fp64", max_loads=1, device="cuda:0",
+                 stream=None, bind=True):
+        self.lib = load()
+        self.shape = tuple(int(s) for s in shape)
+        self.dim = len(self.shape)
+        self.physics = physics
+        self.precision = precision
+        self.max_loads = int(max_loads)
+        self.c = 6 if physics == "elastic" else self.dim
+        n = (C.c_int64 * 3)(*reversed(self.shape), *([1] * (3 - self.dim)))
+        self._stream = stream
+        sptr = None
+        if stream is not None:
+            sptr = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        h = C.c_void_p()
+        self._check(self.lib.lsh_create(C.byref(h), self.dim, n, PHYSICS[physics], PRECISION[precision],
+                                        self.max_loads, sptr), ctx=None)
+        self.h = h
+        self.device = device
+        self.workspace = None
+        if bind:
+            self.bind()
+
+    # -- plumbing ------------------------------------------------------
+    def _check(self, status, ctx="self", allow=(OK,)):
+        if status in allow:
+            return status
+        msg = ""
+        if ctx == "self":
+            msg = (self.lib.lsh_last_error(self.h) or b"").decode()
+        raise LshError(status, msg)
+
+    def workspace_bytes(self):
+        b = C.c_size_t()
+        self._check(self.lib.lsh_workspace_bytes(self.h, C.byref(b)))
+        return int(b.value)
+
+    def bind(self):
+        import torch
+        nbytes = self.workspace_bytes()
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = self.workspace.data_ptr()
+        ptr = (ptr + 255) // 256 * 256
+        self._check(self.lib.lsh_bind_workspace(self.h, C.c_void_p(ptr), nbytes))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lsh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- problem -------------------------------------------------------
+    def set_reference(self, A0):
+        A0 = np.ascontiguousarray(A0, dtype=np.float64)
+        return self._check(self.lib.lsh_set_reference(self.h, _dptr(A0)))
+
+    def set_phases(self, phase, moduli):
+        moduli = np.ascontiguousarray(moduli, dtype=np.float64)
+        nphase = moduli.shape[0]
+        if hasattr(phase, "data_ptr"):
+            assert phase.dtype.__str__() == "torch.uint8" and phase.is_contiguous()
+            self._phase_ref = phase
+            return self._check(self.lib.lsh_set_phases(self.h, C.c_void_p(phase.data_ptr()), DEVICE, nphase,
+                                                       _dptr(moduli)))
+        ph = np.ascontiguousarray(phase, dtype=np.uint8)
+        return self._check(self.lib.lsh_set_phases(self.h, C.c_void_p(ph.ctypes.data), HOST, nphase,
+                                                   _dptr(moduli)))
+
+    def set_green(self, variant):
+        return self._check(self.lib.lsh_set_green(self.h, GREEN[variant] if isinstance(variant, str) else variant))
+
+    # -- solve ---------------------------------------------------------
+    def solve(self, loads, solver="cg", tol=1e-10, maxit=1000, allow=(OK, MAXIT)):
+        loads = np.ascontiguousarray(np.atleast_2d(loads), dtype=np.float64)
+        nload = loads.shape[0]
+        reps = (LoadReport * nload)()
+        summ = SolveReport()
+        st = self.lib.lsh_solve(self.h, SOLVERS[solver], nload, _dptr(loads), float(tol), int(maxit), reps,
+                                C.byref(summ))
+        self._check(st, allow=allow)
+        self.nload = nload
+        return {
+            "status": st,
+            "iterations": [r.iterations for r in reps],
+            "load_status": [r.status for r in reps],
+            "rel_residual": [r.rel_residual for r in reps],
+            "applications_fp64": summ.applications_fp64,
+            "applications_fp32": summ.applications_fp32,
+            "outer_iterations": summ.outer_iterations,
+            "seconds": summ.seconds,
+        }
+
+    def effective(self):
+        """(nload, c) array: row l is A0 p_l + <tau_l>."""
+        out = np.zeros((self.nload, self.c))
+        self._check(self.lib.lsh_get_effective(self.h, _dptr(out)))
+        return out
+
+    def field(self, load=0, which="tau", dtype="f64", device=True):
+        import torch
+        tdt = torch.float64 if dtype == "f64" else torch.float32
+        code = F64 if dtype == "f64" else F32
+        w = TAU if which == "tau" else STRAIN
+        if device:
+            out = torch.empty((self.c,) + self.shape, dtype=tdt, device=self.device)
+            self._check(self.lib.lsh_get_field(self.h, load, w, C.c_void_p(out.data_ptr()), code, DEVICE))
+            return out
+        out = np.empty((self.c,) + self.shape, dtype=np.float64 if dtype == "f64" else np.float32)
+        self._check(self.lib.lsh_get_field(self.h, load, w, C.c_void_p(out.ctypes.data), code, HOST))
+        return out
+
+    # -- operator and transform ----------------------------------------
+    def apply(self, tau):
+        """L tau for a device tensor (nload, c, *shape), float64 or float32."""
+        import torch
+        code = F64 if tau.dtype == torch.float64 else F32
+        tau = tau.contiguous()
+        out = torch.empty_like(tau)
+        self._check(self.lib.lsh_apply(self.h, tau.shape[0], C.c_void_p(tau.data_ptr()),
+                                       C.c_void_p(out.data_ptr()), code))
+        return out
+
+    def forward_dft(self, field):
+        """Packed half spectrum of a device tensor (nload, c, *shape):
+        returns (main [nload, c, nz?, ny, nx/2], nyquist [nload, c, nz?, ny]) complex tensors."""
+        import torch
+        code = F64 if field.dtype == torch.float64 else F32
+        field = field.contiguous()
+        nload = field.shape[0]
+        b = C.c_size_t()
+        self._check(self.lib.lsh_spectrum_bytes(self.h, code, C.byref(b)))
+        rdt = torch.float64 if code == F64 else torch.float32
+        spec = torch.empty(nload * b.value // (8 if code == F64 else 4), dtype=rdt, device=self.device)
+        self._check(self.lib.lsh_forward_dft(self.h, nload, C.c_void_p(field.data_ptr()),
+                                             C.c_void_p(spec.data_ptr()), code))
+        mx = self.shape[-1] // 2
+        lead = self.shape[:-1]
+        nmain = nload * self.c * int(np.prod(lead)) * mx
+        cs = torch.view_as_complex(spec.view(-1, 2))
+        main = cs[:nmain].reshape((nload, self.c) + lead + (mx,))
+        nyq = cs[nmain:].reshape((nload, self.c) + lead)
+        return main, nyq
+
+    # -- timing --------------------------------------------------------
+    def set_timing(self, enable=True):
+        self._check(self.lib.lsh_set_timing(self.h, 1 if enable else 0))
+
+    def kernel_times(self):
+        cap = 32
+        names = (C.c_char_p * cap)()
+        ms = (C.c_double * cap)()
+        cnt = (C.c_int64 * cap)()
+        n = C.c_int()
+        self._check(self.lib.lsh_kernel_times(self.h, names, ms, cnt, cap, C.byref(n)))
+        return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(min(n.value, cap))}
+
+
+def header_symbols(header_path=None):
+    """Function names declared in include/lsh.h."""
+    import re
+    header_path = header_path or os.path.join(os.path.dirname(HERE), "include", "lsh.h")
+    text = open(header_path).read()
+    # declarations: a return type at the start of a line, then the name and "("
+    return sorted(set(re.findall(r"^(?:const\s+)?\w+\s*\*?\s*(lsh_[a-z_]+)\s*\(", text, re.M)))

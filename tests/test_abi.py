@@ -1,0 +1,118 @@
+"""Host-side checks of the C ABI (no GPU work is queued by these calls).
+
+The library must load, export every function that include/lsh.h declares, and
+reject invalid arguments before touching the device.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_1411_0330_amd import inputs as I
+from paper_1411_0330_amd import lsh as L
+
+
+def _create(lib, dim, n, physics=L.SCALAR, precision=L.FP64, max_loads=1):
+    h = C.c_void_p()
+    arr = (C.c_int64 * 3)(*n, *([1] * (3 - len(n))))
+    st = lib.lsh_create(C.byref(h), dim, arr, physics, precision, max_loads, None)
+    return st, h
+
+
+def test_library_exports_every_header_symbol():
+    lib = L.load()
+    syms = L.header_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert lib.lsh_version().decode().startswith("lsh")
+
+
+@pytest.mark.parametrize("dim,n,physics,ok", [
+    (2, (64, 64), L.SCALAR, True),
+    (3, (8, 16, 32), L.SCALAR, True),
+    (3, (4, 2, 2), L.ELASTIC, True),
+    (3, (1024, 1024, 1024), L.ELASTIC, True),
+    (2, (64, 64), L.ELASTIC, False),        # elasticity is 3D
+    (2, (48, 64), L.SCALAR, False),         # not a power of two
+    (2, (2, 64), L.SCALAR, False),          # nx >= 4
+    (3, (8, 8, 2048), L.SCALAR, False),     # at most 1024
+    (4, (8, 8, 8), L.SCALAR, False),
+])
+def test_create_validation(dim, n, physics, ok):
+    lib = L.load()
+    st, h = _create(lib, dim, n, physics)
+    assert (st == L.OK) == ok
+    if ok:
+        b = C.c_size_t()
+        assert lib.lsh_workspace_bytes(h, C.byref(b)) == L.OK
+        c = 6 if physics == L.ELASTIC else dim
+        assert b.value >= 8 * c * int(np.prod(n)) * 3
+        lib.lsh_destroy(h)
+
+
+def test_reference_and_phase_validation_and_hypothesis2():
+    lib = L.load()
+    st, h = _create(lib, 2, (8, 8), max_loads=2)
+    assert st == L.OK
+    dp = lambda a: np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(C.POINTER(C.c_double))
+    assert lib.lsh_set_reference(h, dp([[1.0, 0.0], [0.0, -1.0]])) == L.EINVAL     # not SPD
+    assert lib.lsh_set_reference(h, dp([[1.0, 0.5], [0.0, 1.0]])) == L.EINVAL      # not symmetric
+    assert lib.lsh_set_reference(h, dp(np.eye(2))) == L.OK
+    ph = np.zeros((8, 8), np.uint8)
+    ph[2, 3] = 2
+    mod = np.stack([np.eye(2) * 2, np.eye(2) * 3])
+    vp = C.c_void_p(ph.ctypes.data)
+    assert lib.lsh_set_phases(h, vp, L.HOST, 2, dp(mod)) == L.EINVAL                # id out of range
+    assert lib.lsh_set_phases(h, vp, L.HOST, 33, dp(np.zeros((33, 2, 2)))) == L.EINVAL
+    ph[2, 3] = 1
+    # phase 1 has A - A0 indefinite: hypothesis (2) fails, reported before any GPU work
+    bad = np.stack([np.eye(2) * 2, np.diag([3.0, 0.5])])
+    assert lib.lsh_set_phases(h, vp, L.HOST, 2, dp(bad)) == L.OK
+    loads = np.eye(2)
+    assert lib.lsh_solve(h, L.CG, 2, dp(loads), 1e-8, 10, None, None) == L.EHYP2
+    assert b"hypothesis (2)" in lib.lsh_last_error(h)
+    # singular difference (one eigenvalue zero) also violates it
+    sing = np.stack([np.eye(2) * 2, np.diag([1.0, 4.0])])
+    assert lib.lsh_set_phases(h, vp, L.HOST, 2, dp(sing)) == L.OK
+    assert lib.lsh_solve(h, L.CG, 2, dp(loads), 1e-8, 10, None, None) == L.EHYP2
+    # valid phases but no workspace bound: out-of-order call
+    assert lib.lsh_set_phases(h, vp, L.HOST, 2, dp(mod)) == L.OK
+    assert lib.lsh_solve(h, L.CG, 2, dp(loads), 1e-8, 10, None, None) == L.ESTATE
+    # argument checks
+    assert lib.lsh_solve(h, 7, 2, dp(loads), 1e-8, 10, None, None) == L.EINVAL
+    assert lib.lsh_solve(h, L.CG, 3, dp(np.eye(3)), 1e-8, 10, None, None) == L.EINVAL   # > max_loads
+    assert lib.lsh_solve(h, L.CG, 1, dp(loads), -1.0, 10, None, None) == L.EINVAL
+    assert lib.lsh_solve(h, L.CG, 1, dp([np.nan, 0.0]), 1e-8, 10, None, None) == L.EINVAL
+    assert lib.lsh_set_green(h, 9) == L.EINVAL
+    assert lib.lsh_get_effective(h, dp(np.zeros(4))) == L.ESTATE
+    lib.lsh_destroy(h)
+
+
+def test_elastic_reference_must_be_isotropic():
+    lib = L.load()
+    st, h = _create(lib, 3, (4, 4, 4), L.ELASTIC)
+    assert st == L.OK
+    dp = lambda a: np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(C.POINTER(C.c_double))
+    assert lib.lsh_set_reference(h, dp(I.elastic_from_young(1.0, 0.3))) == L.OK
+    aniso = I.elastic_from_young(1.0, 0.3)
+    aniso[0, 0] += 0.1
+    assert lib.lsh_set_reference(h, dp(aniso)) == L.EINVAL
+    lib.lsh_destroy(h)
+
+
+def test_bind_checks_size_and_alignment():
+    lib = L.load()
+    st, h = _create(lib, 2, (8, 8))
+    b = C.c_size_t()
+    lib.lsh_workspace_bytes(h, C.byref(b))
+    assert lib.lsh_bind_workspace(h, C.c_void_p(4096 * 1024 + 8), b.value) == L.EINVAL       # misaligned
+    assert lib.lsh_bind_workspace(h, C.c_void_p(4096 * 1024), b.value - 1) == L.ENOMEM
+    assert lib.lsh_bind_workspace(h, None, b.value) == L.EINVAL
+    lib.lsh_destroy(h)
+
+
+def test_single_hip_runtime_in_process():
+    # the library binds to the runtime PyTorch loaded (shared device pointers and streams)
+    L.load()
+    assert len(L._hip_runtimes()) == 1

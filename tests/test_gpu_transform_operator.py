@@ -1,0 +1,184 @@
+"""GPU parity of the transform passes and of the operator of eq. (13).
+
+* The packed half spectrum of the forward passes against numpy.fft.rfftn
+  (the unnormalised DFT of Section 3.1), in FP64 and FP32, over axis lengths
+  2..1024 and ragged (non-cubic) grids.
+* L tau from the HIP kernels against the oracle's L tau (full complex FFTs,
+  generic Green tables and per-voxel inverses) on seeded random fields:
+  scalar 2D/3D with anisotropic phases, elasticity, truncated and filtered,
+  a phase equal to A0 (outside I0), several loads.
+* Full size: at the 256^3 elastic shape of the benchmark (6 loads, FP32 and
+  FP64), plane-wave polarisations tau = a cos(2 pi k.x) whose exact image is
+  1_{I0}((A - A0)^{-1} tau + Gamma_hat_k a cos(2 pi k.x)), with Gamma_hat_k
+  evaluated by the oracle at those wave-vectors only.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import green
+from oracle import operator as op
+from paper_1411_0330_amd import inputs as I
+
+from .gpu_util import context, problem, rel_max_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SCAL2 = np.stack([I.scalar_isotropic(1.0, 2), I.scalar_isotropic(10.0, 2)])
+SCAL3 = np.stack([I.scalar_isotropic(1.0, 3), I.scalar_isotropic(100.0, 3)])
+ELAS = np.stack([I.elastic_from_young(1.0, 0.3), I.elastic_from_young(10.0, 0.2)])
+MU0 = 0.5 * I.lame_from_young(1.0, 0.3)[1]
+C0 = I.elastic_isotropic_mandel(2 * MU0 * 0.3 / 0.4, MU0)
+
+
+@pytest.mark.parametrize("shape,physics,nload,dtype", [
+    ((4, 8), "scalar", 1, "f64"),
+    ((16, 4), "scalar", 2, "f64"),
+    ((64, 64), "scalar", 2, "f32"),
+    ((1024, 8), "scalar", 1, "f64"),
+    ((8, 1024), "scalar", 1, "f32"),
+    ((2, 2, 4), "scalar", 1, "f64"),
+    ((8, 4, 16), "scalar", 3, "f64"),
+    ((8, 4, 16), "scalar", 3, "f32"),
+    ((32, 16, 64), "scalar", 1, "f32"),
+    ((4, 8, 8), "elastic", 2, "f64"),
+    ((16, 128, 256), "scalar", 1, "f64"),
+    ((1024, 2, 4), "scalar", 1, "f64"),
+    ((2, 1024, 4), "elastic", 1, "f32"),
+    ((4, 4, 1024), "scalar", 1, "f32"),
+    ((64, 64, 64), "elastic", 1, "f32"),
+])
+def test_forward_dft_matches_numpy(lsh, shape, physics, nload, dtype):
+    d = len(shape)
+    c = 6 if physics == "elastic" else d
+    moduli = ELAS if physics == "elastic" else (SCAL2 if d == 2 else SCAL3)
+    A0 = C0 if physics == "elastic" else 0.5 * np.eye(d)
+    ctx = context(lsh, np.zeros(shape, np.uint8), moduli, A0, physics, "filtered",
+                  precision="mixed" if dtype == "f32" else "fp64", max_loads=nload)
+    f = I.random_field(shape, c, nload, seed=11)
+    main, nyq = ctx.forward_dft(to_dev(f, dtype))
+    ref = np.fft.rfftn(f, axes=tuple(range(2, 2 + d)))
+    mx = shape[-1] // 2
+    tol = 1e-12 if dtype == "f64" else 5e-6
+    scale = np.abs(ref).max()
+    assert np.abs(main.cpu().numpy() - ref[..., :mx]).max() <= tol * scale
+    assert np.abs(nyq.cpu().numpy() - ref[..., mx]).max() <= tol * scale
+
+
+def _aniso_scalar(d, seed):
+    rng = np.random.default_rng(seed)
+    mods = []
+    for a in (1.0, 10.0, 3.0):
+        M = rng.standard_normal((d, d))
+        mods.append(a * np.eye(d) + 0.2 * a * (M @ M.T) / d)
+    return np.stack(mods)
+
+
+OP_CASES = [
+    # physics, shape, green, nload, extra
+    ("scalar", (16, 32), "truncated", 2, "aniso"),
+    ("scalar", (8, 64), "filtered", 1, "aniso"),
+    ("scalar", (8, 16, 4), "truncated", 3, "masked"),
+    ("scalar", (4, 8, 16), "filtered", 2, "aniso-A0"),
+    ("scalar", (32, 32, 32), "filtered", 3, ""),
+    ("elastic", (8, 8, 8), "truncated", 2, "masked"),
+    ("elastic", (4, 16, 8), "filtered", 6, ""),
+    ("elastic", (16, 16, 16), "filtered", 1, ""),
+    ("elastic", (2, 4, 32), "truncated", 1, ""),
+]
+
+
+def _op_setup(physics, shape, variant, extra, seed=0):
+    d = len(shape)
+    ph = I.random_phases(shape, 3, seed=seed)
+    if physics == "elastic":
+        moduli = np.stack([ELAS[0], ELAS[1], I.elastic_from_young(4.0, 0.25)])
+        A0 = C0
+        if extra == "masked":
+            moduli[2] = C0
+    else:
+        moduli = _aniso_scalar(d, seed + 1)
+        A0 = 0.5 * np.eye(d)
+        if extra == "aniso-A0":
+            A0 = np.diag(np.linspace(0.3, 0.5, d)) + 0.05 * (np.ones((d, d)) - np.eye(d))
+        if extra == "masked":
+            moduli[2] = A0
+    return ph, moduli, A0
+
+
+@pytest.mark.parametrize("physics,shape,variant,nload,extra", OP_CASES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_operator_matches_oracle(lsh, physics, shape, variant, nload, extra, dtype):
+    ph, moduli, A0 = _op_setup(physics, shape, variant, extra)
+    pb = problem(ph, moduli, A0, physics, variant)
+    ctx = context(lsh, ph, moduli, A0, physics, variant, precision="mixed" if dtype == "f32" else "fp64",
+                  max_loads=nload)
+    m = op.mask(pb)
+    tau = I.random_field(shape, pb.c, nload, seed=7) * m
+    out = ctx.apply(to_dev(tau, dtype)).cpu().numpy()
+    ref = np.stack([op.apply(pb, tau[l]) for l in range(nload)])
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    assert rel_max_err(out, ref) <= tol
+    if extra == "masked":
+        assert np.all(out[:, :, ~m] == 0)
+
+
+def _plane_wave_case(shape, physics, variant, nload, seed):
+    """Per load: tau = sum over two wave-vectors of a_m cos(2 pi k_m.x/N), and
+    the exact Gamma tau from Gamma_hat at those wave-vectors."""
+    rng = np.random.default_rng(seed)
+    d = len(shape)
+    c = 6 if physics == "elastic" else d
+    A0 = C0 if physics == "elastic" else 0.5 * np.eye(d)
+    nphys = shape[::-1]
+    coords = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")   # array axes
+    tau = np.zeros((nload, c) + shape)
+    gam = np.zeros_like(tau)
+    special = [np.zeros(d, int), np.array([n // 2 for n in nphys]), np.array([nphys[0] // 2] + [1] * (d - 1))]
+    for l in range(nload):
+        for mnum in range(2):
+            if l < len(special) and mnum == 0:
+                k = special[l]
+            else:
+                k = np.array([rng.integers(0, n) for n in nphys])
+            amp = rng.standard_normal(c)
+            phase = 2 * math.pi * sum(k[a] * coords[d - 1 - a] / nphys[a] for a in range(d))
+            cosw = np.cos(phase)
+            G = green.at(shape, physics, A0, variant, k[None, :])[0]
+            tau[l] += amp.reshape(c, *([1] * d)) * cosw
+            gam[l] += (G @ amp).reshape(c, *([1] * d)) * cosw
+    return tau, gam, A0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_operator_full_size_plane_waves(lsh, dtype):
+    # the benchmark's shape and batch: 256^3 elasticity, 6 loads, filtered
+    shape, nload, variant = (256, 256, 256), 6, "filtered"
+    w = I.elastic_rsa_workload(256)
+    tau, gam, A0 = _plane_wave_case(shape, "elastic", variant, nload, seed=3)
+    ctx = context(lsh, w.phase, w.moduli, A0, "elastic", variant, precision="mixed" if dtype == "f32" else "fp64",
+                  max_loads=nload)
+    out = ctx.apply(to_dev(tau, dtype)).cpu().numpy()
+    pb = problem(w.phase, w.moduli, A0, "elastic", variant)
+    _, dinv, in_i0 = op.phase_tables(pb)
+    tol = 1e-11 if dtype == "f64" else 2e-5
+    for l in range(nload):
+        loc = np.einsum("...ij,j...->i...", dinv[w.phase], tau[l])
+        ref = in_i0[w.phase] * (loc + gam[l])
+        assert rel_max_err(out[l], ref) <= tol, l
+
+
+def test_operator_full_size_scalar_128_plane_waves(lsh):
+    shape, nload, variant = (128, 128, 128), 3, "filtered"
+    w = I.boolean_workload(128)
+    tau, gam, A0 = _plane_wave_case(shape, "scalar", variant, nload, seed=5)
+    for dtype in ("f64", "f32"):
+        ctx = context(lsh, w.phase, w.moduli, A0, "scalar", variant,
+                      precision="mixed" if dtype == "f32" else "fp64", max_loads=nload)
+        out = ctx.apply(to_dev(tau, dtype)).cpu().numpy()
+        pb = problem(w.phase, w.moduli, A0, "scalar", variant)
+        _, dinv, in_i0 = op.phase_tables(pb)
+        for l in range(nload):
+            ref = in_i0[w.phase] * (np.einsum("...ij,j...->i...", dinv[w.phase], tau[l]) + gam[l])
+            assert rel_max_err(out[l], ref) <= (1e-11 if dtype == "f64" else 2e-5)
