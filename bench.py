@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Throughput of the Lippmann--Schwinger corrector solver on one MI355X.
+
+A step is one pass of the whole hot path over one batch of synthetic input:
+material setup from an HBM-resident phase map, the batched solve of the six
+Mandel unit strains (FP32 fields and transforms, FP64 dot products and FP64
+iterative refinement of the residual, conjugate gradients to a relative
+residual of 1e-6), the effective tensor C*, and the polarisation and strain
+fields of every load copied out.
+
+The metric is voxel-iterations per second: voxels times operator
+applications (FP32 inner, FP64 refinement and strain applications alike),
+summed over loads, per second of wall time with inputs already in HBM.  The
+same workload is also solved once with the plain FP64 path for comparison,
+the dominant kernel's algorithmic bandwidth is measured live with HIP events,
+and the CPU oracle is timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak, GB/s
+METRIC = "voxel-iterations/s + % HBM roofline, 3D elasticity 256³, mixed vs FP64"
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=256, help="voxels per axis (the named workload is 256)")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--maxit", type=int, default=2000)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-timing", action="store_true", help="do not bracket kernels with HIP events")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_steps(ctx, lsh, w, phase_dev, nsteps, args, keep_fields=True):
+    """Run nsteps solves; returns (seconds, voxel-applications, last report, last effective)."""
+    import torch
+    nvox = int(w.phase.size)
+    total_apps = 0
+    rep = None
+    eff = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        ctx.set_phases(phase_dev, w.moduli)
+        rep = ctx.solve(w.loads, "cg", tol=args.tol, maxit=args.maxit)
+        eff = ctx.effective()
+        apps = rep["applications_fp32"] + rep["applications_fp64"]
+        if keep_fields:
+            for l in range(w.loads.shape[0]):
+                ctx.field(l, "tau", dtype="f32")
+                ctx.field(l, "strain", dtype="f32")
+                apps += 1          # the strain is one more Green application
+        total_apps += apps
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, total_apps * nvox, rep, eff
+
+
+def roofline_from(ktimes):
+    """Dominant kernel class by time; its algorithmic GB/s against the HBM peak."""
+    best = max(ktimes.items(), key=lambda kv: kv[1][0])
+    name, (ms, launches, nbytes) = best
+    achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    total_ms = sum(v[0] for v in ktimes.values())
+    total_bytes = sum(v[2] for v in ktimes.values())
+    return {
+        "kernel": name,
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "avg_launch_ms": round(ms / max(launches, 1), 4),
+        "launches": launches,
+        "all_kernels_GBps": round(total_bytes / (total_ms * 1e-3) / 1e9, 1) if total_ms > 0 else 0.0,
+        "kernel_time_share": round(ms / total_ms, 3) if total_ms > 0 else 0.0,
+    }
+
+
+def cpu_baseline(w, target_s=20.0):
+    """The oracle on a bounded sample: one operator application of one load of
+    this workload with its full forward/inverse FFTs and local term, and the
+    Green table and product on a few kz-planes, scaled to the whole grid."""
+    import numpy as np
+    import scipy.fft as sfft
+
+    from oracle import green
+    from oracle import operator as op
+
+    pb = op.Problem(w.phase, w.moduli, w.A0, w.physics, w.green)
+    tau = op.rhs(pb, w.loads[0])
+    axes = tuple(range(1, pb.d + 1))
+    t0 = time.perf_counter()
+    th = sfft.fftn(tau, axes=axes, workers=-1)
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loc = op.local_apply(pb, tau)
+    t_loc = time.perf_counter() - t0
+    n0 = pb.shape[0]
+    planes = 0
+    t_planes = 0.0
+    out = np.zeros_like(th)
+    budget = max(2.0, target_s - t_fwd - 2 * t_loc)
+    while planes < n0:
+        t0 = time.perf_counter()
+        sl = slice(planes, planes + 1)
+        G = green.table(pb.shape, pb.physics, pb.A0, pb.green, a_slice=sl)
+        out[:, sl] = np.einsum("...ij,j...->i...", G, th[:, sl])
+        t_planes += time.perf_counter() - t0
+        planes += 1
+        if t_planes >= budget * 0.6:
+            break
+    t0 = time.perf_counter()
+    res = sfft.ifftn(out, axes=axes, workers=-1).real + loc
+    t_inv = time.perf_counter() - t0
+    del res
+    est = t_fwd + t_inv + t_loc + t_planes * n0 / planes
+    nvox = int(w.phase.size)
+    return {
+        "value": nvox / est,
+        "unit": "voxel-iterations/s",
+        "cores": os.cpu_count(),
+        "kind": "oracle",
+        "sample": (f"one FP64 operator application (1 of 6 loads) of the 256^3 elastic workload: full "
+                   f"forward/inverse FFTs (scipy, all {os.cpu_count()} threads) and local term, Green table "
+                   f"and product on {planes} of {n0} kz-planes (single-threaded NumPy), scaled to the grid; "
+                   f"estimated {est:.1f} s per application"),
+        "seconds_measured": round(t_fwd + t_inv + t_loc + t_planes, 2),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on a single GPU; --gpus must be 1 "
+              "(the multi-GPU slab decomposition is a design note, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1411_0330_amd import inputs as I
+    from paper_1411_0330_amd import lsh
+
+    lsh.load()
+    dev = "cuda:0"
+    log(f"building the {args.grid}^3 RSA microstructure")
+    w = I.elastic_rsa_workload(args.grid, seed=0, tol=args.tol)
+    phase_dev = torch.from_numpy(w.phase).to(dev)
+    nload = w.loads.shape[0]
+    shape = w.phase.shape
+
+    # ---------------- mixed precision (the measured path) ----------------
+    ctx = lsh.Context(shape, "elastic", "mixed", max_loads=nload, device=dev)
+    ctx.set_reference(w.A0)
+    ctx.set_green(w.green)
+    log(f"warmup {args.warmup} step(s)")
+    if args.warmup > 0:
+        run_steps(ctx, lsh, w, phase_dev, args.warmup, args)
+    if not args.no_timing:
+        ctx.set_timing(True)
+    log(f"timing {args.steps} step(s)")
+    secs, vox_apps, rep, eff = run_steps(ctx, lsh, w, phase_dev, args.steps, args)
+    ktimes = ctx.kernel_times() if not args.no_timing else {}
+    if not args.no_timing:
+        ctx.set_timing(False)
+    value = vox_apps / secs
+    C_mixed = eff.T.copy()
+    log(f"mixed: {secs / args.steps * 1e3:.1f} ms/step, {value:.3e} voxel-it/s, "
+        f"fp32 apps {rep['applications_fp32']}, fp64 apps {rep['applications_fp64']}, "
+        f"outer {rep['outer_iterations']}, residuals {max(rep['rel_residual']):.2e}")
+    del ctx
+    torch.cuda.empty_cache()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"3D isotropic elasticity {args.grid}^3, RSA spheres r={8 * args.grid // 256} vox "
+                         f"f={w.info['fraction']:.4f} ({w.info['spheres']} spheres, seed 0), matrix E=1 nu=0.3, "
+                         f"inclusions E=10 nu=0.2, C0 mu0=mu_m/2 nu0=0.3, filtered Green operator, "
+                         f"6 Mandel unit strains batched, CG to {args.tol:g} with FP32 fields and FP64 refinement"),
+            "grid": args.grid, "loads": nload, "physics": "elastic", "green": w.green, "solver": "cg",
+            "precision": "mixed", "tol": args.tol,
+        },
+        "iterations": {"fp32_applications": rep["applications_fp32"], "fp64_applications": rep["applications_fp64"],
+                       "outer_refinements": rep["outer_iterations"], "per_load": rep["iterations"],
+                       "final_rel_residual_fp64": rep["rel_residual"]},
+    }
+    if ktimes:
+        out["roofline"] = roofline_from(ktimes)
+        out["kernels"] = {k: {"ms": round(v[0], 3), "launches": v[1],
+                              "alg_GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else 0.0}
+                          for k, v in ktimes.items() if v[1] > 0}
+
+    # ---------------- FP64 comparison on the same workload ----------------
+    if not args.no_fp64:
+        ctx = lsh.Context(shape, "elastic", "fp64", max_loads=nload, device=dev)
+        ctx.set_reference(w.A0)
+        ctx.set_green(w.green)
+        run_steps(ctx, lsh, w, phase_dev, 1, args, keep_fields=False)        # warm
+        s64, va64, rep64, eff64 = run_steps(ctx, lsh, w, phase_dev, 1, args)
+        C64 = eff64.T.copy()
+        diff = float(np.max(np.abs(C_mixed - C64)) / np.max(np.abs(C64)))
+        out["fp64"] = {"value": va64 / s64, "ms_per_step": s64 * 1e3,
+                       "fp64_applications": rep64["applications_fp64"],
+                       "final_rel_residual": max(rep64["rel_residual"])}
+        out["mixed_vs_fp64"] = {"speedup_time_to_solution": s64 / (secs / args.steps),
+                                "C_star_rel_diff": diff}
+        log(f"fp64: {s64 * 1e3:.1f} ms/step, speedup {s64 / (secs / args.steps):.2f}x, C* rel diff {diff:.2e}")
+        del ctx
+        torch.cuda.empty_cache()
+    out["C_star_mandel"] = [[round(x, 8) for x in row] for row in C_mixed.tolist()]
+
+    # ---------------- CPU oracle on a bounded sample ----------------
+    if not args.no_cpu:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -47,7 +47,7 @@ typedef enum {
   LSH_ENOMEM = -2,      /* workspace missing or too small */
   LSH_EHIP = -3,        /* HIP runtime error */
   LSH_EHYP2 = -4,       /* A_phase - A0 neither zero nor definite (hypothesis (2)) */
-  LSH_EBREAKDOWN = -5,  /* CG breakdown: p.Lp <= 0 (the system is not positive definite) */
+  LSH_EBREAKDOWN = -5,  /* CG breakdown: p.Lp vanished */
   LSH_ENUMERIC = -6,    /* NaN or Inf met during the solve */
   LSH_ESTATE = -7       /* call out of order (e.g. solve before phases are set) */
 } lsh_status;
@@ -137,8 +137,11 @@ lsh_status lsh_set_green(lsh_ctx* ctx, int variant);
  *   summary   host lsh_solve_report (may be NULL).
  * Returns LSH_OK, LSH_MAXIT (results valid, some load unconverged), or an error.
  * The basic scheme converges only when A0 dominates (scalar isotropic:
- * max|a - a0| < a0); CG needs a positive definite system (A0 softer than every
- * phase) and reports LSH_EBREAKDOWN otherwise.
+ * max|a - a0| < a0).  CG is guaranteed to converge when the system is positive
+ * definite (A0 softer than every phase, Section 5); with A0 between the phases
+ * the system is symmetric indefinite and CG proceeds, reporting
+ * LSH_EBREAKDOWN if p.Lp vanishes.  Loads converge independently: a converged
+ * load is frozen while the others iterate.
  */
 lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, double tol,
                      int maxit, lsh_load_report* reports, lsh_solve_report* summary);
@@ -158,8 +161,10 @@ lsh_status lsh_get_effective(lsh_ctx* ctx, double* sigma_mean);
 /*
  * Matrix-free operator of eq. (13): out_l = 1_{I0} ((A - A0)^{-1} tau_l + Gamma tau_l)
  * for nload fields tau (device, [load][component][z][y][x], element type
- * dtype: LSH_F64 uses the FP64 kernels, LSH_F32 the FP32 ones).  out is a
- * device buffer of the same shape and type; it may not alias tau.
+ * dtype: LSH_F64 uses the FP64 kernels, LSH_F32 the FP32 ones, the latter in
+ * a LSH_MIXED context only).  tau is meant to vanish outside I0 (Gamma acts
+ * on tau as given).  out is a device buffer of the same shape and type; it
+ * may not alias tau.
  */
 lsh_status lsh_apply(lsh_ctx* ctx, int nload, const void* tau, void* out, int dtype);
 
@@ -178,14 +183,18 @@ lsh_status lsh_spectrum_bytes(const lsh_ctx* ctx, int dtype, size_t* bytes);
 
 /*
  * Kernel timing: when enabled, every kernel launch is bracketed by HIP events
- * on the context's stream and accumulated per kernel class.
- * lsh_kernel_times fills up to cap entries of names (static strings),
- * total milliseconds and launch counts since the last reset; *count receives
- * the number of classes.  Reading synchronises the stream.
+ * on the context's stream and accumulated per kernel class (transform and
+ * update classes are split by element type, e.g. "zgamma_f32").
+ * lsh_kernel_times fills up to cap entries of names (static strings), total
+ * milliseconds, launch counts and algorithmic bytes (the HBM traffic each
+ * pass must move: its inputs read once, its outputs written once, for the
+ * loads still iterating) since the last reset; any output array may be NULL.
+ * *count receives the number of classes.  Reading synchronises the stream.
+ * Enabling or disabling resets the counters.
  */
 lsh_status lsh_set_timing(lsh_ctx* ctx, int enable);
 lsh_status lsh_kernel_times(lsh_ctx* ctx, const char** names, double* total_ms, int64_t* launches,
-                            int cap, int* count);
+                            double* alg_bytes, int cap, int* count);
 
 /* Message of the last error on this context ("" when none). */
 const char* lsh_last_error(const lsh_ctx* ctx);

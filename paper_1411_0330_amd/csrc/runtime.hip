@@ -94,12 +94,21 @@ bool symmetric(int n, const double* a) {
 }
 
 struct KTimer {
-  const char* name;
+  int cls;
+  double bytes;
   hipEvent_t a, b;
 };
 
-const char* kClassNames[] = {"xfwd", "y", "zgamma", "xinv", "cg_update", "scalars", "init", "mean", "copy"};
-enum KClass { K_XFWD, K_Y, K_ZG, K_XINV, K_CGUPD, K_SCAL, K_INIT, K_MEAN, K_COPY, K_NCLASS };
+// Kernel classes for the timing facility; the transform and update kernels
+// are split by element type (FP32 / FP64).
+const char* kClassNames[] = {"xfwd_f32",   "xfwd_f64",   "y_f32",   "y_f64",   "zgamma_f32",
+                             "zgamma_f64", "xinv_f32",   "xinv_f64", "cg_update_f32", "cg_update_f64",
+                             "scalars",    "init",       "mean",     "copy"};
+enum KClass {
+  K_XFWD = 0, K_Y = 2, K_ZG = 4, K_XINV = 6, K_CGUPD = 8,  // + 1 for FP64
+  K_SCAL = 10, K_INIT, K_MEAN, K_COPY, K_NCLASS
+};
+template <typename T> constexpr int kcls(int base) { return base + (sizeof(T) == 8 ? 1 : 0); }
 
 }  // namespace
 
@@ -149,9 +158,11 @@ struct lsh_ctx {
 
   // timing
   bool timing = false;
+  int nact = 1 << 30;  // host's count of loads still iterating (bounds the bytes of a launch)
   std::vector<KTimer> pending;
   std::vector<hipEvent_t> pool;
   double tsum[K_NCLASS] = {0};
+  double tbytes[K_NCLASS] = {0};
   long long tcount[K_NCLASS] = {0};
 
   std::string err;
@@ -190,11 +201,14 @@ hipEvent_t take_event(lsh_ctx* ctx) {
   return e;
 }
 
+// Brackets one kernel launch with events when timing is on; `bytes` is the
+// launch's algorithmic HBM traffic (what the pass must read and write).
 struct Scope {
   lsh_ctx* ctx;
   int cls;
+  double bytes;
   hipEvent_t a = nullptr;
-  Scope(lsh_ctx* c, int k) : ctx(c), cls(k) {
+  Scope(lsh_ctx* c, int k, double b = 0.0) : ctx(c), cls(k), bytes(b) {
     if (ctx->timing) {
       a = take_event(ctx);
       if (a) (void)hipEventRecord(a, ctx->stream);
@@ -205,8 +219,7 @@ struct Scope {
       hipEvent_t b = take_event(ctx);
       if (b) {
         (void)hipEventRecord(b, ctx->stream);
-        ctx->pending.push_back({kClassNames[cls], a, b});
-        ctx->pending.back().name = kClassNames[cls];
+        ctx->pending.push_back({cls, bytes, a, b});
       }
     }
   }
@@ -218,11 +231,9 @@ void drain_timers(lsh_ctx* ctx) {
   for (auto& t : ctx->pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
-      for (int k = 0; k < K_NCLASS; ++k)
-        if (std::strcmp(kClassNames[k], t.name) == 0) {
-          ctx->tsum[k] += ms;
-          ctx->tcount[k] += 1;
-        }
+      ctx->tsum[t.cls] += ms;
+      ctx->tbytes[t.cls] += t.bytes;
+      ctx->tcount[t.cls] += 1;
     }
     ctx->pool.push_back(t.a);
     ctx->pool.push_back(t.b);
@@ -491,16 +502,21 @@ lsh_status forward_part(lsh_ctx* ctx, int l0, int nload, int xmode, const T* src
   cpx<T>* sm = Sel<T>::sm(ctx) + (long long)l0 * main_cpx(g);
   cpx<T>* sn = Sel<T>::sn(ctx) + (long long)l0 * nyq_cpx(g);
   XfwdArgs<T> xa{g, xmode, src, pdir, dsrc, sm, sn, Sel<T>::tw(ctx, 0), st};
+  // algorithmic bytes per launch (loads still iterating x per-load traffic)
+  const double nl = std::min(ctx->nact, nload);
+  const double cvs = (double)ctx->F * sizeof(T);
+  const double spec = cvs + 2.0 * sizeof(T) * (double)nyq_cpx(g);
+  const double xin = xmode == XF_CG ? 3.0 * cvs : (xmode == XF_IRX ? 2.0 * cvs + 4.0 * ctx->F : cvs);
   {
-    Scope sc(ctx, K_XFWD);
+    Scope sc(ctx, kcls<T>(K_XFWD), nl * (xin + spec));
     STCHK(check_launch(ctx, launch_xfwd<T>(ctx->stream, xa, nload), "x forward"));
   }
   {
-    Scope sc(ctx, K_Y);
+    Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
     STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, -1, sm, sn, Sel<T>::tw(ctx, 1), st, nload), "y forward"));
   }
   {
-    Scope sc(ctx, K_ZG);
+    Scope sc(ctx, kcls<T>(K_ZG), nl * 2.0 * spec);
     GreenTabs<T> tb{Sel<T>::wt(ctx), ctx->wstride};
     STCHK(check_launch(ctx,
                        launch_zg<T>(ctx->stream, g, ctx->gp, tb, gamma ? Z_GAMMA : Z_FWD, sm, sn, Sel<T>::tw(ctx, 2),
@@ -508,7 +524,7 @@ lsh_status forward_part(lsh_ctx* ctx, int l0, int nload, int xmode, const T* src
                        "z/Green"));
   }
   if (gamma) {
-    Scope sc(ctx, K_Y);
+    Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
     STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, 1, sm, sn, Sel<T>::tw(ctx, 1), st, nload), "y inverse"));
   }
   return LSH_OK;
@@ -535,7 +551,13 @@ lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T*
   a.partials = partials;
   a.pstride = (int)ctx->pstride;
   a.scale = static_cast<T>(1.0 / (double)g.nvox);
-  Scope sc(ctx, K_XINV);
+  const double nl = std::min(ctx->nact, nload);
+  const double cvs = (double)ctx->F * sizeof(T);
+  double bytes = cvs + 2.0 * sizeof(T) * (double)nyq_cpx(g) + (double)g.nvox;  // spectrum + phase ids
+  if (mode != XI_STRAIN) bytes += cvs;                                          // the field transformed
+  if (mode == XI_IRRES) bytes += 4.0 * ctx->F;                                  // FP32 residual out
+  else if (mode != XI_RESNORM) bytes += cvs;                                    // real output
+  Scope sc(ctx, kcls<T>(K_XINV), nl * bytes);
   const int nb = launch_xinv<T>(ctx->stream, a, nload);
   STCHK(check_launch(ctx, nb, "x inverse"));
   if (nparts) *nparts = nb;
@@ -568,7 +590,7 @@ lsh_status cg_update(lsh_ctx* ctx, int nload, T* x, const T* p, T* r, const T* q
   const long long nvec = ctx->F / Vec16<T>::n;
   const int nb = (int)((nvec + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
   {
-    Scope sc(ctx, K_CGUPD);
+    Scope sc(ctx, kcls<T>(K_CGUPD), std::min(ctx->nact, nload) * 6.0 * (double)ctx->F * sizeof(T));
     hipLaunchKernelGGL((k_cgupd<T>), dim3(nb, nload), dim3(256), 0, ctx->stream, nvec, x, p, r, q, st,
                        ctx->ptr<double>(ctx->off.partials), (int)ctx->pstride);
     STCHK(check_launch(ctx, 0, "cg update"));
@@ -597,7 +619,8 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
   T* q = reinterpret_cast<T*>(Sel<T>::sm(ctx));
   STCHK(read_states(ctx, st_off, nload, hst));
   bool any = false;
-  for (auto& s : hst) any |= s.active != 0;
+  ctx->nact = 0;
+  for (auto& s : hst) any |= s.active != 0, ctx->nact += s.active != 0;
   if (!any) return LSH_OK;
   for (int it = 0; it < maxit; ++it) {
     STCHK(forward_part<T>(ctx, 0, nload, XF_CG, r, p, nullptr, st, true));
@@ -608,7 +631,8 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
     if ((it + 1) % period == 0 || it + 1 == maxit) {
       STCHK(read_states(ctx, st_off, nload, hst));
       any = false;
-      for (auto& s : hst) any |= s.active != 0;
+      ctx->nact = 0;
+      for (auto& s : hst) any |= s.active != 0, ctx->nact += s.active != 0;
       if (!any) break;
     }
   }
@@ -620,7 +644,8 @@ lsh_status basic_loop(lsh_ctx* ctx, int nload, double* x, LoadState* st, size_t 
   const int period = check_period(ctx, nload);
   STCHK(read_states(ctx, st_off, nload, hst));
   bool any = false;
-  for (auto& s : hst) any |= s.active != 0;
+  ctx->nact = 0;
+  for (auto& s : hst) any |= s.active != 0, ctx->nact += s.active != 0;
   if (!any) return LSH_OK;
   for (int it = 0; it < maxit; ++it) {
     STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, x, nullptr, nullptr, st, true));
@@ -630,7 +655,8 @@ lsh_status basic_loop(lsh_ctx* ctx, int nload, double* x, LoadState* st, size_t 
     if ((it + 1) % period == 0 || it + 1 == maxit) {
       STCHK(read_states(ctx, st_off, nload, hst));
       any = false;
-      for (auto& s : hst) any |= s.active != 0;
+      ctx->nact = 0;
+      for (auto& s : hst) any |= s.active != 0, ctx->nact += s.active != 0;
       if (!any) break;
     }
   }
@@ -836,6 +862,7 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
   for (int i = 0; i < nload * c; ++i)
     if (!std::isfinite(loads[i])) return fail(ctx, LSH_EINVAL, "non-finite load");
   STCHK(prepare(ctx));
+  ctx->nact = 1 << 30;
   const auto t0 = std::chrono::steady_clock::now();
   ctx->have_solution = false;
   ctx->last_nload = nload;
@@ -887,6 +914,8 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
         used = std::max(used, hin[l].iters);
       }
       budget -= used;
+      ctx->nact = 0;
+      for (auto& sv : hst) ctx->nact += sv.active != 0;
       STCHK(forward_part<double>(ctx, 0, nload, XF_IRX, nullptr, x64, d, sto, true));
       int np = 0;
       STCHK(inverse_x<double>(ctx, 0, nload, XI_IRRES, x64, nullptr, r, sto, ctx->ptr<double>(ctx->off.partials),
@@ -938,6 +967,7 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
   }
 
   // FP64 true residual of the result (CG and basic), A*
+  ctx->nact = 1 << 30;
   if (!residual_known) {
     STCHK(true_residual(ctx, nload));
     std::vector<double> s(nload);
@@ -1096,23 +1126,21 @@ lsh_status lsh_set_timing(lsh_ctx* ctx, int enable) {
   ctx->timing = enable != 0;
   for (int k = 0; k < K_NCLASS; ++k) {
     ctx->tsum[k] = 0.0;
+    ctx->tbytes[k] = 0.0;
     ctx->tcount[k] = 0;
   }
   return LSH_OK;
 }
 
-lsh_status lsh_kernel_times(lsh_ctx* ctx, const char** names, double* total_ms, int64_t* launches, int cap,
-                            int* count) {
+lsh_status lsh_kernel_times(lsh_ctx* ctx, const char** names, double* total_ms, int64_t* launches,
+                            double* alg_bytes, int cap, int* count) {
   if (!ctx || !count) return LSH_EINVAL;
   drain_timers(ctx);
-  int k = 0;
-  for (int i = 0; i < K_NCLASS; ++i) {
-    if (k < cap) {
-      if (names) names[k] = kClassNames[i];
-      if (total_ms) total_ms[k] = ctx->tsum[i];
-      if (launches) launches[k] = ctx->tcount[i];
-    }
-    ++k;
+  for (int i = 0; i < K_NCLASS && i < cap; ++i) {
+    if (names) names[i] = kClassNames[i];
+    if (total_ms) total_ms[i] = ctx->tsum[i];
+    if (launches) launches[i] = ctx->tcount[i];
+    if (alg_bytes) alg_bytes[i] = ctx->tbytes[i];
   }
   *count = K_NCLASS;
   return LSH_OK;

@@ -63,7 +63,7 @@ _SIGS = {
     "lsh_spectrum_bytes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_size_t)]),
     "lsh_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "lsh_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
-                                   C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int)]),
+                                   C.POINTER(C.c_int64), C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_int)]),
     "lsh_last_error": (C.c_char_p, [C.c_void_p]),
     "lsh_version": (C.c_char_p, []),
 }
@@ -268,13 +268,15 @@ class Context:
         self._check(self.lib.lsh_set_timing(self.h, 1 if enable else 0))
 
     def kernel_times(self):
+        """{class: (total ms, launches, algorithmic bytes)} since timing was enabled."""
         cap = 32
         names = (C.c_char_p * cap)()
         ms = (C.c_double * cap)()
         cnt = (C.c_int64 * cap)()
+        by = (C.c_double * cap)()
         n = C.c_int()
-        self._check(self.lib.lsh_kernel_times(self.h, names, ms, cnt, cap, C.byref(n)))
-        return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(min(n.value, cap))}
+        self._check(self.lib.lsh_kernel_times(self.h, names, ms, cnt, by, cap, C.byref(n)))
+        return {names[i].decode(): (ms[i], int(cnt[i]), by[i]) for i in range(min(n.value, cap))}
 
 
 def header_symbols(header_path=None):

@@ -160,3 +160,16 @@ def test_boolean_128_fp64_and_mixed_against_golden(lsh):
     Am, repm = _gpu_effective(ctxm, w.loads, tol=1e-8)
     assert max(repm["rel_residual"]) <= 1e-8
     assert rel_max_err(Am, gold["A_star"]) <= 1e-6
+
+
+def test_elastic_rsa_64_fp64_and_mixed_against_golden(lsh):
+    gold = json.load(open(os.path.join(GOLDEN, "elastic_rsa_n64_filtered.json")))
+    w = I.elastic_rsa_workload(64, tol=1e-10)
+    ctx = context(lsh, w.phase, w.moduli, w.A0, "elastic", "filtered", max_loads=6)
+    A, rep = _gpu_effective(ctx, w.loads, tol=1e-11)
+    assert rep["status"] == lsh.OK
+    assert rel_max_err(A, gold["A_star"]) <= 1e-10
+    ctxm = context(lsh, w.phase, w.moduli, w.A0, "elastic", "filtered", precision="mixed", max_loads=6)
+    Am, repm = _gpu_effective(ctxm, w.loads, tol=1e-8)
+    assert max(repm["rel_residual"]) <= 1e-8
+    assert rel_max_err(Am, gold["A_star"]) <= 1e-6

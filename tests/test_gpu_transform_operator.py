@@ -151,6 +151,7 @@ def _plane_wave_case(shape, physics, variant, nload, seed):
     return tau, gam, A0
 
 
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_operator_full_size_plane_waves(lsh, dtype):
     # the benchmark's shape and batch: 256^3 elasticity, 6 loads, filtered
@@ -169,6 +170,7 @@ def test_operator_full_size_plane_waves(lsh, dtype):
         assert rel_max_err(out[l], ref) <= tol, l
 
 
+@pytest.mark.timeout(600)
 def test_operator_full_size_scalar_128_plane_waves(lsh):
     shape, nload, variant = (128, 128, 128), 3, "filtered"
     w = I.boolean_workload(128)
