@@ -19,7 +19,8 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // points per thread
 template <typename T> constexpr int p_xfwd(int mx) { return cmin(8, mx); }
 template <typename T, int C> constexpr int p_xinv(int mx) {
-  return cmin((C == 6 && sizeof(T) == 8) ? 4 : 8, mx);
+  // six components: fewer points per thread keep the register file for occupancy
+  return cmin(C == 6 ? (sizeof(T) == 8 ? 2 : 4) : 8, mx);
 }
 template <typename T> constexpr int p_y(int n) { return cmin(sizeof(T) == 4 ? 16 : 8, n); }
 template <typename T, int C> constexpr int p_z(int n) {
@@ -43,6 +44,7 @@ struct XfwdArgs {
   int mode;
   const T* src;
   T* pdir;
+  T* xacc;
   const float* dsrc;
   cpx<T>* smain;
   cpx<T>* snyq;
@@ -50,13 +52,38 @@ struct XfwdArgs {
   const LoadState* st;
 };
 
-template <typename T> int launch_xfwd(hipStream_t s, const XfwdArgs<T>& a, int nload);
+// Kernel-shape variants of each pass (0 = the default shape).  For the axis
+// lengths 128 and 256 every pass is compiled in kVariants shapes:
+//   strided passes (y, zg): 1 = half the pencils per workgroup,
+//                           2 = half the points per thread, 3 = both;
+//   row passes (xfwd, xinv): 1 = half the points per thread, 2 = twice,
+//                            3 = a quarter.
+// Shapes that break a limit (threads, LDS, points) fall back to the default.
+constexpr int kVariants = 4;
+enum : int { PASS_XFWD = 0, PASS_Y = 1, PASS_ZG = 2, PASS_XINV = 3, NPASS = 4 };
+
+template <typename T> int launch_xfwd(hipStream_t s, const XfwdArgs<T>& a, int nload, int variant = 0);
 template <typename T> int launch_y(hipStream_t s, const Geo& g, int dir, cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw,
-                                   const LoadState* st, int nload);
+                                   const LoadState* st, int nload, int variant = 0);
 template <typename T> int launch_zg(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb,
                                     int zmode, cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw, const LoadState* st,
-                                    int nload);
-template <typename T> int launch_xinv(hipStream_t s, const XinvArgs<T>& a, int nload);
+                                    int nload, int variant = 0);
+template <typename T> int launch_xinv(hipStream_t s, const XinvArgs<T>& a, int nload, int variant = 0);
+
+// strided-pass shape of a variant: (pencils per workgroup, points per thread)
+template <typename T> constexpr int sv_tx(int n, int p0, int v) {
+  const int tx0 = tx_strided<T>(n, p0);
+  return (v == 1 || v == 3) ? (tx0 / 2 >= 2 ? tx0 / 2 : tx0) : tx0;
+}
+constexpr int sv_p(int p0, int v) { return (v == 2 || v == 3) ? (p0 / 2 >= 2 ? p0 / 2 : p0) : p0; }
+template <typename T> constexpr bool sv_ok(int n, int tx, int p) {
+  return p >= 1 && p <= n && tx >= 1 && tx * (n / p) <= 1024 && (long)tx * n * 2 * (int)sizeof(T) <= 65536;
+}
+// row-pass points per thread of a variant
+constexpr int rv_p(int mx, int p0, int v) {
+  const int p = v == 1 ? p0 / 2 : (v == 2 ? p0 * 2 : (v == 3 ? p0 / 4 : p0));
+  return (p >= 2 && p <= mx && p <= 16 && mx / p <= 256) ? p : p0;
+}
 
 // number of workgroups per load of the reducing passes (partials sizing)
 inline long long xinv_blocks(const Geo& g, int p) {

@@ -40,6 +40,10 @@ struct GreenTabs {
   int wstride;
 };
 
+// reciprocal: the FP32 path uses the hardware reciprocal (1 ulp), FP64 divides
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // ----------------------------------------------------------------------------
 // scalar conduction, D = 2 or 3 components, general symmetric A0
 // ----------------------------------------------------------------------------
@@ -126,7 +130,7 @@ __device__ __forceinline__ void green_scalar(const GreenParams& gp, const GreenT
 #pragma unroll
       for (int j = 0; j < D; ++j) den += xi[i] * A[i][j] * xi[j];
     if (w != T(0) && den > T(0)) {
-      const T f = w / den;
+      const T f = w * recip(den);
 #pragma unroll
       for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -167,19 +171,22 @@ __device__ __forceinline__ void bd_zero(BD<T>& s) {
 // accumulate weight w along frequency xi (any length; normalised here)
 template <typename T>
 __device__ __forceinline__ void bd_add(BD<T>& s, T w, T a, T b, T c) {
-  const T n2 = a * a + b * b + c * c;
-  if (!(n2 > T(0)) || w == T(0)) return;
-  const T q = w / n2;      // w / |xi|^2
-  const T u = q / n2;      // w / |xi|^4
-  s.b11 += q * a * a; s.b22 += q * b * b; s.b33 += q * c * c;
-  s.b23 += q * b * c; s.b13 += q * a * c; s.b12 += q * a * b;
   const T aa = a * a, bb = b * b, cc = c * c;
-  s.d1111 += u * aa * aa; s.d2222 += u * bb * bb; s.d3333 += u * cc * cc;
-  s.d1122 += u * aa * bb; s.d1133 += u * aa * cc; s.d2233 += u * bb * cc;
-  s.d1112 += u * aa * a * b; s.d1113 += u * aa * a * c;
-  s.d2221 += u * bb * b * a; s.d2223 += u * bb * b * c;
-  s.d3331 += u * cc * c * a; s.d3332 += u * cc * c * b;
-  s.d1123 += u * aa * b * c; s.d2213 += u * bb * a * c; s.d3312 += u * cc * a * b;
+  const T n2 = aa + bb + cc;
+  if (!(n2 > T(0)) || w == T(0)) return;
+  const T inv = recip(n2);
+  const T q = w * inv;      // w / |xi|^2
+  const T u = q * inv;      // w / |xi|^4
+  const T ab = a * b, ac = a * c, bc = b * c;
+  s.b11 += q * aa; s.b22 += q * bb; s.b33 += q * cc;
+  s.b23 += q * bc; s.b13 += q * ac; s.b12 += q * ab;
+  const T ua = u * aa, ub = u * bb, uc = u * cc;
+  s.d1111 += ua * aa; s.d2222 += ub * bb; s.d3333 += uc * cc;
+  s.d1122 += ua * bb; s.d1133 += ua * cc; s.d2233 += ub * cc;
+  s.d1112 += ua * ab; s.d1113 += ua * ac;
+  s.d2221 += ub * ab; s.d2223 += ub * bc;
+  s.d3331 += uc * ac; s.d3332 += uc * bc;
+  s.d1123 += ua * bc; s.d2213 += ub * ac; s.d3312 += uc * ab;
 }
 
 // out = (B t + t B)/(2 mu0) - kappa D:t on one real symmetric tensor (Mandel in/out)
@@ -246,19 +253,18 @@ __device__ __forceinline__ void green_elastic(const GreenParams& gp, const Green
     bd_add(s, T(1), xi[0], xi[1], xi[2]);
   } else {
     cpx<T> wa[3];
+    T x0[3], x1[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) wa[a] = tb.w[a * tb.wstride + k[a]];
+    for (int a = 0; a < 3; ++a) {
+      wa[a] = tb.w[a * tb.wstride + k[a]];
+      x0[a] = static_cast<T>(k[a]);
+      x1[a] = static_cast<T>(k[a] - gp.n[a]);
+    }
+    const T wxy[4] = {wa[0].x * wa[1].x, wa[0].y * wa[1].x, wa[0].x * wa[1].y, wa[0].y * wa[1].y};
 #pragma unroll
     for (int alias = 0; alias < 8; ++alias) {
-      T w = 1;
-      T xi[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const bool lo = (alias >> a) & 1;
-        w *= lo ? wa[a].y : wa[a].x;
-        xi[a] = static_cast<T>(lo ? k[a] - gp.n[a] : k[a]);
-      }
-      bd_add(s, w, xi[0], xi[1], xi[2]);
+      const T w = wxy[alias & 3] * ((alias & 4) ? wa[2].y : wa[2].x);
+      bd_add(s, w, (alias & 1) ? x1[0] : x0[0], (alias & 2) ? x1[1] : x0[1], (alias & 4) ? x1[2] : x0[2]);
     }
   }
   T re[6], im[6], ore[6], oim[6];

@@ -3,64 +3,90 @@
 
 namespace lsh {
 
-template <typename T, int MX>
-static int xfwd_one(hipStream_t s, const XfwdArgs<T>& a, int nload) {
-  constexpr int P = p_xfwd<T>(MX);
+template <typename T, int MX, int P>
+static int xfwd_inst(hipStream_t s, const XfwdArgs<T>& a, int nload) {
   constexpr int TR = MX / P;
   constexpr int RPW = 256 / TR;
   const long long rows = (long long)a.g.c * a.g.nz * a.g.ny;
   const int nb = (int)((rows + RPW - 1) / RPW);
-  hipLaunchKernelGGL((k_xfwd<T, MX, P>), dim3(nb, nload), dim3(256), 0, s, a.g, a.mode, a.src, a.pdir, a.dsrc,
-                     a.smain, a.snyq, a.twx, a.st);
+  hipLaunchKernelGGL((k_xfwd<T, MX, P>), dim3(nb, nload), dim3(256), 0, s, a.g, a.mode, a.src, a.pdir, a.xacc,
+                     a.dsrc, a.smain, a.snyq, a.twx, a.st);
   return nb;
 }
 
+template <typename T, int MX>
+static int xfwd_one(hipStream_t s, const XfwdArgs<T>& a, int nload, int v = 0) {
+  constexpr int P0 = p_xfwd<T>(MX);
+  if constexpr (MX == 64 || MX == 128) {
+    switch (v) {
+      case 1: return xfwd_inst<T, MX, rv_p(MX, P0, 1)>(s, a, nload);
+      case 2: return xfwd_inst<T, MX, rv_p(MX, P0, 2)>(s, a, nload);
+      case 3: return xfwd_inst<T, MX, rv_p(MX, P0, 3)>(s, a, nload);
+      default: break;
+    }
+  }
+  return xfwd_inst<T, MX, P0>(s, a, nload);
+}
+
 template <typename T>
-int launch_xfwd(hipStream_t s, const XfwdArgs<T>& a, int nload) {
+int launch_xfwd(hipStream_t s, const XfwdArgs<T>& a, int nload, int v) {
   switch (a.g.mx) {
     case 2: return xfwd_one<T, 2>(s, a, nload);
     case 4: return xfwd_one<T, 4>(s, a, nload);
     case 8: return xfwd_one<T, 8>(s, a, nload);
     case 16: return xfwd_one<T, 16>(s, a, nload);
     case 32: return xfwd_one<T, 32>(s, a, nload);
-    case 64: return xfwd_one<T, 64>(s, a, nload);
-    case 128: return xfwd_one<T, 128>(s, a, nload);
+    case 64: return xfwd_one<T, 64>(s, a, nload, v);
+    case 128: return xfwd_one<T, 128>(s, a, nload, v);
     case 256: return xfwd_one<T, 256>(s, a, nload);
     case 512: return xfwd_one<T, 512>(s, a, nload);
     default: return -1;
   }
 }
 
-template <typename T, int MX, int C>
-static int xinv_one(hipStream_t s, const XinvArgs<T>& a, int nload) {
-  constexpr int P = p_xinv<T, C>(MX);
+template <typename T, int MX, int C, int P>
+static int xinv_inst(hipStream_t s, const XinvArgs<T>& a, int nload) {
   const int nb = (int)xinv_blocks(a.g, P);
   hipLaunchKernelGGL((k_xinv<T, MX, P, C>), dim3(nb, nload), dim3(256), 0, s, a);
   return nb;
 }
 
+template <typename T, int MX, int C>
+static int xinv_one(hipStream_t s, const XinvArgs<T>& a, int nload, int v) {
+  constexpr int P0 = p_xinv<T, C>(MX);
+  if constexpr (MX == 64 || MX == 128) {
+    switch (v) {
+      case 1: return xinv_inst<T, MX, C, rv_p(MX, P0, 1)>(s, a, nload);
+      case 2: return xinv_inst<T, MX, C, rv_p(MX, P0, 2)>(s, a, nload);
+      case 3: return xinv_inst<T, MX, C, rv_p(MX, P0, 3)>(s, a, nload);
+      default: break;
+    }
+  }
+  return xinv_inst<T, MX, C, P0>(s, a, nload);
+}
+
 template <typename T, int MX>
-static int xinv_c(hipStream_t s, const XinvArgs<T>& a, int nload) {
+static int xinv_c(hipStream_t s, const XinvArgs<T>& a, int nload, int v) {
   switch (a.g.c) {
-    case 2: return xinv_one<T, MX, 2>(s, a, nload);
-    case 3: return xinv_one<T, MX, 3>(s, a, nload);
-    case 6: return xinv_one<T, MX, 6>(s, a, nload);
+    case 2: return xinv_one<T, MX, 2>(s, a, nload, v);
+    case 3: return xinv_one<T, MX, 3>(s, a, nload, v);
+    case 6: return xinv_one<T, MX, 6>(s, a, nload, v);
     default: return -1;
   }
 }
 
 template <typename T>
-int launch_xinv(hipStream_t s, const XinvArgs<T>& a, int nload) {
+int launch_xinv(hipStream_t s, const XinvArgs<T>& a, int nload, int v) {
   switch (a.g.mx) {
-    case 2: return xinv_c<T, 2>(s, a, nload);
-    case 4: return xinv_c<T, 4>(s, a, nload);
-    case 8: return xinv_c<T, 8>(s, a, nload);
-    case 16: return xinv_c<T, 16>(s, a, nload);
-    case 32: return xinv_c<T, 32>(s, a, nload);
-    case 64: return xinv_c<T, 64>(s, a, nload);
-    case 128: return xinv_c<T, 128>(s, a, nload);
-    case 256: return xinv_c<T, 256>(s, a, nload);
-    case 512: return xinv_c<T, 512>(s, a, nload);
+    case 2: return xinv_c<T, 2>(s, a, nload, v);
+    case 4: return xinv_c<T, 4>(s, a, nload, v);
+    case 8: return xinv_c<T, 8>(s, a, nload, v);
+    case 16: return xinv_c<T, 16>(s, a, nload, v);
+    case 32: return xinv_c<T, 32>(s, a, nload, v);
+    case 64: return xinv_c<T, 64>(s, a, nload, v);
+    case 128: return xinv_c<T, 128>(s, a, nload, v);
+    case 256: return xinv_c<T, 256>(s, a, nload, v);
+    case 512: return xinv_c<T, 512>(s, a, nload, v);
     default: return -1;
   }
 }
@@ -68,7 +94,7 @@ int launch_xinv(hipStream_t s, const XinvArgs<T>& a, int nload) {
 #ifndef LSH_X_TYPE
 #error "define LSH_X_TYPE"
 #endif
-template int launch_xfwd<LSH_X_TYPE>(hipStream_t, const XfwdArgs<LSH_X_TYPE>&, int);
-template int launch_xinv<LSH_X_TYPE>(hipStream_t, const XinvArgs<LSH_X_TYPE>&, int);
+template int launch_xfwd<LSH_X_TYPE>(hipStream_t, const XfwdArgs<LSH_X_TYPE>&, int, int);
+template int launch_xinv<LSH_X_TYPE>(hipStream_t, const XinvArgs<LSH_X_TYPE>&, int, int);
 
 }  // namespace lsh

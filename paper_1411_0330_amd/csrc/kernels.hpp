@@ -9,7 +9,8 @@
 //
 // One application of eq. (13) is five passes:
 //   xfwd  real rows -> half spectrum (R2C through an nx/2-point complex FFT),
-//         optionally fused with the CG direction update p = r + beta p;
+//         optionally fused with the CG updates x += alpha p (of the previous
+//         step) and p = r + beta p;
 //   y     strided y-pencils (and contiguous rows of the Nyquist plane);
 //   zg    strided z-pencils: forward z FFT, Gamma_hat on the c components of
 //         every wave-vector, inverse z FFT (the Nyquist plane too);
@@ -35,6 +36,8 @@ struct LoadState {
   int iters;     // operator applications spent
   int status;    // lsh_status of the load
   int first;     // next CG direction is p = r
+  int pending;   // x += alpha p of the last CG step is still to be applied
+  int pad;
 };
 
 struct Geo {
@@ -78,9 +81,10 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // ----------------------------------------------------------------------------
 template <typename T, int MX, int P>
 __global__ __launch_bounds__(256) void k_xfwd(const Geo g, const int mode, const T* __restrict__ src,
-                                              T* __restrict__ pdir, const float* __restrict__ dsrc,
-                                              cpx<T>* __restrict__ smain, cpx<T>* __restrict__ snyq,
-                                              const cpx<T>* __restrict__ twx, const LoadState* __restrict__ st) {
+                                              T* __restrict__ pdir, T* __restrict__ xacc,
+                                              const float* __restrict__ dsrc, cpx<T>* __restrict__ smain,
+                                              cpx<T>* __restrict__ snyq, const cpx<T>* __restrict__ twx,
+                                              const LoadState* __restrict__ st) {
   constexpr int TR = MX / P;
   constexpr int RPW = 256 / TR;
   __shared__ cpx<T> lds[RPW * MX];
@@ -95,10 +99,14 @@ __global__ __launch_bounds__(256) void k_xfwd(const Geo g, const int mode, const
 
   cpx<T> v[P];
   if (mode == XF_CG) {
+    // x += alpha p (the previous step, when pending), then p = r + beta p
     const cpx<T>* r2 = reinterpret_cast<const cpx<T>*>(src + roff);
     cpx<T>* p2 = reinterpret_cast<cpx<T>*>(pdir + roff);
+    cpx<T>* x2 = reinterpret_cast<cpx<T>*>(xacc + roff);
     const bool first = st[l].first != 0;
+    const bool pend = st[l].pending != 0;
     const T beta = static_cast<T>(st[l].beta);
+    const T alpha = static_cast<T>(st[l].alpha);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const int n = t + TR * i;
@@ -109,6 +117,10 @@ __global__ __launch_bounds__(256) void k_xfwd(const Geo g, const int mode, const
           pv = rv;
         } else {
           const cpx<T> po = p2[n];
+          if (pend) {
+            const cpx<T> xo = x2[n];
+            x2[n] = cpx<T>{xo.x + alpha * po.x, xo.y + alpha * po.y};
+          }
           pv = cpx<T>{rv.x + beta * po.x, rv.y + beta * po.y};
         }
         p2[n] = pv;
@@ -249,14 +261,15 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
   }
   cpx<T>* lp = lds + xl;
 
+  // all components' loads are issued before the first transform
   cpx<T> v[C][P];
 #pragma unroll
-  for (int j = 0; j < C; ++j) {
+  for (int j = 0; j < C; ++j)
 #pragma unroll
     for (int i = 0; i < P; ++i)
       v[j][i] = valid ? base[j * cstride + (long long)(t + TZ * i) * es_g] : cpx<T>{0, 0};
-    fft_pencil<NZ, P, -1, T>(v[j], t, lp, TX, twz, 1);
-  }
+#pragma unroll
+  for (int j = 0; j < C; ++j) fft_pencil<NZ, P, -1, T>(v[j], t, lp, TX, twz, 1);
   if (zmode == Z_GAMMA) {
     if (valid) {
 #pragma unroll
@@ -289,13 +302,14 @@ struct XinvArgs {
   Geo g;
   int mode;
   int nphase;
+  int iso;                // every phase has the short (a Id + b m m^T) form
   const cpx<T>* smain;    // input spectrum (may alias out)
   const cpx<T>* snyq;
   const cpx<T>* twx;
   const T* tau;           // field the spectrum was taken of (p, tau, x)
   T* out;                 // real output (q, new tau, strain); may alias smain
   float* rout;            // FP32 residual (refinement)
-  const T* ptab;          // [nphase][2 c c + 1]: (A-A0)^{-1}, (A-A0), in-I0 flag
+  const T* ptab;          // [nphase][2 c c + 5], see phase_row
   const uint8_t* phase;
   const double* loads;    // [load][c]
   const LoadState* st;
@@ -304,11 +318,31 @@ struct XinvArgs {
   T scale;                // 1/N^d times the factor of the half-length route
 };
 
+// Row j of a per-phase c x c matrix applied to v.  Table row layout:
+// [(A-A0)^{-1} (c*c) | (A-A0) (c*c) | in-I0 flag | a_inv b_inv a_dir b_dir]
+// where, when every phase is "isotropic", each matrix is a Id + b m m^T with
+// m the indicator of the three normal Mandel components (b = 0 for scalar
+// problems), and the short form is used.
+template <typename T, int C>
+__device__ __forceinline__ T phase_row(const T* tb, int which, bool iso, int j, const T (&v)[C]) {
+  if (iso) {
+    const T a = tb[2 * C * C + 1 + 2 * which], b = tb[2 * C * C + 2 + 2 * which];
+    T r = a * v[j];
+    if (C == 6 && j < 3) r += b * (v[0] + v[1] + v[2]);
+    return r;
+  }
+  const T* M = tb + which * C * C + j * C;
+  T r = 0;
+#pragma unroll
+  for (int m = 0; m < C; ++m) r += M[m] * v[m];
+  return r;
+}
+
 template <typename T, int MX, int P, int C>
 __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
   constexpr int TR = MX / P;
   constexpr int RPW = 256 / TR;
-  constexpr int TABW = 2 * C * C + 1;
+  constexpr int TABW = 2 * C * C + 5;
   __shared__ cpx<T> lds[RPW * MX];
   __shared__ T tab[kMaxPhases * TABW];
   __shared__ double red[4];
@@ -323,20 +357,30 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
   const bool valid = vr < vrows;
   const long long vrc = valid ? vr : 0;
   cpx<T>* lrow = lds + slot * MX;
+  const bool iso = a.iso != 0;
 
+  // all components' spectrum rows are loaded before the first transform
   cpx<T> gam[C][P];
+  cpx<T> nqs[C];
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     const long long srow = (long long)j * vrows + vrc;
     const cpx<T>* sm = a.smain + (long long)l * main_cpx(g) + srow * MX;
+#pragma unroll
+    for (int i = 0; i < P; ++i) gam[j][i] = sm[t + TR * i];
+    nqs[j] = a.snyq[(long long)l * nyq_cpx(g) + srow];
+  }
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
     cpx<T> v[P];
 #pragma unroll
-    for (int i = 0; i < P; ++i) v[i] = sm[t + TR * i];
-    const cpx<T> nq = a.snyq[(long long)l * nyq_cpx(g) + srow];
+    for (int i = 0; i < P; ++i) v[i] = gam[j][i];
+    const cpx<T> nq = nqs[j];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < P; ++i) lrow[t + TR * i] = v[i];
     __syncthreads();
+    // repack the half spectrum as the half-length complex transform 2Z = 2E + i 2O
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const int k = t + TR * i;
@@ -345,7 +389,7 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
       const cpx<T> e = cpx<T>{xk.x + xm.x, xk.y - xm.y};          // 2E = X + conj(Xm)
       const cpx<T> d = cpx<T>{xk.x - xm.x, xk.y + xm.y};          // X - conj(Xm)
       const cpx<T> o = cmulc(d, a.twx[k]);                        // 2O = (X - conj Xm) W^{-k}
-      v[i] = cadd(e, mul_i(o));                                   // 2Z = 2E + i 2O
+      v[i] = cadd(e, mul_i(o));
     }
     __syncthreads();
     fft_pencil<MX, P, 1, T>(v, t, lrow, 1, a.twx, 2);
@@ -353,7 +397,7 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
     for (int i = 0; i < P; ++i) gam[j][i] = v[i];
   }
 
-  // scale: the half-length route returns 2 * (M N_y N_z) / 2 ... folded in a.scale (includes the 1/2 of 2Z)
+  // the route above returns N^d times the inverse DFT: a.scale = 1/N^d
   const T sc = a.scale;
   const long long fo = (long long)l * field_elems(g);
   double part = 0.0;
@@ -363,64 +407,59 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     const int n = t + TR * i;
-    const long long vox = vrc * (2 * MX) + 2 * n;   // voxel index of the pair
-    cpx<T> tv[C];
-    if (a.mode != XI_STRAIN) {
-#pragma unroll
-      for (int j = 0; j < C; ++j) tv[j] = *reinterpret_cast<const cpx<T>*>(a.tau + fo + (long long)j * g.nvox + vox);
-    }
-    const uint16_t ph2 = *reinterpret_cast<const uint16_t*>(a.phase + vox);
-    const int ph0 = ph2 & 0xff, ph1 = ph2 >> 8;
-    const T* tb0 = tab + ph0 * TABW;
-    const T* tb1 = tab + ph1 * TABW;
-    const T in0 = tb0[2 * C * C], in1 = tb1[2 * C * C];
-    cpx<T> res[C];
+    const long long vox = vrc * (2 * MX) + 2 * n;   // first voxel of the pair
+    T t0[C], t1[C], g0[C], g1[C];
 #pragma unroll
     for (int j = 0; j < C; ++j) {
-      const T gx = gam[j][i].x * sc, gy = gam[j][i].y * sc;
-      if (a.mode == XI_APPLY || a.mode == XI_CG) {
-        T lx = 0, ly = 0;
+      g0[j] = gam[j][i].x * sc;
+      g1[j] = gam[j][i].y * sc;
+      t0[j] = t1[j] = T(0);
+    }
+    if (a.mode != XI_STRAIN) {
 #pragma unroll
-        for (int m = 0; m < C; ++m) {
-          lx += tb0[j * C + m] * tv[m].x;
-          ly += tb1[j * C + m] * tv[m].y;
-        }
-        res[j] = cpx<T>{in0 * (lx + gx), in1 * (ly + gy)};
-      } else if (a.mode == XI_BASIC) {
-        // new tau = (A - A0)(p - Gamma tau); residual (p - Gamma tau) - (A - A0)^{-1} tau
-        T ux[C], uy[C];
-#pragma unroll
-        for (int m = 0; m < C; ++m) {
-          ux[m] = pl[m] - gam[m][i].x * sc;
-          uy[m] = pl[m] - gam[m][i].y * sc;
-        }
-        T nx = 0, ny = 0, lx = 0, ly = 0;
-#pragma unroll
-        for (int m = 0; m < C; ++m) {
-          nx += tb0[C * C + j * C + m] * ux[m];
-          ny += tb1[C * C + j * C + m] * uy[m];
-          lx += tb0[j * C + m] * tv[m].x;
-          ly += tb1[j * C + m] * tv[m].y;
-        }
-        res[j] = cpx<T>{in0 * nx, in1 * ny};
-        const double rx = in0 * (ux[j] - lx), ry = in1 * (uy[j] - ly);
-        part += rx * rx + ry * ry;
-      } else if (a.mode == XI_IRRES || a.mode == XI_RESNORM) {
-        T lx = 0, ly = 0;
-#pragma unroll
-        for (int m = 0; m < C; ++m) {
-          lx += tb0[j * C + m] * tv[m].x;
-          ly += tb1[j * C + m] * tv[m].y;
-        }
-        res[j] = cpx<T>{in0 * (pl[j] - lx - gx), in1 * (pl[j] - ly - gy)};
-        part += (double)res[j].x * res[j].x + (double)res[j].y * res[j].y;
-      } else {  // XI_STRAIN
-        res[j] = cpx<T>{pl[j] - gx, pl[j] - gy};
+      for (int j = 0; j < C; ++j) {
+        const cpx<T> tv = *reinterpret_cast<const cpx<T>*>(a.tau + fo + (long long)j * g.nvox + vox);
+        t0[j] = tv.x;
+        t1[j] = tv.y;
       }
     }
+    const uint16_t ph2 = *reinterpret_cast<const uint16_t*>(a.phase + vox);
+    const T* tb0 = tab + (ph2 & 0xff) * TABW;
+    const T* tb1 = tab + (ph2 >> 8) * TABW;
+    const T in0 = tb0[2 * C * C], in1 = tb1[2 * C * C];
+    cpx<T> res[C];
     if (a.mode == XI_APPLY || a.mode == XI_CG) {
 #pragma unroll
-      for (int j = 0; j < C; ++j) part += (double)tv[j].x * res[j].x + (double)tv[j].y * res[j].y;
+      for (int j = 0; j < C; ++j)
+        res[j] = cpx<T>{in0 * (phase_row<T, C>(tb0, 0, iso, j, t0) + g0[j]),
+                        in1 * (phase_row<T, C>(tb1, 0, iso, j, t1) + g1[j])};
+#pragma unroll
+      for (int j = 0; j < C; ++j) part += (double)t0[j] * res[j].x + (double)t1[j] * res[j].y;
+    } else if (a.mode == XI_BASIC) {
+      // new tau = (A - A0)(p - Gamma tau); residual (p - Gamma tau) - (A - A0)^{-1} tau
+      T u0[C], u1[C];
+#pragma unroll
+      for (int m = 0; m < C; ++m) {
+        u0[m] = pl[m] - g0[m];
+        u1[m] = pl[m] - g1[m];
+      }
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        res[j] = cpx<T>{in0 * phase_row<T, C>(tb0, 1, iso, j, u0), in1 * phase_row<T, C>(tb1, 1, iso, j, u1)};
+        const double rx = in0 * (u0[j] - phase_row<T, C>(tb0, 0, iso, j, t0));
+        const double ry = in1 * (u1[j] - phase_row<T, C>(tb1, 0, iso, j, t1));
+        part += rx * rx + ry * ry;
+      }
+    } else if (a.mode == XI_IRRES || a.mode == XI_RESNORM) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        res[j] = cpx<T>{in0 * (pl[j] - phase_row<T, C>(tb0, 0, iso, j, t0) - g0[j]),
+                        in1 * (pl[j] - phase_row<T, C>(tb1, 0, iso, j, t1) - g1[j])};
+        part += (double)res[j].x * res[j].x + (double)res[j].y * res[j].y;
+      }
+    } else {  // XI_STRAIN: p - Gamma tau everywhere
+#pragma unroll
+      for (int j = 0; j < C; ++j) res[j] = cpx<T>{pl[j] - g0[j], pl[j] - g1[j]};
     }
     if (valid) {
       if (a.mode == XI_IRRES) {
@@ -464,10 +503,10 @@ __device__ __forceinline__ double2 vaxpy(double2 x, double s, double2 y) {
 
 constexpr int kEwUnroll = 4;
 
-// x += alpha p;  r -= alpha q;  partial r.r      (per load, 16-byte vectors)
+// r -= alpha q;  partial r.r      (per load, 16-byte vectors; x is updated
+// one step later inside the x forward pass, or by k_xflush)
 template <typename T>
-__global__ __launch_bounds__(256) void k_cgupd(const long long nvec, T* __restrict__ x, const T* __restrict__ p,
-                                               T* __restrict__ r, const T* __restrict__ q,
+__global__ __launch_bounds__(256) void k_cgupd(const long long nvec, T* __restrict__ r, const T* __restrict__ q,
                                                const LoadState* __restrict__ st, double* __restrict__ partials,
                                                const int pstride) {
   using V = typename Vec16<T>::type;
@@ -476,8 +515,6 @@ __global__ __launch_bounds__(256) void k_cgupd(const long long nvec, T* __restri
   if (!st[l].active) return;
   const T al = static_cast<T>(st[l].alpha);
   const long long off = (long long)l * nvec;
-  V* xv = reinterpret_cast<V*>(x) + off;
-  const V* pv = reinterpret_cast<const V*>(p) + off;
   V* rv = reinterpret_cast<V*>(r) + off;
   const V* qv = reinterpret_cast<const V*>(q) + off;
   double part = 0.0;
@@ -486,15 +523,32 @@ __global__ __launch_bounds__(256) void k_cgupd(const long long nvec, T* __restri
   for (int u = 0; u < kEwUnroll; ++u) {
     const long long i = b0 + (long long)u * 256;
     if (i < nvec) {
-      const V xo = xv[i], po = pv[i], ro = rv[i], qo = qv[i];
-      xv[i] = vaxpy(xo, al, po);
-      const V rn = vaxpy(ro, -al, qo);
+      const V rn = vaxpy(rv[i], -al, qv[i]);
       rv[i] = rn;
       part += vdot(rn, rn);
     }
   }
   const double s = block_sum<256>(part, red);
   if (threadIdx.x == 0) partials[(long long)l * pstride + blockIdx.x] = s;
+}
+
+// x += alpha p for the loads whose last CG step is still pending
+template <typename T>
+__global__ __launch_bounds__(256) void k_xflush(const long long nvec, T* __restrict__ x, const T* __restrict__ p,
+                                                const LoadState* __restrict__ st) {
+  using V = typename Vec16<T>::type;
+  const int l = blockIdx.y;
+  if (!st[l].pending) return;
+  const T al = static_cast<T>(st[l].alpha);
+  const long long off = (long long)l * nvec;
+  V* xv = reinterpret_cast<V*>(x) + off;
+  const V* pv = reinterpret_cast<const V*>(p) + off;
+  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kEwUnroll; ++u) {
+    const long long i = b0 + (long long)u * 256;
+    if (i < nvec) xv[i] = vaxpy(xv[i], al, pv[i]);
+  }
 }
 
 // x = 0;  r = 1_{I0} p_l;  partial ||r||^2
@@ -603,6 +657,7 @@ static __global__ __launch_bounds__(256) void k_scal(const int mode, const doubl
     L.pq = 0.0;
     L.iters = 0;
     L.first = 1;
+    L.pending = 0;
     L.status = isfinite(S) ? kStatusOk : kStatusNumeric;
     L.active = (S > 0.0 && isfinite(S)) ? 1 : 0;
     return;
@@ -612,6 +667,8 @@ static __global__ __launch_bounds__(256) void k_scal(const int mode, const doubl
     L.pq = S;
     // p.Lp may be negative when A0 lies between the phases (indefinite
     // system): CG proceeds; it breaks down only when p.Lp vanishes.
+    // the previous step (if any) was applied to x by this iteration's x pass
+    L.pending = 0;
     if (!isfinite(S)) {
       L.status = kStatusNumeric;
       L.active = 0;
@@ -621,6 +678,7 @@ static __global__ __launch_bounds__(256) void k_scal(const int mode, const doubl
     } else {
       L.alpha = L.rr / S;
       L.first = 0;
+      L.pending = 1;
     }
   } else if (mode == SC_BETA) {
     L.iters += 1;

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -132,6 +133,8 @@ struct lsh_ctx {
   const uint8_t* phase_dev_src = nullptr;
   bool tables_dirty = true, phase_dirty = true, consts_ready = false;
   GreenParams gp{};
+  int iso = 0;  // every phase matrix has the short form (see phase_row)
+  int tune[2][NPASS] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // kernel-shape variant per (FP32/FP64, pass)
 
   // workspace
   char* ws = nullptr;
@@ -159,6 +162,7 @@ struct lsh_ctx {
   // timing
   bool timing = false;
   int nact = 1 << 30;  // host's count of loads still iterating (bounds the bytes of a launch)
+  bool xf_first = false;  // the CG x pass being queued is the first of its solve
   std::vector<KTimer> pending;
   std::vector<hipEvent_t> pool;
   double tsum[K_NCLASS] = {0};
@@ -265,7 +269,7 @@ void compute_layout(lsh_ctx* ctx) {
   ctx->off.s32n = mixed ? take(2 * sizeof(float) * L * nyq) : 0;
   ctx->off.phase = take(V + 16);
   ctx->off.i0 = take(256);
-  const int tabw = 2 * ctx->c * ctx->c + 1;
+  const int tabw = 2 * ctx->c * ctx->c + 5;
   ctx->off.ptab64 = take(sizeof(double) * kMaxPhases * tabw);
   ctx->off.ptab32 = take(sizeof(float) * kMaxPhases * tabw);
   const int ntw = ctx->n[0] + ctx->n[1] + ctx->n[2];
@@ -346,8 +350,9 @@ lsh_status upload_consts(lsh_ctx* ctx) {
 // Phase tables against the current A0: (A-A0)^{-1}, (A-A0), I0 flag; checks hypothesis (2).
 lsh_status build_tables(lsh_ctx* ctx) {
   const int c = ctx->c;
-  const int tabw = 2 * c * c + 1;
+  const int tabw = 2 * c * c + 5;
   ctx->h_ptab64.assign((size_t)kMaxPhases * tabw, 0.0);
+  bool all_iso = true;
   ctx->h_ptab32.assign((size_t)kMaxPhases * tabw, 0.f);
   ctx->h_i0.assign(256, 0);
   for (int p = 0; p < ctx->nphase; ++p) {
@@ -378,8 +383,25 @@ lsh_status build_tables(lsh_ctx* ctx) {
       row[c * c + i] = D[i];
     }
     row[2 * c * c] = 1.0;
+    // short form a Id + b m m^T (m: normal Mandel components; b = 0 for scalar)
+    for (int which = 0; which < 2; ++which) {
+      const double* M = which == 0 ? Dinv : D;
+      const bool el = ctx->physics == LSH_ELASTIC;
+      const double b = el ? M[1] : 0.0;
+      const double a = M[0] - b;
+      double mscale = 0.0;
+      for (int i = 0; i < c * c; ++i) mscale = std::max(mscale, std::fabs(M[i]));
+      for (int i = 0; i < c; ++i)
+        for (int j = 0; j < c; ++j) {
+          const double expect = (i == j ? a : 0.0) + ((el && i < 3 && j < 3) ? b : 0.0);
+          if (std::fabs(M[i * c + j] - expect) > 1e-13 * mscale) all_iso = false;
+        }
+      row[2 * c * c + 1 + 2 * which] = a;
+      row[2 * c * c + 2 + 2 * which] = b;
+    }
     ctx->h_i0[p] = 1;
   }
+  ctx->iso = all_iso ? 1 : 0;
   for (size_t i = 0; i < ctx->h_ptab64.size(); ++i) ctx->h_ptab32[i] = (float)ctx->h_ptab64[i];
 
   // Green parameters
@@ -494,38 +516,68 @@ lsh_status check_launch(lsh_ctx* ctx, int r, const char* what) {
 }
 
 
+template <typename T> int tv(const lsh_ctx* ctx, int pass) { return ctx->tune[sizeof(T) == 8 ? 1 : 0][pass]; }
+
+// Variants from LSH_TUNE, e.g. "zg32=3,y32=1,xinv64=2" (pass name + 32/64 = variant).
+void tune_from_env(lsh_ctx* ctx) {
+  const char* e = std::getenv("LSH_TUNE");
+  if (!e) return;
+  const char* names[NPASS] = {"xfwd", "y", "zg", "xinv"};
+  std::string s(e);
+  size_t pos = 0;
+  while (pos < s.size()) {
+    size_t end = s.find(',', pos);
+    if (end == std::string::npos) end = s.size();
+    const std::string item = s.substr(pos, end - pos);
+    const size_t eq = item.find('=');
+    if (eq != std::string::npos) {
+      const std::string key = item.substr(0, eq);
+      const int val = std::atoi(item.c_str() + eq + 1);
+      for (int p = 0; p < NPASS; ++p)
+        for (int prec = 0; prec < 2; ++prec)
+          if (key == std::string(names[p]) + (prec ? "64" : "32") && val >= 0 && val < kVariants)
+            ctx->tune[prec][p] = val;
+    }
+    pos = end + 1;
+  }
+}
+
 // Forward passes on load slots [l0, l0+nload): x (mode), y, z (+Gamma and inverse z), y inverse.
 template <typename T>
-lsh_status forward_part(lsh_ctx* ctx, int l0, int nload, int xmode, const T* src, T* pdir, const float* dsrc,
-                        const LoadState* st, bool gamma) {
+lsh_status forward_part(lsh_ctx* ctx, int l0, int nload, int xmode, const T* src, T* pdir, T* xacc,
+                        const float* dsrc, const LoadState* st, bool gamma) {
   const Geo& g = ctx->geo;
   cpx<T>* sm = Sel<T>::sm(ctx) + (long long)l0 * main_cpx(g);
   cpx<T>* sn = Sel<T>::sn(ctx) + (long long)l0 * nyq_cpx(g);
-  XfwdArgs<T> xa{g, xmode, src, pdir, dsrc, sm, sn, Sel<T>::tw(ctx, 0), st};
+  XfwdArgs<T> xa{g, xmode, src, pdir, xacc, dsrc, sm, sn, Sel<T>::tw(ctx, 0), st};
   // algorithmic bytes per launch (loads still iterating x per-load traffic)
   const double nl = std::min(ctx->nact, nload);
   const double cvs = (double)ctx->F * sizeof(T);
   const double spec = cvs + 2.0 * sizeof(T) * (double)nyq_cpx(g);
-  const double xin = xmode == XF_CG ? 3.0 * cvs : (xmode == XF_IRX ? 2.0 * cvs + 4.0 * ctx->F : cvs);
+  // CG: read r, p, write p, and (after the first step) read and write x
+  const double xin = xmode == XF_CG ? (ctx->xf_first ? 3.0 : 5.0) * cvs
+                                    : (xmode == XF_IRX ? 2.0 * cvs + 4.0 * ctx->F : cvs);
   {
     Scope sc(ctx, kcls<T>(K_XFWD), nl * (xin + spec));
-    STCHK(check_launch(ctx, launch_xfwd<T>(ctx->stream, xa, nload), "x forward"));
+    STCHK(check_launch(ctx, launch_xfwd<T>(ctx->stream, xa, nload, tv<T>(ctx, PASS_XFWD)), "x forward"));
   }
   {
     Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
-    STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, -1, sm, sn, Sel<T>::tw(ctx, 1), st, nload), "y forward"));
+    STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, -1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y)),
+                       "y forward"));
   }
   {
     Scope sc(ctx, kcls<T>(K_ZG), nl * 2.0 * spec);
     GreenTabs<T> tb{Sel<T>::wt(ctx), ctx->wstride};
     STCHK(check_launch(ctx,
                        launch_zg<T>(ctx->stream, g, ctx->gp, tb, gamma ? Z_GAMMA : Z_FWD, sm, sn, Sel<T>::tw(ctx, 2),
-                                    st, nload),
+                                    st, nload, tv<T>(ctx, PASS_ZG)),
                        "z/Green"));
   }
   if (gamma) {
     Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
-    STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, 1, sm, sn, Sel<T>::tw(ctx, 1), st, nload), "y inverse"));
+    STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, 1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y)),
+                       "y inverse"));
   }
   return LSH_OK;
 }
@@ -538,6 +590,7 @@ lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T*
   a.g = g;
   a.mode = mode;
   a.nphase = ctx->nphase;
+  a.iso = ctx->iso;
   a.smain = Sel<T>::sm(ctx) + (long long)l0 * main_cpx(g);
   a.snyq = Sel<T>::sn(ctx) + (long long)l0 * nyq_cpx(g);
   a.twx = Sel<T>::tw(ctx, 0);
@@ -558,7 +611,7 @@ lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T*
   if (mode == XI_IRRES) bytes += 4.0 * ctx->F;                                  // FP32 residual out
   else if (mode != XI_RESNORM) bytes += cvs;                                    // real output
   Scope sc(ctx, kcls<T>(K_XINV), nl * bytes);
-  const int nb = launch_xinv<T>(ctx->stream, a, nload);
+  const int nb = launch_xinv<T>(ctx->stream, a, nload, tv<T>(ctx, PASS_XINV));
   STCHK(check_launch(ctx, nb, "x inverse"));
   if (nparts) *nparts = nb;
   return LSH_OK;
@@ -586,16 +639,26 @@ lsh_status cg_init(lsh_ctx* ctx, int nload, T* x, T* r, LoadState* st, double to
 }
 
 template <typename T>
-lsh_status cg_update(lsh_ctx* ctx, int nload, T* x, const T* p, T* r, const T* q, LoadState* st) {
+lsh_status cg_update(lsh_ctx* ctx, int nload, T* r, const T* q, LoadState* st) {
   const long long nvec = ctx->F / Vec16<T>::n;
   const int nb = (int)((nvec + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
   {
-    Scope sc(ctx, kcls<T>(K_CGUPD), std::min(ctx->nact, nload) * 6.0 * (double)ctx->F * sizeof(T));
-    hipLaunchKernelGGL((k_cgupd<T>), dim3(nb, nload), dim3(256), 0, ctx->stream, nvec, x, p, r, q, st,
+    Scope sc(ctx, kcls<T>(K_CGUPD), std::min(ctx->nact, nload) * 3.0 * (double)ctx->F * sizeof(T));
+    hipLaunchKernelGGL((k_cgupd<T>), dim3(nb, nload), dim3(256), 0, ctx->stream, nvec, r, q, st,
                        ctx->ptr<double>(ctx->off.partials), (int)ctx->pstride);
     STCHK(check_launch(ctx, 0, "cg update"));
   }
   return scal(ctx, SC_BETA, nload, nb, st, 0.0);
+}
+
+// x += alpha p for the loads whose last step is pending (end of a CG solve)
+template <typename T>
+lsh_status cg_flush(lsh_ctx* ctx, int nload, T* x, const T* p, LoadState* st) {
+  const long long nvec = ctx->F / Vec16<T>::n;
+  const int nb = (int)((nvec + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
+  Scope sc(ctx, kcls<T>(K_CGUPD), nload * 3.0 * (double)ctx->F * sizeof(T));
+  hipLaunchKernelGGL((k_xflush<T>), dim3(nb, nload), dim3(256), 0, ctx->stream, nvec, x, p, st);
+  return check_launch(ctx, 0, "cg flush");
 }
 
 lsh_status read_states(lsh_ctx* ctx, size_t off, int nload, std::vector<LoadState>& h) {
@@ -623,11 +686,12 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
   for (auto& s : hst) any |= s.active != 0, ctx->nact += s.active != 0;
   if (!any) return LSH_OK;
   for (int it = 0; it < maxit; ++it) {
-    STCHK(forward_part<T>(ctx, 0, nload, XF_CG, r, p, nullptr, st, true));
+    ctx->xf_first = it == 0;
+    STCHK(forward_part<T>(ctx, 0, nload, XF_CG, r, p, x, nullptr, st, true));
     int np = 0;
     STCHK(inverse_x<T>(ctx, 0, nload, XI_CG, p, q, nullptr, st, ctx->ptr<double>(ctx->off.partials), &np));
     STCHK(scal(ctx, SC_ALPHA, nload, np, st, 0.0));
-    STCHK(cg_update<T>(ctx, nload, x, p, r, q, st));
+    STCHK(cg_update<T>(ctx, nload, r, q, st));
     if ((it + 1) % period == 0 || it + 1 == maxit) {
       STCHK(read_states(ctx, st_off, nload, hst));
       any = false;
@@ -636,7 +700,8 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
       if (!any) break;
     }
   }
-  return LSH_OK;
+  ctx->xf_first = false;
+  return cg_flush<T>(ctx, nload, x, p, st);
 }
 
 lsh_status basic_loop(lsh_ctx* ctx, int nload, double* x, LoadState* st, size_t st_off, int maxit,
@@ -648,7 +713,7 @@ lsh_status basic_loop(lsh_ctx* ctx, int nload, double* x, LoadState* st, size_t 
   for (auto& s : hst) any |= s.active != 0, ctx->nact += s.active != 0;
   if (!any) return LSH_OK;
   for (int it = 0; it < maxit; ++it) {
-    STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, x, nullptr, nullptr, st, true));
+    STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, x, nullptr, nullptr, nullptr, st, true));
     int np = 0;
     STCHK(inverse_x<double>(ctx, 0, nload, XI_BASIC, x, x, nullptr, st, ctx->ptr<double>(ctx->off.partials), &np));
     STCHK(scal(ctx, SC_BASIC, nload, np, st, 0.0));
@@ -666,7 +731,7 @@ lsh_status basic_loop(lsh_ctx* ctx, int nload, double* x, LoadState* st, size_t 
 // ||b - L x||^2 per load into sums[0..nload) (FP64 application on x64)
 lsh_status true_residual(lsh_ctx* ctx, int nload) {
   double* x = ctx->ptr<double>(ctx->off.x64);
-  STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, x, nullptr, nullptr, nullptr, true));
+  STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, x, nullptr, nullptr, nullptr, nullptr, true));
   int np = 0;
   STCHK(inverse_x<double>(ctx, 0, nload, XI_RESNORM, x, nullptr, nullptr, nullptr,
                           ctx->ptr<double>(ctx->off.partials), &np));
@@ -740,6 +805,7 @@ lsh_status lsh_create(lsh_ctx** out, int dim, const int64_t* n, int physics, int
   ctx->F = (long long)ctx->c * ctx->geo.nvox;
   ctx->A0.assign((size_t)ctx->c * ctx->c, 0.0);
   compute_layout(ctx);
+  tune_from_env(ctx);
   *out = ctx;
   return LSH_OK;
 }
@@ -916,7 +982,7 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
       budget -= used;
       ctx->nact = 0;
       for (auto& sv : hst) ctx->nact += sv.active != 0;
-      STCHK(forward_part<double>(ctx, 0, nload, XF_IRX, nullptr, x64, d, sto, true));
+      STCHK(forward_part<double>(ctx, 0, nload, XF_IRX, nullptr, x64, nullptr, d, sto, true));
       int np = 0;
       STCHK(inverse_x<double>(ctx, 0, nload, XI_IRRES, x64, nullptr, r, sto, ctx->ptr<double>(ctx->off.partials),
                               &np));
@@ -1055,7 +1121,7 @@ lsh_status lsh_get_field(lsh_ctx* ctx, int load, int which, void* dst, int dtype
   double* x = ctx->ptr<double>(ctx->off.x64) + (long long)load * F;
   if (which == LSH_FIELD_TAU) return copy_field_out(ctx, x, F, dst, dtype, mem);
   // strain p - Gamma tau, computed into the FP64 spectrum slot of this load
-  STCHK(forward_part<double>(ctx, load, 1, XF_PLAIN, x, nullptr, nullptr, nullptr, true));
+  STCHK(forward_part<double>(ctx, load, 1, XF_PLAIN, x, nullptr, nullptr, nullptr, nullptr, true));
   double* out = reinterpret_cast<double*>(Sel<double>::sm(ctx) + (long long)load * main_cpx(ctx->geo));
   STCHK(inverse_x<double>(ctx, load, 1, XI_STRAIN, x, out, nullptr, nullptr, nullptr, nullptr));
   return copy_field_out(ctx, out, F, dst, dtype, mem);
@@ -1071,12 +1137,12 @@ lsh_status lsh_apply(lsh_ctx* ctx, int nload, const void* tau, void* out, int dt
   STCHK(prepare(ctx));
   if (dtype == LSH_F64) {
     STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, static_cast<const double*>(tau), nullptr, nullptr, nullptr,
-                               true));
+                               nullptr, true));
     STCHK(inverse_x<double>(ctx, 0, nload, XI_APPLY, static_cast<const double*>(tau), static_cast<double*>(out),
                             nullptr, nullptr, nullptr, nullptr));
   } else {
     STCHK(forward_part<float>(ctx, 0, nload, XF_PLAIN, static_cast<const float*>(tau), nullptr, nullptr, nullptr,
-                              true));
+                              nullptr, true));
     STCHK(inverse_x<float>(ctx, 0, nload, XI_APPLY, static_cast<const float*>(tau), static_cast<float*>(out), nullptr,
                            nullptr, nullptr, nullptr));
   }
@@ -1104,13 +1170,13 @@ lsh_status lsh_forward_dft(lsh_ctx* ctx, int nload, const void* field, void* spe
   const long long nm = main_cpx(ctx->geo) * nload, nn = nyq_cpx(ctx->geo) * nload;
   if (dtype == LSH_F64) {
     STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, static_cast<const double*>(field), nullptr, nullptr, nullptr,
-                               false));
+                               nullptr, false));
     HIPCHK(hipMemcpyAsync(spec, Sel<double>::sm(ctx), nm * 16, hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(static_cast<char*>(spec) + nm * 16, Sel<double>::sn(ctx), nn * 16, hipMemcpyDeviceToDevice,
                           ctx->stream));
   } else {
     STCHK(forward_part<float>(ctx, 0, nload, XF_PLAIN, static_cast<const float*>(field), nullptr, nullptr, nullptr,
-                              false));
+                              nullptr, false));
     HIPCHK(hipMemcpyAsync(spec, Sel<float>::sm(ctx), nm * 8, hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(static_cast<char*>(spec) + nm * 8, Sel<float>::sn(ctx), nn * 8, hipMemcpyDeviceToDevice,
                           ctx->stream));

@@ -184,3 +184,21 @@ def test_operator_full_size_scalar_128_plane_waves(lsh):
         for l in range(nload):
             ref = in_i0[w.phase] * (np.einsum("...ij,j...->i...", dinv[w.phase], tau[l]) + gam[l])
             assert rel_max_err(out[l], ref) <= (1e-11 if dtype == "f64" else 2e-5)
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("physics,shape", [("scalar", (128, 8, 128)), ("scalar", (4, 128, 256)),
+                                           ("elastic", (256, 4, 128)), ("elastic", (8, 256, 256))])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_operator_kernel_shape_variants(lsh, monkeypatch, physics, shape, variant, dtype):
+    # every compiled kernel shape of the 128/256-point passes gives the oracle's L tau
+    bits = "64" if dtype == "f64" else "32"
+    monkeypatch.setenv("LSH_TUNE", ",".join(f"{p}{bits}={variant}" for p in ("xfwd", "y", "zg", "xinv")))
+    ph, moduli, A0 = _op_setup(physics, shape, "filtered", "")
+    pb = problem(ph, moduli, A0, physics, "filtered")
+    ctx = context(lsh, ph, moduli, A0, physics, "filtered", precision="mixed" if dtype == "f32" else "fp64",
+                  max_loads=2)
+    tau = I.random_field(shape, pb.c, 2, seed=9)
+    out = ctx.apply(to_dev(tau, dtype)).cpu().numpy()
+    ref = np.stack([op.apply(pb, tau[l]) for l in range(2)])
+    assert rel_max_err(out, ref) <= (1e-12 if dtype == "f64" else 1e-5)
