@@ -182,6 +182,15 @@ lsh_status lsh_forward_dft(lsh_ctx* ctx, int nload, const void* field, void* spe
 lsh_status lsh_spectrum_bytes(const lsh_ctx* ctx, int dtype, size_t* bytes);
 
 /*
+ * Iteration graphs (default on): the kernels of one solver iteration are
+ * captured once into a HIP graph (on a private stream of default priority)
+ * and the graph is replayed on the context's stream for every iteration.
+ * Graphs are not used while kernel timing is enabled.  The captured graph
+ * holds only kernel nodes.
+ */
+lsh_status lsh_set_graphs(lsh_ctx* ctx, int enable);
+
+/*
  * Kernel timing: when enabled, every kernel launch is bracketed by HIP events
  * on the context's stream and accumulated per kernel class (transform and
  * update classes are split by element type, e.g. "zgamma_f32").

@@ -159,6 +159,15 @@ struct lsh_ctx {
   bool have_solution = false;
   std::vector<double> last_loads, sigma;
 
+  // graphs: one solver iteration captured once and replayed
+  bool use_graphs = true;
+  hipStream_t cap_stream = nullptr;
+  struct IterGraph {
+    hipGraphExec_t exec = nullptr;
+    long long key = -1;
+  } graphs[3];
+  long long graph_epoch = 0;  // bumped whenever captured kernel arguments may change
+
   // timing
   bool timing = false;
   int nact = 1 << 30;  // host's count of loads still iterating (bounds the bytes of a launch)
@@ -432,6 +441,7 @@ lsh_status build_tables(lsh_ctx* ctx) {
   HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.i0, ctx->h_i0.data(), 256, hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->tables_dirty = false;
+  ctx->graph_epoch++;
   return LSH_OK;
 }
 
@@ -673,6 +683,45 @@ int check_period(lsh_ctx* ctx, int nload) {
   return work >= (1LL << 22) ? 1 : 8;
 }
 
+// Queue one solver iteration.  With graphs enabled (and kernel timing off)
+// the iteration is captured once on a private stream, instantiated, and the
+// graph is launched on the context's stream thereafter; `key` identifies the
+// argument set the capture baked in.
+template <typename F>
+lsh_status run_iteration(lsh_ctx* ctx, int slot, long long key, F&& enqueue) {
+  if (!ctx->use_graphs || ctx->timing) return enqueue();
+  auto& G = ctx->graphs[slot];
+  key = key * 1000003LL + ctx->graph_epoch;
+  if (G.exec == nullptr || G.key != key) {
+    if (G.exec) {
+      (void)hipGraphExecDestroy(G.exec);
+      G.exec = nullptr;
+    }
+    if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+    hipStream_t user = ctx->stream;
+    ctx->stream = ctx->cap_stream;
+    const lsh_status s = enqueue();
+    ctx->stream = user;
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (s != LSH_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return fail(ctx, LSH_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+      G.exec = nullptr;
+      return fail(ctx, LSH_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e2));
+    }
+    G.key = key;
+  }
+  HIPCHK(hipGraphLaunch(G.exec, ctx->stream));
+  return LSH_OK;
+}
+
 // CG iterations on (x, r, p) with q held in the spectrum buffer; returns after
 // convergence of every load, or maxit iterations.
 template <typename T>
@@ -685,13 +734,17 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
   ctx->nact = 0;
   for (auto& s : hst) any |= s.active != 0, ctx->nact += s.active != 0;
   if (!any) return LSH_OK;
-  for (int it = 0; it < maxit; ++it) {
-    ctx->xf_first = it == 0;
+  auto iteration = [&]() -> lsh_status {
     STCHK(forward_part<T>(ctx, 0, nload, XF_CG, r, p, x, nullptr, st, true));
     int np = 0;
     STCHK(inverse_x<T>(ctx, 0, nload, XI_CG, p, q, nullptr, st, ctx->ptr<double>(ctx->off.partials), &np));
     STCHK(scal(ctx, SC_ALPHA, nload, np, st, 0.0));
-    STCHK(cg_update<T>(ctx, nload, r, q, st));
+    return cg_update<T>(ctx, nload, r, q, st);
+  };
+  const long long key = (long long)nload * 4 + (st_off == ctx->off.st_in ? 1 : 0);
+  for (int it = 0; it < maxit; ++it) {
+    ctx->xf_first = it == 0;
+    STCHK(run_iteration(ctx, sizeof(T) == 8 ? 0 : 1, key, iteration));
     if ((it + 1) % period == 0 || it + 1 == maxit) {
       STCHK(read_states(ctx, st_off, nload, hst));
       any = false;
@@ -712,11 +765,14 @@ lsh_status basic_loop(lsh_ctx* ctx, int nload, double* x, LoadState* st, size_t 
   ctx->nact = 0;
   for (auto& s : hst) any |= s.active != 0, ctx->nact += s.active != 0;
   if (!any) return LSH_OK;
-  for (int it = 0; it < maxit; ++it) {
+  auto iteration = [&]() -> lsh_status {
     STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, x, nullptr, nullptr, nullptr, st, true));
     int np = 0;
     STCHK(inverse_x<double>(ctx, 0, nload, XI_BASIC, x, x, nullptr, st, ctx->ptr<double>(ctx->off.partials), &np));
-    STCHK(scal(ctx, SC_BASIC, nload, np, st, 0.0));
+    return scal(ctx, SC_BASIC, nload, np, st, 0.0);
+  };
+  for (int it = 0; it < maxit; ++it) {
+    STCHK(run_iteration(ctx, 2, (long long)nload, iteration));
     if ((it + 1) % period == 0 || it + 1 == maxit) {
       STCHK(read_states(ctx, st_off, nload, hst));
       any = false;
@@ -814,6 +870,9 @@ lsh_status lsh_destroy(lsh_ctx* ctx) {
   if (!ctx) return LSH_EINVAL;
   drain_timers(ctx);
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  for (auto& G : ctx->graphs)
+    if (G.exec) (void)hipGraphExecDestroy(G.exec);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return LSH_OK;
 }
@@ -834,6 +893,7 @@ lsh_status lsh_bind_workspace(lsh_ctx* ctx, void* dev_ptr, size_t bytes) {
     return fail(ctx, LSH_ESTATE, "device phase map must be set again after rebinding the workspace");
   ctx->ws = static_cast<char*>(dev_ptr);
   ctx->ws_size = bytes;
+  ctx->graph_epoch++;
   ctx->consts_ready = false;
   ctx->tables_dirty = true;
   ctx->phase_dirty = ctx->have_phase;
@@ -1183,6 +1243,12 @@ lsh_status lsh_forward_dft(lsh_ctx* ctx, int nload, const void* field, void* spe
   }
   ctx->have_solution = false;
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  return LSH_OK;
+}
+
+lsh_status lsh_set_graphs(lsh_ctx* ctx, int enable) {
+  if (!ctx) return LSH_EINVAL;
+  ctx->use_graphs = enable != 0;
   return LSH_OK;
 }
 

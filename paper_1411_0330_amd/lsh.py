@@ -62,6 +62,7 @@ _SIGS = {
     "lsh_forward_dft": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "lsh_spectrum_bytes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_size_t)]),
     "lsh_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "lsh_set_graphs": (C.c_int, [C.c_void_p, C.c_int]),
     "lsh_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
                                    C.POINTER(C.c_int64), C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_int)]),
     "lsh_last_error": (C.c_char_p, [C.c_void_p]),
@@ -263,7 +264,10 @@ class Context:
         nyq = cs[nmain:].reshape((nload, self.c) + lead)
         return main, nyq
 
-    # -- timing --------------------------------------------------------
+    # -- graphs and timing ---------------------------------------------
+    def set_graphs(self, enable=True):
+        self._check(self.lib.lsh_set_graphs(self.h, 1 if enable else 0))
+
     def set_timing(self, enable=True):
         self._check(self.lib.lsh_set_timing(self.h, 1 if enable else 0))
 

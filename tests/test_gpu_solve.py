@@ -173,3 +173,32 @@ def test_elastic_rsa_64_fp64_and_mixed_against_golden(lsh):
     Am, repm = _gpu_effective(ctxm, w.loads, tol=1e-8)
     assert max(repm["rel_residual"]) <= 1e-8
     assert rel_max_err(Am, gold["A_star"]) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_matches_eager(lsh, precision):
+    # the captured iteration replays across solves, with eager work in between,
+    # and gives bitwise the results of the eager launches
+    w = I.boolean_workload(32, seed=3)
+    def run(graphs):
+        ctx = context(lsh, w.phase, w.moduli, w.A0, "scalar", "filtered", precision=precision, max_loads=3)
+        ctx.set_graphs(graphs)
+        outs = []
+        for rep in range(3):
+            r = ctx.solve(w.loads, "cg", tol=1e-10 if precision == "fp64" else 1e-8)
+            outs.append((ctx.effective().copy(), ctx.field(1).cpu().numpy(), r["iterations"]))
+            ctx.apply(ctx.field(0).reshape((1,) + ctx.field(0).shape).contiguous())   # eager work between replays
+        return outs
+    eager, graph = run(False), run(True)
+    for (a1, f1, i1), (a2, f2, i2) in zip(eager, graph):
+        assert np.array_equal(a1, a2) and np.array_equal(f1, f2) and i1 == i2
+    assert np.array_equal(graph[0][0], graph[2][0])
+    # basic scheme too
+    w2 = I.disk_workload(32, "truncated")
+    res = []
+    for graphs in (False, True):
+        ctx = context(lsh, w2.phase, w2.moduli, w2.A0, "scalar", "truncated", precision=precision, max_loads=2)
+        ctx.set_graphs(graphs)
+        ctx.solve(w2.loads, "basic", tol=1e-10, maxit=3000)
+        res.append(ctx.effective())
+    assert np.array_equal(res[0], res[1])
