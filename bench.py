@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-timing", action="store_true", help="do not bracket kernels with HIP events")
+    ap.add_argument("--no-small", action="store_true", help="skip the 64^2 launch-bound leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a plain 1 GiB device copy (y = 1.0 * x) to calibrate HBM counters")
     return ap.parse_args()
 
 
@@ -73,6 +76,35 @@ def run_steps(ctx, lsh, w, phase_dev, nsteps, args, keep_fields=True):
     return time.perf_counter() - t0, total_apps * nvox, rep, eff
 
 
+def kernel_source_sha256():
+    """Hash of the HIP sources (as recorded with the HBM counter summary)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1411_0330_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + glob.glob(os.path.join(csrc, "*.hip")),
+                    key=os.path.basename):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "elastic256_mixed_hbm_counters.md")
+    try:
+        with open(path) as f:
+            line = next(ln for ln in f if ln.strip().startswith("traffic-json:"))
+        rec = json.loads(line.split("traffic-json:", 1)[1])
+    except (OSError, StopIteration, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_sha256():
+        return None
+    return rec.get("bytes_per_launch", {}).get(kernel)
+
+
 def roofline_from(ktimes):
     """Dominant kernel class by time; its algorithmic GB/s against the HBM peak."""
     best = max(ktimes.items(), key=lambda kv: kv[1][0])
@@ -87,7 +119,9 @@ def roofline_from(ktimes):
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(name),
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
+        "alg_bytes_per_launch": round(nbytes / max(launches, 1)),
         "avg_launch_ms": round(ms / max(launches, 1), 4),
         "launches": launches,
         "all_kernels_GBps": round(total_bytes / (total_ms * 1e-3) / 1e9, 1) if total_ms > 0 else 0.0,
@@ -162,6 +196,14 @@ def main():
 
     lsh.load()
     dev = "cuda:0"
+    if args.copy_probe:
+        # a plain elementwise copy of known size: reads 1 GiB, writes 1 GiB
+        xc = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        yc = torch.empty_like(xc)
+        torch.mul(xc, 1.0, out=yc)
+        torch.cuda.synchronize()
+        del xc, yc
+        log("copy probe: 1 GiB read + 1 GiB written by one elementwise kernel")
     log(f"building the {args.grid}^3 RSA microstructure")
     w = I.elastic_rsa_workload(args.grid, seed=0, tol=args.tol)
     phase_dev = torch.from_numpy(w.phase).to(dev)
@@ -243,7 +285,7 @@ def main():
     # ---------------- a launch-bound grid: 2D disk 64^2, graphs vs eager ----------------
     wd = I.disk_workload(64, "truncated")
     small = {}
-    for graphs in (False, True):
+    for graphs in (() if args.no_small else (False, True)):
         ctxs = lsh.Context(wd.phase.shape, "scalar", "fp64", max_loads=2, device=dev)
         ctxs.set_reference(wd.A0)
         ctxs.set_phases(wd.phase, wd.moduli)
@@ -262,8 +304,9 @@ def main():
                                                    "us_per_iteration": round(dt * 1e6 / its, 2),
                                                    "iterations": its}
         del ctxs
-    out["disk64_fp64_cg"] = small
-    log(f"disk 64^2: {small}")
+    if small:
+        out["disk64_fp64_cg"] = small
+        log(f"disk 64^2: {small}")
 
     # ---------------- CPU oracle on a bounded sample ----------------
     if not args.no_cpu:
