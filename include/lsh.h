@@ -54,7 +54,7 @@ typedef enum {
 
 enum { LSH_SCALAR = 0, LSH_ELASTIC = 1 };            /* physics */
 enum { LSH_FP64 = 0, LSH_MIXED = 1 };                /* precision */
-enum { LSH_GREEN_TRUNCATED = 0, LSH_GREEN_FILTERED = 1 };
+enum { LSH_GREEN_TRUNCATED = 0, LSH_GREEN_FILTERED = 1, LSH_GREEN_CONSISTENT = 2, LSH_GREEN_FD = 3 };
 enum { LSH_SOLVER_BASIC = 0, LSH_SOLVER_CG = 1 };
 enum { LSH_HOST = 0, LSH_DEVICE = 1 };               /* memory space of a pointer */
 enum { LSH_F64 = 0, LSH_F32 = 1 };                   /* element type of a field buffer */
@@ -124,8 +124,23 @@ lsh_status lsh_set_phases(lsh_ctx* ctx, const uint8_t* phase, int mem, int nphas
                           const double* moduli);
 
 /* Discrete Green operator: truncated (eqs. 14/15 with the Nyquist rule of
- * Section 3.2.1) or filtered (Section 3.2.2).  Default: filtered. */
+ * Section 3.2.1), filtered (Section 3.2.2), consistent (eq. 11, stored; needs a
+ * bound table, see below) or finite-difference (Section 3.2.3, scalar physics
+ * only; LSH_EINVAL for elasticity).  Default: filtered. */
 lsh_status lsh_set_green(lsh_ctx* ctx, int variant);
+
+/*
+ * The consistent operator of eq. (11) is a slowly converging lattice series
+ * that has to be stored (Section 3.2).  It is evaluated once on the GPU, in
+ * FP64, into caller-owned device memory of lsh_green_table_bytes bytes bound
+ * with lsh_bind_green_table, keeping the aliases whose reduced frequency
+ * k_a/N_a + n_a lies in [-(nmax + 1/2), nmax + 1/2] on every axis
+ * (lsh_set_green_series, default nmax = 8; 0 <= nmax <= 64).  The table holds
+ * the upper triangle of the c x c matrix at every stored wave-vector.
+ */
+lsh_status lsh_green_table_bytes(const lsh_ctx* ctx, size_t* bytes);
+lsh_status lsh_bind_green_table(lsh_ctx* ctx, void* dev_ptr, size_t bytes);
+lsh_status lsh_set_green_series(lsh_ctx* ctx, int nmax);
 
 /*
  * Solve eq. (13) for nload (1..max_loads) macroscopic loads p_l (host,

@@ -22,7 +22,7 @@ from . import operator as op
 
 def real_space_kernel(pb: op.Problem) -> np.ndarray:
     """Gamma_beta for every beta of the grid: array (*grid, c, c)."""
-    G = _green.table(pb.shape, pb.physics, pb.A0, pb.green)
+    G = _green.table(pb.shape, pb.physics, pb.A0, pb.green, nmax=pb.series)
     shape = pb.shape
     d = len(shape)
     idx = np.array(list(itertools.product(*[range(n) for n in shape])))   # array-axis order

@@ -195,7 +195,7 @@ def finite_difference(shape, A0, a_slice=None) -> np.ndarray:
     return out
 
 
-def at(shape, physics, A0, variant, kidx) -> np.ndarray:
+def at(shape, physics, A0, variant, kidx, nmax=8) -> np.ndarray:
     """Table entries at the DFT index vectors ``kidx`` (rows of physical-axis
     indices (kx, ky[, kz])), evaluated by the same definitions on a
     one-point view of the grid.  Returns (n, c, c)."""
@@ -205,19 +205,19 @@ def at(shape, physics, A0, variant, kidx) -> np.ndarray:
     for k in kidx:
         # the entry of the full table at array index reversed(k)
         sl = slice(int(k[d - 1]), int(k[d - 1]) + 1)
-        T = table(shape, physics, A0, variant, a_slice=sl)
+        T = table(shape, physics, A0, variant, a_slice=sl, nmax=nmax)
         idx = (0,) + tuple(int(k[d - 1 - ax]) for ax in range(1, d))
         out.append(T[idx])
     return np.stack(out)
 
 
-def table(shape, physics, A0, variant, a_slice=None) -> np.ndarray:
+def table(shape, physics, A0, variant, a_slice=None, nmax=8) -> np.ndarray:
     if variant == "truncated":
         return truncated(shape, physics, A0, a_slice)
     if variant == "filtered":
         return filtered(shape, physics, A0, a_slice)
     if variant == "consistent":
-        return consistent(shape, physics, A0, a_slice=a_slice)
+        return consistent(shape, physics, A0, nmax=nmax, a_slice=a_slice)
     if variant == "fd":
         if physics != "scalar":
             raise ValueError("the finite-difference operator is scalar-only")

@@ -34,6 +34,7 @@ class Problem:
     A0: np.ndarray         # (c, c) reference medium
     physics: str           # "scalar" | "elastic"
     green: str = "filtered"
+    series: int = 8        # consistent operator: alias cut nmax
 
     @property
     def shape(self):
@@ -91,17 +92,17 @@ _CACHE_LIMIT = 2.0e8   # table entries kept in memory (doubles)
 
 
 def _slab_table(pb, sl):
-    key = (pb.shape, pb.physics, np.asarray(pb.A0).tobytes(), pb.green)
+    key = (pb.shape, pb.physics, np.asarray(pb.A0).tobytes(), pb.green, pb.series)
     full = _TABLE_CACHE.get(key)
     if full is not None:
         return full[sl]
     if pb.nvox * pb.c * pb.c <= _CACHE_LIMIT:
         if len(_TABLE_CACHE) > 8:
             _TABLE_CACHE.clear()
-        full = _green.table(pb.shape, pb.physics, pb.A0, pb.green)
+        full = _green.table(pb.shape, pb.physics, pb.A0, pb.green, nmax=pb.series)
         _TABLE_CACHE[key] = full
         return full[sl]
-    return _green.table(pb.shape, pb.physics, pb.A0, pb.green, a_slice=sl)
+    return _green.table(pb.shape, pb.physics, pb.A0, pb.green, a_slice=sl, nmax=pb.series)
 
 
 def gamma_apply(pb: Problem, tau: np.ndarray, slab: int = 16) -> np.ndarray:

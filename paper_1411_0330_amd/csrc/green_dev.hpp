@@ -20,7 +20,7 @@
 
 namespace lsh {
 
-enum : int { kGreenTruncated = 0, kGreenFiltered = 1 };
+enum : int { kGreenTruncated = 0, kGreenFiltered = 1, kGreenConsistent = 2, kGreenFD = 3 };
 
 // Parameters shared by all wave-vectors (kernel argument, by value).
 struct GreenParams {
@@ -33,12 +33,78 @@ struct GreenParams {
   double s0_vol;     // ... plus s0_vol on the 3x3 normal block
 };
 
-// Per-axis filter weights: wtab[a*wstride + k] = (cos^2, sin^2)(pi k/(2 N_a)).
+// Device tables of the Green operators:
+//  w      per-axis filter weights, w[a*wstride + k] = (cos^2, sin^2)(pi k/(2 N_a));
+//  tw[a]  per-axis twiddles exp(-2 pi i m / N_a) (finite differences);
+//  tab    stored operator (consistent): the upper triangle (row-major, c(c+1)/2
+//         entries) of the real symmetric c x c matrix at every stored
+//         wave-vector, main spectrum order then the Nyquist plane.
 template <typename T>
 struct GreenTabs {
   const cpx<T>* w;
   int wstride;
+  const cpx<T>* tw[3];
+  const T* tab;
 };
+
+// Stored symmetric table applied to a c-vector
+template <typename T, int D>
+__device__ __forceinline__ void green_table_apply(const T* e, cpx<T> (&v)[D]) {
+  T M[D][D];
+  int q = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = i; j < D; ++j) {
+      M[i][j] = M[j][i] = e[q];
+      ++q;
+    }
+  cpx<T> o[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    o[i] = cpx<T>{0, 0};
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      o[i].x += M[i][j] * v[j].x;
+      o[i].y += M[i][j] * v[j].y;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) v[i] = o[i];
+}
+
+// Finite-difference operator of Section 3.2.3 (scalar problems):
+// V V^H / (V^H A0 V) with V_a = (exp(2 i pi k_a/N_a) - 1) N_a, zero at k = 0.
+template <typename T, int D>
+__device__ __forceinline__ void green_fd(const GreenParams& gp, const GreenTabs<T>& tb, const int (&k)[3],
+                                         cpx<T> (&v)[D]) {
+  cpx<T> V[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const cpx<T> wv = tb.tw[a][k[a]];                       // exp(-2 pi i k/N)
+    const T n = static_cast<T>(gp.n[a]);
+    V[a] = cpx<T>{(wv.x - T(1)) * n, -wv.y * n};            // (exp(+2 pi i k/N) - 1) N
+  }
+  T den = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const T a = static_cast<T>(gp.a0[3 * i + j]);
+      den += a * (V[i].x * V[j].x + V[i].y * V[j].y);       // Re(conj(V_i) A_ij V_j)
+    }
+  if (!(den > T(0))) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) v[i] = cpx<T>{0, 0};
+    return;
+  }
+  cpx<T> s{0, 0};                                           // V^H v
+#pragma unroll
+  for (int i = 0; i < D; ++i) s = cadd(s, cmulc(v[i], V[i]));
+  const T inv = T(1) / den;
+#pragma unroll
+  for (int i = 0; i < D; ++i) v[i] = cscale(cmul(V[i], s), inv);
+}
 
 // reciprocal: the FP32 path uses the hardware reciprocal (1 ulp), FP64 divides
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -279,12 +345,22 @@ __device__ __forceinline__ void green_elastic(const GreenParams& gp, const Green
   for (int i = 0; i < 6; ++i) v[i] = cpx<T>{ore[i], oim[i]};
 }
 
+// Dispatch on the operator; `tidx` is the wave-vector's position in the
+// stored table (consistent operator only).
 template <typename T, int C>
 __device__ __forceinline__ void green_apply(const GreenParams& gp, const GreenTabs<T>& tb, const int (&k)[3],
-                                            cpx<T> (&v)[C]) {
+                                            long long tidx, cpx<T> (&v)[C]) {
+  if (gp.variant == kGreenConsistent) {
+    green_table_apply<T, C>(tb.tab + tidx * (C * (C + 1) / 2), v);
+    return;
+  }
   if constexpr (C == 6) {
     green_elastic<T>(gp, tb, k, v);
   } else {
+    if (gp.variant == kGreenFD) {
+      green_fd<T, C>(gp, tb, k, v);
+      return;
+    }
     green_scalar<T, C>(gp, tb, k, v);
   }
 }

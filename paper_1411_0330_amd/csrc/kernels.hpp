@@ -274,11 +274,14 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
     if (valid) {
 #pragma unroll
       for (int i = 0; i < P; ++i) {
-        const int k[3] = {kx, ky, t + TZ * i};
+        const int kz = t + TZ * i;
+        const int k[3] = {kx, ky, kz};
+        const long long tidx = (kx < g.mx) ? ((long long)kz * g.ny + ky) * g.mx + kx
+                                           : (long long)g.nz * g.ny * g.mx + (long long)kz * g.ny + ky;
         cpx<T> w[C];
 #pragma unroll
         for (int j = 0; j < C; ++j) w[j] = v[j][i];
-        green_apply<T, C>(gp, tb, k, w);
+        green_apply<T, C>(gp, tb, k, tidx, w);
 #pragma unroll
         for (int j = 0; j < C; ++j) v[j][i] = w[j];
       }
@@ -478,6 +481,96 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
     const double s = block_sum<256>(part, red);
     if (tid == 0) a.partials[(long long)l * a.pstride + blockIdx.x] = s;
   }
+}
+
+// ----------------------------------------------------------------------------
+// Consistent operator of eq. (11), stored: one thread per wave-vector of the
+// packed half spectrum (main part, then the Nyquist plane) sums
+// F(2 pi (k/N + n))^2 Gamma0_hat(k + n N) over the aliases whose reduced
+// frequency k_a/N_a + n_a lies in [-(nmax+1/2), nmax+1/2] on every axis
+// (a cut that keeps the truncated series even in k), in FP64, and writes the
+// upper triangle in FP64 and FP32.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ double sinc_pi(double x) {   // sin(pi x)/(pi x)
+  if (x == 0.0) return 1.0;
+  return sinpi(x) / (3.14159265358979323846 * x);
+}
+
+template <int C>
+__global__ __launch_bounds__(256) void k_consistent_table(const Geo g, const GreenParams gp, const int nmax,
+                                                          double* __restrict__ tab64, float* __restrict__ tab32) {
+  constexpr int NE = C * (C + 1) / 2;
+  const long long nmain = (long long)g.nz * g.ny * g.mx;
+  const long long total = nmain + (long long)g.nz * g.ny;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= total) return;
+  int k[3];
+  if (id < nmain) {
+    k[0] = (int)(id % g.mx);
+    k[1] = (int)((id / g.mx) % g.ny);
+    k[2] = (int)(id / ((long long)g.mx * g.ny));
+  } else {
+    const long long r = id - nmain;
+    k[0] = g.mx;
+    k[1] = (int)(r % g.ny);
+    k[2] = (int)(r / g.ny);
+  }
+  const int dim = (C == 2) ? 2 : 3;
+  double acc[C][C];
+  for (int i = 0; i < C; ++i)
+    for (int j = 0; j < C; ++j) acc[i][j] = 0.0;
+  const double lim = nmax + 0.5;
+  int lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = 0;
+    hi[a] = 0;
+  }
+  for (int a = 0; a < dim; ++a) {
+    lo[a] = -nmax - 1;
+    hi[a] = nmax + 1;
+  }
+  for (int n2 = lo[2]; n2 <= hi[2]; ++n2)
+    for (int n1 = lo[1]; n1 <= hi[1]; ++n1)
+      for (int n0 = lo[0]; n0 <= hi[0]; ++n0) {
+        const int nn[3] = {n0, n1, n2};
+        double w = 1.0, xi[3] = {0.0, 0.0, 0.0};
+        bool inside = true;
+        for (int a = 0; a < dim; ++a) {
+          const double frac = (double)k[a] / gp.n[a] + nn[a];
+          inside &= fabs(frac) <= lim;
+          const double sc = sinc_pi(frac);
+          w *= sc * sc;
+          xi[a] = frac * gp.n[a];
+        }
+        if (!inside || w == 0.0) continue;
+        // Gamma0_hat at xi, as a c x c matrix (columns: images of the unit vectors)
+        if constexpr (C == 6) {
+          BD<double> s;
+          bd_zero(s);
+          bd_add(s, 1.0, xi[0], xi[1], xi[2]);
+          for (int j = 0; j < 6; ++j) {
+            double e[6], o[6];
+            for (int i = 0; i < 6; ++i) e[i] = i == j ? 1.0 : 0.0;
+            bd_apply_real(s, 0.5 / gp.mu0, gp.kappa, e, o);
+            for (int i = 0; i < 6; ++i) acc[i][j] += w * o[i];
+          }
+        } else {
+          double den = 0.0;
+          for (int a = 0; a < C; ++a)
+            for (int b = 0; b < C; ++b) den += xi[a] * gp.a0[3 * a + b] * xi[b];
+          if (den > 0.0)
+            for (int i = 0; i < C; ++i)
+              for (int j = 0; j < C; ++j) acc[i][j] += w * xi[i] * xi[j] / den;
+        }
+      }
+  int q = 0;
+  for (int i = 0; i < C; ++i)
+    for (int j = i; j < C; ++j) {
+      const double val = 0.5 * (acc[i][j] + acc[j][i]);
+      tab64[id * NE + q] = val;
+      tab32[id * NE + q] = (float)val;
+      ++q;
+    }
 }
 
 // ----------------------------------------------------------------------------

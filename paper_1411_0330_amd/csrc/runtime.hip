@@ -133,6 +133,9 @@ struct lsh_ctx {
   const uint8_t* phase_dev_src = nullptr;
   bool tables_dirty = true, phase_dirty = true, consts_ready = false;
   GreenParams gp{};
+  char* gtab = nullptr;   // bound consistent-operator table (FP64 entries, then FP32)
+  size_t gtab_size = 0;
+  int series = 8;
   int iso = 0;  // every phase matrix has the short form (see phase_row)
   int tune[2][NPASS] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // kernel-shape variant per (FP32/FP64, pass)
 
@@ -201,6 +204,13 @@ lsh_status fail(lsh_ctx* ctx, lsh_status s, const std::string& msg) {
     lsh_status s_ = (expr);               \
     if (s_ != LSH_OK) return s_;          \
   } while (0)
+
+lsh_status check_launch(lsh_ctx* ctx, int r, const char* what) {
+  if (r < 0) return fail(ctx, LSH_EINVAL, std::string("unsupported grid size for ") + what);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, LSH_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return LSH_OK;
+}
 
 // ------------------------- kernel timing ---------------------------------
 hipEvent_t take_event(lsh_ctx* ctx) {
@@ -416,7 +426,10 @@ lsh_status build_tables(lsh_ctx* ctx) {
   // Green parameters
   GreenParams& gp = ctx->gp;
   std::memset(&gp, 0, sizeof(gp));
-  gp.variant = ctx->green == LSH_GREEN_TRUNCATED ? kGreenTruncated : kGreenFiltered;
+  gp.variant = ctx->green == LSH_GREEN_TRUNCATED    ? kGreenTruncated
+               : ctx->green == LSH_GREEN_CONSISTENT ? kGreenConsistent
+               : ctx->green == LSH_GREEN_FD         ? kGreenFD
+                                                    : kGreenFiltered;
   for (int a = 0; a < 3; ++a) gp.n[a] = ctx->n[a];
   if (ctx->physics == LSH_SCALAR) {
     double inv[9];
@@ -439,6 +452,22 @@ lsh_status build_tables(lsh_ctx* ctx) {
   HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.ptab32, ctx->h_ptab32.data(), ctx->h_ptab32.size() * sizeof(float),
                         hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.i0, ctx->h_i0.data(), 256, hipMemcpyHostToDevice, ctx->stream));
+  if (ctx->green == LSH_GREEN_CONSISTENT) {
+    const long long nk = main_cpx(ctx->geo) / ctx->c + nyq_cpx(ctx->geo) / ctx->c;
+    const int nb = (int)((nk + 255) / 256);
+    const int ne = ctx->c * (ctx->c + 1) / 2;
+    double* t64 = reinterpret_cast<double*>(ctx->gtab);
+    float* t32 = reinterpret_cast<float*>(ctx->gtab + align_up(sizeof(double) * nk * ne));
+    switch (ctx->c) {
+      case 2: hipLaunchKernelGGL((k_consistent_table<2>), dim3(nb), dim3(256), 0, ctx->stream, ctx->geo, gp,
+                                 ctx->series, t64, t32); break;
+      case 3: hipLaunchKernelGGL((k_consistent_table<3>), dim3(nb), dim3(256), 0, ctx->stream, ctx->geo, gp,
+                                 ctx->series, t64, t32); break;
+      default: hipLaunchKernelGGL((k_consistent_table<6>), dim3(nb), dim3(256), 0, ctx->stream, ctx->geo, gp,
+                                  ctx->series, t64, t32); break;
+    }
+    STCHK(check_launch(ctx, 0, "consistent table"));
+  }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->tables_dirty = false;
   ctx->graph_epoch++;
@@ -478,6 +507,8 @@ lsh_status prepare(lsh_ctx* ctx) {
   if (!ctx->have_phase) return fail(ctx, LSH_ESTATE, "phases not set");
   if (ctx->tables_dirty) STCHK(validate_phases(ctx));
   if (!ctx->ws) return fail(ctx, LSH_ESTATE, "no workspace bound");
+  if (ctx->green == LSH_GREEN_CONSISTENT && !ctx->gtab)
+    return fail(ctx, LSH_ESTATE, "the consistent operator needs a bound table (lsh_bind_green_table)");
   if (!ctx->consts_ready) {
     lsh_status s = upload_consts(ctx);
     if (s != LSH_OK) return s;
@@ -509,6 +540,7 @@ template <> struct Sel<double> {
   static const cpx<double>* tw(lsh_ctx* c, int a) { return c->ptr<cpx<double>>(c->off.tw64) + c->twoff[a]; }
   static const cpx<double>* wt(lsh_ctx* c) { return c->ptr<cpx<double>>(c->off.wt64); }
   static const double* ptab(lsh_ctx* c) { return c->ptr<double>(c->off.ptab64); }
+  static const double* gtab(lsh_ctx* c) { return reinterpret_cast<const double*>(c->gtab); }
 };
 template <> struct Sel<float> {
   static cpx<float>* sm(lsh_ctx* c) { return c->ptr<cpx<float>>(c->off.s32m); }
@@ -516,14 +548,13 @@ template <> struct Sel<float> {
   static const cpx<float>* tw(lsh_ctx* c, int a) { return c->ptr<cpx<float>>(c->off.tw32) + c->twoff[a]; }
   static const cpx<float>* wt(lsh_ctx* c) { return c->ptr<cpx<float>>(c->off.wt32); }
   static const float* ptab(lsh_ctx* c) { return c->ptr<float>(c->off.ptab32); }
+  static const float* gtab(lsh_ctx* c) {
+    if (!c->gtab) return nullptr;
+    const long long nk = main_cpx(c->geo) / c->c + nyq_cpx(c->geo) / c->c;
+    return reinterpret_cast<const float*>(c->gtab + align_up(sizeof(double) * nk * (c->c * (c->c + 1) / 2)));
+  }
 };
 
-lsh_status check_launch(lsh_ctx* ctx, int r, const char* what) {
-  if (r < 0) return fail(ctx, LSH_EINVAL, std::string("unsupported grid size for ") + what);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(ctx, LSH_EHIP, std::string(what) + ": " + hipGetErrorString(e));
-  return LSH_OK;
-}
 
 
 template <typename T> int tv(const lsh_ctx* ctx, int pass) { return ctx->tune[sizeof(T) == 8 ? 1 : 0][pass]; }
@@ -578,7 +609,8 @@ lsh_status forward_part(lsh_ctx* ctx, int l0, int nload, int xmode, const T* src
   }
   {
     Scope sc(ctx, kcls<T>(K_ZG), nl * 2.0 * spec);
-    GreenTabs<T> tb{Sel<T>::wt(ctx), ctx->wstride};
+    GreenTabs<T> tb{Sel<T>::wt(ctx), ctx->wstride, {Sel<T>::tw(ctx, 0), Sel<T>::tw(ctx, 1), Sel<T>::tw(ctx, 2)},
+                    Sel<T>::gtab(ctx)};
     STCHK(check_launch(ctx,
                        launch_zg<T>(ctx->stream, g, ctx->gp, tb, gamma ? Z_GAMMA : Z_FWD, sm, sn, Sel<T>::tw(ctx, 2),
                                     st, nload, tv<T>(ctx, PASS_ZG)),
@@ -968,9 +1000,41 @@ lsh_status lsh_set_phases(lsh_ctx* ctx, const uint8_t* phase, int mem, int nphas
 
 lsh_status lsh_set_green(lsh_ctx* ctx, int variant) {
   if (!ctx) return LSH_EINVAL;
-  if (variant != LSH_GREEN_TRUNCATED && variant != LSH_GREEN_FILTERED)
-    return fail(ctx, LSH_EINVAL, "unknown Green operator");
+  if (variant < LSH_GREEN_TRUNCATED || variant > LSH_GREEN_FD) return fail(ctx, LSH_EINVAL, "unknown Green operator");
+  if (variant == LSH_GREEN_FD && ctx->physics != LSH_SCALAR)
+    return fail(ctx, LSH_EINVAL, "the finite-difference operator is defined for scalar problems only");
   ctx->green = variant;
+  ctx->tables_dirty = true;
+  ctx->have_solution = false;
+  return LSH_OK;
+}
+
+lsh_status lsh_green_table_bytes(const lsh_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return LSH_EINVAL;
+  const long long nk = main_cpx(ctx->geo) / ctx->c + nyq_cpx(ctx->geo) / ctx->c;
+  const int ne = ctx->c * (ctx->c + 1) / 2;
+  *bytes = align_up(sizeof(double) * nk * ne) + align_up(sizeof(float) * nk * ne);
+  return LSH_OK;
+}
+
+lsh_status lsh_bind_green_table(lsh_ctx* ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return LSH_EINVAL;
+  size_t need = 0;
+  lsh_green_table_bytes(ctx, &need);
+  if (!dev_ptr) return fail(ctx, LSH_EINVAL, "null table buffer");
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % kAlign != 0) return fail(ctx, LSH_EINVAL, "table not 256-byte aligned");
+  if (bytes < need) return fail(ctx, LSH_ENOMEM, "table buffer too small: need " + std::to_string(need) + " bytes");
+  ctx->gtab = static_cast<char*>(dev_ptr);
+  ctx->gtab_size = bytes;
+  ctx->tables_dirty = true;
+  ctx->have_solution = false;
+  return LSH_OK;
+}
+
+lsh_status lsh_set_green_series(lsh_ctx* ctx, int nmax) {
+  if (!ctx) return LSH_EINVAL;
+  if (nmax < 0 || nmax > 64) return fail(ctx, LSH_EINVAL, "nmax must be in 0..64");
+  ctx->series = nmax;
   ctx->tables_dirty = true;
   ctx->have_solution = false;
   return LSH_OK;

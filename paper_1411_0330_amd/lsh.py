@@ -22,13 +22,13 @@ STATUS_NAMES = {0: "OK", 1: "MAXIT", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4:
                 -5: "EBREAKDOWN", -6: "ENUMERIC", -7: "ESTATE"}
 SCALAR, ELASTIC = 0, 1
 FP64, MIXED = 0, 1
-TRUNCATED, FILTERED = 0, 1
+TRUNCATED, FILTERED, CONSISTENT, FD = 0, 1, 2, 3
 BASIC, CG = 0, 1
 HOST, DEVICE = 0, 1
 F64, F32 = 0, 1
 TAU, STRAIN = 0, 1
 
-GREEN = {"truncated": TRUNCATED, "filtered": FILTERED}
+GREEN = {"truncated": TRUNCATED, "filtered": FILTERED, "consistent": CONSISTENT, "fd": FD}
 SOLVERS = {"basic": BASIC, "cg": CG}
 PHYSICS = {"scalar": SCALAR, "elastic": ELASTIC}
 PRECISION = {"fp64": FP64, "mixed": MIXED}
@@ -54,6 +54,9 @@ _SIGS = {
     "lsh_set_reference": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "lsh_set_phases": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)]),
     "lsh_set_green": (C.c_int, [C.c_void_p, C.c_int]),
+    "lsh_green_table_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "lsh_bind_green_table": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "lsh_set_green_series": (C.c_int, [C.c_void_p, C.c_int]),
     "lsh_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_double, C.c_int,
                             C.POINTER(LoadReport), C.POINTER(SolveReport)]),
     "lsh_get_field": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int]),
@@ -189,8 +192,20 @@ class Context:
         return self._check(self.lib.lsh_set_phases(self.h, C.c_void_p(ph.ctypes.data), HOST, nphase,
                                                    _dptr(moduli)))
 
-    def set_green(self, variant):
-        return self._check(self.lib.lsh_set_green(self.h, GREEN[variant] if isinstance(variant, str) else variant))
+    def set_green(self, variant, series=None):
+        """Select the Green operator; the consistent one gets a table buffer
+        (owned by this object) and optionally its series cut nmax."""
+        code = GREEN[variant] if isinstance(variant, str) else variant
+        if code == CONSISTENT and getattr(self, "green_table", None) is None:
+            import torch
+            b = C.c_size_t()
+            self._check(self.lib.lsh_green_table_bytes(self.h, C.byref(b)))
+            self.green_table = torch.empty(b.value + 256, dtype=torch.uint8, device=self.device)
+            ptr = (self.green_table.data_ptr() + 255) // 256 * 256
+            self._check(self.lib.lsh_bind_green_table(self.h, C.c_void_p(ptr), b.value))
+        if series is not None:
+            self._check(self.lib.lsh_set_green_series(self.h, int(series)))
+        return self._check(self.lib.lsh_set_green(self.h, code))
 
     # -- solve ---------------------------------------------------------
     def solve(self, loads, solver="cg", tol=1e-10, maxit=1000, allow=(OK, MAXIT)):

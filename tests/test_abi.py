@@ -116,3 +116,22 @@ def test_single_hip_runtime_in_process():
     # the library binds to the runtime PyTorch loaded (shared device pointers and streams)
     L.load()
     assert len(L._hip_runtimes()) == 1
+
+
+def test_green_operator_validation():
+    lib = L.load()
+    st, h = _create(lib, 3, (4, 4, 4), L.ELASTIC)
+    assert lib.lsh_set_green(h, L.FD) == L.EINVAL          # scalar only
+    assert lib.lsh_set_green(h, 7) == L.EINVAL
+    assert lib.lsh_set_green(h, L.CONSISTENT) == L.OK
+    assert lib.lsh_set_green_series(h, -1) == L.EINVAL
+    assert lib.lsh_set_green_series(h, 65) == L.EINVAL
+    b = C.c_size_t()
+    assert lib.lsh_green_table_bytes(h, C.byref(b)) == L.OK
+    nk = 4 * 4 * 2 + 4 * 4
+    assert b.value >= nk * 21 * 12
+    assert lib.lsh_bind_green_table(h, C.c_void_p(4096 * 1024), b.value - 1) == L.ENOMEM
+    lib.lsh_destroy(h)
+    st, h = _create(lib, 2, (8, 8))
+    assert lib.lsh_set_green(h, L.FD) == L.OK
+    lib.lsh_destroy(h)

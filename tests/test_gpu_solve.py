@@ -202,3 +202,22 @@ def test_graph_replay_matches_eager(lsh, precision):
         ctx.solve(w2.loads, "basic", tol=1e-10, maxit=3000)
         res.append(ctx.effective())
     assert np.array_equal(res[0], res[1])
+
+
+def test_fd_and_consistent_solves_match_oracle(lsh):
+    w = I.disk_workload(32, "truncated")
+    for variant, a0s in (("fd", (0.5, 5.5)), ("consistent", (5.5,))):
+        vals = []
+        for a0 in a0s:
+            pb = problem(w.phase, w.moduli, a0 * np.eye(2), "scalar", variant)
+            pb.series = 6
+            A_ref, _ = _oracle_effective(pb, w.loads)
+            ctx = lsh.Context(w.phase.shape, "scalar", "fp64", max_loads=2)
+            ctx.set_reference(a0 * np.eye(2))
+            ctx.set_phases(w.phase, w.moduli)
+            ctx.set_green(variant, series=6)
+            A, rep = _gpu_effective(ctx, w.loads, tol=1e-12)
+            assert rel_max_err(A, A_ref) <= 1e-10
+            vals.append(A[0, 0])
+        if variant == "fd":   # Table 1: independent of A0
+            assert abs(vals[0] - vals[1]) < 1e-10

@@ -202,3 +202,25 @@ def test_operator_kernel_shape_variants(lsh, monkeypatch, physics, shape, varian
     out = ctx.apply(to_dev(tau, dtype)).cpu().numpy()
     ref = np.stack([op.apply(pb, tau[l]) for l in range(2)])
     assert rel_max_err(out, ref) <= (1e-12 if dtype == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("physics,shape,variant,series", [
+    ("scalar", (16, 32), "fd", 8),
+    ("scalar", (8, 16, 4), "fd", 8),
+    ("scalar", (16, 16), "consistent", 6),
+    ("scalar", (8, 8, 8), "consistent", 3),
+    ("elastic", (4, 8, 8), "consistent", 2),
+])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fd_and_consistent_operators_match_oracle(lsh, physics, shape, variant, series, dtype):
+    ph, moduli, A0 = _op_setup(physics, shape, variant, "aniso-A0" if physics == "scalar" else "")
+    pb = problem(ph, moduli, A0, physics, variant)
+    pb.series = series
+    ctx = lsh.Context(shape, physics, "mixed" if dtype == "f32" else "fp64", max_loads=2)
+    ctx.set_reference(A0)
+    ctx.set_phases(ph, moduli)
+    ctx.set_green(variant, series=series)
+    tau = I.random_field(shape, pb.c, 2, seed=13)
+    out = ctx.apply(to_dev(tau, dtype)).cpu().numpy()
+    ref = np.stack([op.apply(pb, tau[l]) for l in range(2)])
+    assert rel_max_err(out, ref) <= (1e-12 if dtype == "f64" else 1e-5)

@@ -268,3 +268,32 @@ def test_disk_within_hashin_shtrikman():
     a = effective.mean_stress(w.A0, [1, 0], tau)[0]
     lo, hi = cf.hashin_shtrikman_scalar(w.phase.mean(), 10.0, 1.0, 2)
     assert lo <= a <= hi
+
+
+def test_fd_and_consistent_operators_solve_and_fd_is_a0_independent():
+    # Table 1: the finite-difference scheme does not depend on A0
+    w = I.disk_workload(16)
+    vals = []
+    for a0 in (0.4, 5.5, 20.0):
+        pb = op.Problem(w.phase, w.moduli, a0 * np.eye(2), "scalar", "fd")
+        tau = solvers.cg(pb, [1.0, 0.0], tol=1e-13, maxit=3000)["tau"]
+        vals.append(effective.mean_stress(pb.A0, [1.0, 0.0], tau)[0])
+    assert max(vals) - min(vals) < 1e-10
+    # both operators: FFT route = dense eq. (12) route, laminate exact
+    ph = I.laminate((4, 16), 0, [(1, 6), (0, 10)])
+    mod = np.stack([I.scalar_isotropic(1.0, 2), I.scalar_isotropic(10.0, 2)])
+    harm, arith = cf.scalar_laminate([10 / 16, 6 / 16], [1.0, 10.0])
+    pb = op.Problem(ph, mod, 0.5 * np.eye(2), "scalar", "fd")
+    A = effective.effective_matrix(pb.A0, np.eye(2), [solvers.cg(pb, p, tol=1e-13)["tau"] for p in np.eye(2)])
+    np.testing.assert_allclose(A, [[harm, 0], [0, arith]], atol=1e-9)
+    # the cut consistent series converges slowly to the exact laminate (eq. 11)
+    errs = []
+    for nmax in (1, 4, 16):
+        pb = op.Problem(ph, mod, 0.5 * np.eye(2), "scalar", "consistent", series=nmax)
+        A = effective.effective_matrix(pb.A0, np.eye(2), [solvers.cg(pb, p, tol=1e-13)["tau"] for p in np.eye(2)])
+        errs.append(np.abs(A - [[harm, 0], [0, arith]]).max())
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 0.02
+    for variant in ("fd", "consistent"):
+        pbr = op.Problem(I.random_phases((6, 4), 2, seed=1), mod, 0.5 * np.eye(2), "scalar", variant, series=3)
+        p = np.array([1.0, 0.3])
+        np.testing.assert_allclose(solvers.cg(pbr, p, tol=1e-13)["tau"], dense.solve(pbr, p), atol=1e-10)
