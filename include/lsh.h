@@ -80,7 +80,8 @@ typedef struct {
  * Create a context for a grid of n[0] x n[1] (x n[2]) voxels along x, y (, z)
  * (the unit cell (0,1)^dim with h_a = 1/n[a], Section 3.1).
  *   dim        2 or 3 (elasticity needs 3).
- *   n          voxels per axis; each a power of two, n[0] >= 4, n[1], n[2] >= 2, all <= 1024.
+ *   n          voxels per axis; each a power of two (n[0] >= 4, n[1], n[2] >= 2, all
+ *              <= 1024) or one of 48, 96, 192 (3 * 2^m) and 80, 160 (5 * 2^m).
  *   physics    LSH_SCALAR or LSH_ELASTIC.
  *   precision  LSH_FP64: FP64 fields, transforms and reductions.
  *              LSH_MIXED: FP32 fields and transforms with FP64 dot products,

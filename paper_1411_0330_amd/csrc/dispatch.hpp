@@ -1,5 +1,5 @@
-// Launchers of the transform passes, dispatched on the (power-of-two) axis
-// lengths to the compile-time kernel instances.  Each launcher returns the
+// Launchers of the transform passes, dispatched on the axis lengths (powers
+// of two, and 3 or 5 times a power of two) to the compile-time kernel instances.  Each launcher returns the
 // number of workgroups along x of the grid it queued (the number of partial
 // sums a reducing kernel wrote per load), or -1 for an unsupported size.
 #pragma once
@@ -16,14 +16,25 @@ template <typename T> constexpr int min_tx() { return sizeof(T) == 4 ? 16 : 8; }
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
-// points per thread
-template <typename T> constexpr int p_xfwd(int mx) { return cmin(8, mx); }
+// points per thread.  For an axis length F 2^m with F = 3 or 5 the points per
+// thread are F 2^a (the first FFT stage then has radix F 2^a): 2^a = 4 where
+// the exchange buffer of the row passes stays within 48 KiB, else 2.
+template <typename T> constexpr int p_odd(int n, int q) {
+  const int f = odd_part(n);
+  while (q > 2 && 256 * f * q * 2 * (int)sizeof(T) > 48 * 1024) q /= 2;
+  return f * cmin(q, pow2_part(n));
+}
+template <typename T> constexpr int p_xfwd(int mx) { return odd_part(mx) > 1 ? p_odd<T>(mx, 4) : cmin(8, mx); }
 template <typename T, int C> constexpr int p_xinv(int mx) {
   // six components: fewer points per thread keep the register file for occupancy
+  if (odd_part(mx) > 1) return p_odd<T>(mx, C == 6 ? 2 : 4);
   return cmin(C == 6 ? (sizeof(T) == 8 ? 2 : 4) : 8, mx);
 }
-template <typename T> constexpr int p_y(int n) { return cmin(sizeof(T) == 4 ? 16 : 8, n); }
+template <typename T> constexpr int p_y(int n) {
+  return odd_part(n) > 1 ? p_odd<T>(n, 4) : cmin(sizeof(T) == 4 ? 16 : 8, n);
+}
 template <typename T, int C> constexpr int p_z(int n) {
+  if (odd_part(n) > 1) return p_odd<T>(n, C == 6 ? 2 : 4);
   return cmin(C == 6 ? (sizeof(T) == 4 ? 8 : 4) : (sizeof(T) == 4 ? 16 : 8), n);
 }
 

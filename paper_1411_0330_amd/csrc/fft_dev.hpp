@@ -73,11 +73,108 @@ __device__ __forceinline__ V twc(V v) {
   }
 }
 
-// In-place R-point DFT of a register array (R a power of two <= 64):
+constexpr int pow2_part(int n) {
+  int r = 1;
+  while (n > 0 && n % 2 == 0) {
+    n /= 2;
+    r *= 2;
+  }
+  return r;
+}
+constexpr int odd_part(int n) { return n / pow2_part(n); }
+
+// v * exp(DIR * 2 pi i M / L) for a period L dividing 64 or 960.
+template <int M, int L, int DIR, typename V>
+__device__ __forceinline__ V twl(V v) {
+  if constexpr (64 % L == 0) {
+    return twc<(M % L) * (64 / L), DIR>(v);
+  } else {
+    static_assert(960 % L == 0, "twiddle period must divide 960");
+    constexpr int m = (M % L) * (960 / L);
+    if constexpr (m == 0) {
+      return v;
+    } else if constexpr (4 * m == 960) {
+      return DIR < 0 ? mul_neg_i(v) : mul_i(v);
+    } else if constexpr (2 * m == 960) {
+      return V{-v.x, -v.y};
+    } else if constexpr (4 * m == 3 * 960) {
+      return DIR < 0 ? mul_i(v) : mul_neg_i(v);
+    } else {
+      using T = decltype(v.x);
+      const T c = static_cast<T>(kCos960[m]);
+      const T s = static_cast<T>(DIR * kSin960[m]);
+      return V{v.x * c - v.y * s, v.x * s + v.y * c};
+    }
+  }
+}
+
+// In-place DFT of odd prime length F (3 or 5) by pairing x_n with x_{F-n}:
+// with b_n = x_n + x_{F-n} and d_n = x_n - x_{F-n},
+//   X_k = x_0 + sum_n cos(2 pi n k / F) b_n + i DIR sum_n sin(2 pi n k / F) d_n,
+// and X_{F-k} is the same with the sine sum negated.
+template <int F, int DIR, typename V>
+__device__ __forceinline__ void dft_odd(V* a) {
+  using T = decltype(a[0].x);
+  constexpr int H = (F - 1) / 2;
+  V b[H + 1], d[H + 1];
+  V x0 = a[0];
+  static_for<1, H + 1>([&](auto n_) {
+    constexpr int n = decltype(n_)::value;
+    b[n] = cadd(a[n], a[F - n]);
+    d[n] = csub(a[n], a[F - n]);
+    x0 = cadd(x0, b[n]);
+  });
+  static_for<1, H + 1>([&](auto k_) {
+    constexpr int k = decltype(k_)::value;
+    V A = a[0], B = V{0, 0};
+    static_for<1, H + 1>([&](auto n_) {
+      constexpr int n = decltype(n_)::value;
+      constexpr int m = ((n * k) % F) * (960 / F);
+      const T c = static_cast<T>(kCos960[m]);
+      const T s = static_cast<T>(kSin960[m]);
+      A = V{A.x + c * b[n].x, A.y + c * b[n].y};
+      B = V{B.x + s * d[n].x, B.y + s * d[n].y};
+    });
+    const V iB = DIR < 0 ? mul_neg_i(B) : mul_i(B);
+    a[k] = cadd(A, iB);
+    a[F - k] = csub(A, iB);
+  });
+  a[0] = x0;
+}
+
+// In-place R-point DFT of a register array.  R a power of two <= 64:
 // radix-2 decimation in frequency, then a compile-time bit reversal.
+// R = F Q with F in {3, 5} and Q a power of two: with n = n1 + Q n2 and
+// k = k2 + F k1, F-point DFTs over n2, twiddles W_R^{n1 k2}, then Q-point
+// DFTs over n1.
 template <int R, int DIR, typename V>
 __device__ __forceinline__ void dft(V* a) {
-  if constexpr (R == 2) {
+  if constexpr (odd_part(R) != 1) {
+    constexpr int F = odd_part(R), Q = R / F;
+    static_assert(F == 3 || F == 5, "odd radix must be 3 or 5");
+    if constexpr (Q == 1) {
+      dft_odd<F, DIR>(a);
+    } else {
+      V y[Q][F];
+      static_for<0, Q>([&](auto n1_) {
+        constexpr int n1 = decltype(n1_)::value;
+        V u[F];
+        static_for<0, F>([&](auto n2_) { u[decltype(n2_)::value] = a[n1 + Q * decltype(n2_)::value]; });
+        dft_odd<F, DIR>(u);
+        static_for<0, F>([&](auto k2_) {
+          constexpr int k2 = decltype(k2_)::value;
+          y[n1][k2] = twl<n1 * k2, R, DIR>(u[k2]);
+        });
+      });
+      static_for<0, F>([&](auto k2_) {
+        constexpr int k2 = decltype(k2_)::value;
+        V w[Q];
+        static_for<0, Q>([&](auto n1_) { w[decltype(n1_)::value] = y[decltype(n1_)::value][k2]; });
+        dft<Q, DIR>(w);
+        static_for<0, Q>([&](auto k1_) { a[k2 + F * decltype(k1_)::value] = w[decltype(k1_)::value]; });
+      });
+    }
+  } else if constexpr (R == 2) {
     const V u = a[0], w = a[1];
     a[0] = cadd(u, w);
     a[1] = csub(u, w);
@@ -111,6 +208,10 @@ __device__ __forceinline__ void dft(V* a) {
 // ---------------------------------------------------------------------------
 // Pencil FFT (Stockham autosort, radix P with a smaller last radix).
 //
+// N = F 2^m with F in {1, 3, 5}; P = F 2^a must divide N.  The first stage
+// has radix P (the odd factor included), every later stage the power-of-two
+// part of P (the last one possibly smaller).
+//
 // An N-point pencil is spread over TT = N/P threads; thread t holds
 // v[j] = x[t + TT*j] on entry and X[t + TT*j] on exit.  Stages exchange data
 // through `lds` (element e at lds[e*es]); the stage of span NS and radix R
@@ -123,7 +224,9 @@ template <int N, int P, int NS, int DIR, typename T>
 __device__ __forceinline__ void fft_stages(cpx<T> (&v)[P], int t, cpx<T>* lds, int es, const cpx<T>* __restrict__ tw,
                                            int tstride) {
   if constexpr (NS < N) {
-    constexpr int R = (N / NS < P) ? N / NS : P;
+    constexpr int P2 = pow2_part(P);
+    constexpr int R = (NS == 1) ? P : ((N / NS < P2) ? N / NS : P2);
+    static_assert(N % (NS * R) == 0, "pencil length must be a multiple of the stage spans");
     constexpr int TT = N / P;
     constexpr bool last = (NS * R == N);
     static_for<0, P / R>([&](auto i_) {
@@ -134,7 +237,7 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[P], int t, cpx<T>* lds, i
         u[r] = v[i + r * (P / R)];
       });
       const int b = t + TT * i;
-      const int k = b & (NS - 1);
+      const int k = b % NS;
       if constexpr (NS > 1) {
         static_for<1, R>([&](auto r_) {
           constexpr int r = decltype(r_)::value;
@@ -172,7 +275,8 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[P], int t, cpx<T>* lds, i
 template <int N, int P, int DIR, typename T>
 __device__ __forceinline__ void fft_pencil(cpx<T> (&v)[P], int t, cpx<T>* lds, int es, const cpx<T>* __restrict__ tw,
                                            int tstride) {
-  static_assert(P <= N || N == 1, "points per thread exceed the pencil length");
+  static_assert(N == 1 || (P <= N && N % P == 0 && odd_part(N) == odd_part(P)),
+                "points per thread must divide the pencil length and carry its odd factor");
   fft_stages<N, P, 1, DIR, T>(v, t, lds, es, tw, tstride);
 }
 

@@ -40,6 +40,11 @@ int launch_xfwd(hipStream_t s, const XfwdArgs<T>& a, int nload, int v) {
     case 128: return xfwd_one<T, 128>(s, a, nload, v);
     case 256: return xfwd_one<T, 256>(s, a, nload);
     case 512: return xfwd_one<T, 512>(s, a, nload);
+    case 24: return xfwd_one<T, 24>(s, a, nload);
+    case 48: return xfwd_one<T, 48>(s, a, nload);
+    case 96: return xfwd_one<T, 96>(s, a, nload);
+    case 40: return xfwd_one<T, 40>(s, a, nload);
+    case 80: return xfwd_one<T, 80>(s, a, nload);
     default: return -1;
   }
 }
@@ -87,6 +92,11 @@ int launch_xinv(hipStream_t s, const XinvArgs<T>& a, int nload, int v) {
     case 128: return xinv_c<T, 128>(s, a, nload, v);
     case 256: return xinv_c<T, 256>(s, a, nload, v);
     case 512: return xinv_c<T, 512>(s, a, nload, v);
+    case 24: return xinv_c<T, 24>(s, a, nload, v);
+    case 48: return xinv_c<T, 48>(s, a, nload, v);
+    case 96: return xinv_c<T, 96>(s, a, nload, v);
+    case 40: return xinv_c<T, 40>(s, a, nload, v);
+    case 80: return xinv_c<T, 80>(s, a, nload, v);
     default: return -1;
   }
 }

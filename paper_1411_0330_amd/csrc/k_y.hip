@@ -55,6 +55,11 @@ static int y_dir(hipStream_t s, const Geo& g, cpx<T>* sm, cpx<T>* sn, const cpx<
     case 256: return y_one<T, 256, DIR>(s, g, sm, sn, tw, st, nload, v);
     case 512: return y_one<T, 512, DIR>(s, g, sm, sn, tw, st, nload);
     case 1024: return y_one<T, 1024, DIR>(s, g, sm, sn, tw, st, nload);
+    case 48: return y_one<T, 48, DIR>(s, g, sm, sn, tw, st, nload);
+    case 96: return y_one<T, 96, DIR>(s, g, sm, sn, tw, st, nload);
+    case 192: return y_one<T, 192, DIR>(s, g, sm, sn, tw, st, nload);
+    case 80: return y_one<T, 80, DIR>(s, g, sm, sn, tw, st, nload);
+    case 160: return y_one<T, 160, DIR>(s, g, sm, sn, tw, st, nload);
     default: return -1;
   }
 }

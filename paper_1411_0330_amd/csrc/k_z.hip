@@ -56,6 +56,11 @@ static int z_c(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTa
     case 256: return z_one<T, 256, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload, v);
     case 512: return z_one<T, 512, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
     case 1024: return z_one<T, 1024, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    case 48: return z_one<T, 48, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    case 96: return z_one<T, 96, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    case 192: return z_one<T, 192, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    case 80: return z_one<T, 80, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
+    case 160: return z_one<T, 160, C>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);
     default: return -1;
   }
 }

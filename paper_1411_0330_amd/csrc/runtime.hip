@@ -22,6 +22,12 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
+// axis lengths with compiled transform instances: powers of two up to 1024,
+// and 48, 96, 192 (3 * 2^m), 80, 160 (5 * 2^m)
+bool supported_axis(long long v) {
+  if (is_pow2(v)) return v <= 1024;
+  return v == 48 || v == 96 || v == 192 || v == 80 || v == 160;
+}
 
 // ---------------------------------------------------------------------------
 // small dense linear algebra on the host (c <= 6)
@@ -872,7 +878,7 @@ lsh_status lsh_create(lsh_ctx** out, int dim, const int64_t* n, int physics, int
   if (precision != LSH_FP64 && precision != LSH_MIXED) return LSH_EINVAL;
   if (max_loads < 1 || max_loads > 65535) return LSH_EINVAL;
   for (int a = 0; a < dim; ++a) {
-    if (!is_pow2(n[a]) || n[a] > 1024) return LSH_EINVAL;
+    if (!supported_axis(n[a])) return LSH_EINVAL;
     if (a == 0 && n[a] < 4) return LSH_EINVAL;
     if (a > 0 && n[a] < 2) return LSH_EINVAL;
   }

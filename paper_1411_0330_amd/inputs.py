@@ -111,18 +111,19 @@ def _paint_sphere(phase, centre_zyx, radius, value=1):
     return newly
 
 
-def boolean_spheres(n: int, radius: float, fraction: float, seed: int = 0):
+def boolean_spheres(n, radius: float, fraction: float, seed: int = 0):
     """Boolean model: overlapping spheres of ``radius`` voxels with continuous
-    uniform centres in [0, n)^3.  The sphere count is fixed so that the
-    expected volume fraction is ``fraction``:
-    ``round(-ln(1-f) * n^3 / (4/3 pi r^3))``.
+    uniform centres in the periodic box (an ``n``^3 cube, or ``n`` = (nz, ny,
+    nx)).  The sphere count is fixed so that the expected volume fraction is
+    ``fraction``: ``round(-ln(1-f) * V / (4/3 pi r^3))``.
 
     Returns ``(phase, centres)``."""
+    shape = (n, n, n) if np.isscalar(n) else tuple(int(v) for v in n)
     rng = np.random.default_rng(seed)
     vol = 4.0 / 3.0 * math.pi * radius ** 3
-    count = int(round(-math.log(1.0 - fraction) * n ** 3 / vol))
-    centres = rng.uniform(0.0, n, size=(count, 3))  # (z, y, x)
-    phase = np.zeros((n, n, n), dtype=np.uint8)
+    count = int(round(-math.log(1.0 - fraction) * float(np.prod(shape)) / vol))
+    centres = rng.uniform(0.0, 1.0, size=(count, 3)) * np.array(shape, dtype=np.float64)  # (z, y, x)
+    phase = np.zeros(shape, dtype=np.uint8)
     for c in centres:
         _paint_sphere(phase, c, radius)
     return phase, centres

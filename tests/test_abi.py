@@ -34,7 +34,11 @@ def test_library_exports_every_header_symbol():
     (3, (4, 2, 2), L.ELASTIC, True),
     (3, (1024, 1024, 1024), L.ELASTIC, True),
     (2, (64, 64), L.ELASTIC, False),        # elasticity is 3D
-    (2, (48, 64), L.SCALAR, False),         # not a power of two
+    (2, (48, 64), L.SCALAR, True),          # 3 * 2^4
+    (3, (96, 160, 192), L.ELASTIC, True),   # mixed radix 3 and 5
+    (2, (40, 64), L.SCALAR, False),         # no transform compiled for 40
+    (2, (64, 100), L.SCALAR, False),        # odd factor 25
+    (3, (8, 8, 384), L.SCALAR, False),      # 3 * 2^7 not compiled
     (2, (2, 64), L.SCALAR, False),          # nx >= 4
     (3, (8, 8, 2048), L.SCALAR, False),     # at most 1024
     (4, (8, 8, 8), L.SCALAR, False),
