@@ -44,9 +44,8 @@ def assemble(pb: op.Problem):
     K = real_space_kernel(pb)
     shape = pb.shape
     c = pb.c
-    _, dinv, in_i0 = op.phase_tables(pb)
-    flat_phase = pb.phase.ravel()
-    i0 = np.nonzero(in_i0[flat_phase])[0]
+    _, dinv, in_i0 = op.voxel_tables(pb)
+    i0 = np.nonzero(in_i0)[0]
     coords = np.array(np.unravel_index(i0, shape)).T
     n = i0.size
     M = np.zeros((n * c, n * c))
@@ -54,7 +53,7 @@ def assemble(pb: op.Problem):
         diff = (ca[None, :] - coords) % np.array(shape)[None, :]
         blocks = K[tuple(diff.T)]                 # (n, c, c): Gamma_{beta_a - gamma}
         M[a * c:(a + 1) * c, :] = blocks.transpose(1, 0, 2).reshape(c, n * c)
-        M[a * c:(a + 1) * c, a * c:(a + 1) * c] += dinv[flat_phase[i0[a]]]
+        M[a * c:(a + 1) * c, a * c:(a + 1) * c] += dinv[i0[a]]
     return M, i0
 
 

@@ -13,7 +13,8 @@ vanish there.
 
 This oracle uses full complex FFTs (scipy.fft, a library primitive) over the
 whole grid, a per-voxel generic matrix inverse for (A_beta - A0)^{-1}, and
-the Green tables of ``oracle.green``.  The real part of the inverse transform
+the Green tables of ``oracle.green``.  A problem is given either by a phase
+map with one modulus per phase or by one modulus per voxel (``voxel``).  The real part of the inverse transform
 is returned after checking the imaginary part is at rounding level.
 """
 from __future__ import annotations
@@ -35,6 +36,7 @@ class Problem:
     physics: str           # "scalar" | "elastic"
     green: str = "filtered"
     series: int = 8        # consistent operator: alias cut nmax
+    voxel: np.ndarray | None = None   # (*grid, c, c) per-voxel moduli; replaces phase/moduli
 
     @property
     def shape(self):
@@ -77,8 +79,31 @@ def phase_tables(pb: Problem):
     return delta, dinv, in_i0
 
 
+def voxel_tables(pb: Problem):
+    """Per voxel (flattened grid order): delta = A_beta - A0, its inverse
+    (zero outside I0) and membership of I0, with the checks of
+    ``phase_tables`` applied voxel by voxel."""
+    c = pb.c
+    if pb.voxel is None:
+        delta, dinv, in_i0 = phase_tables(pb)
+        ph = pb.phase.ravel()
+        return delta[ph], dinv[ph], in_i0[ph]
+    D = np.asarray(pb.voxel, dtype=np.float64).reshape(-1, c, c) - np.asarray(pb.A0)
+    in_i0 = np.any(D != 0.0, axis=(1, 2))
+    ev = np.linalg.eigvalsh(0.5 * (D + D.transpose(0, 2, 1)))
+    definite = np.all(ev > 0, axis=1) | np.all(ev < 0, axis=1)
+    bad = np.nonzero(in_i0 & ~definite)[0]
+    if bad.size:
+        raise ValueError(f"voxel {bad[0]}: A - A0 is not definite (hypothesis (2))")
+    dinv = np.zeros_like(D)
+    dinv[in_i0] = np.linalg.inv(D[in_i0])
+    return D, dinv, in_i0
+
+
 def mask(pb: Problem) -> np.ndarray:
     """Indicator of I0 on the grid."""
+    if pb.voxel is not None:
+        return voxel_tables(pb)[2].reshape(pb.shape)
     _, _, in_i0 = phase_tables(pb)
     return in_i0[pb.phase]
 
@@ -128,6 +153,11 @@ def gamma_apply(pb: Problem, tau: np.ndarray, slab: int = 16) -> np.ndarray:
 
 def local_apply(pb: Problem, tau: np.ndarray, which: str = "inverse") -> np.ndarray:
     """Per-voxel (A_beta - A0)^{-1} tau_beta (``inverse``) or (A_beta - A0) tau_beta."""
+    if pb.voxel is not None:
+        delta, dinv, _ = voxel_tables(pb)
+        M = dinv if which == "inverse" else delta
+        t = tau.reshape(pb.c, -1)
+        return np.einsum("vij,jv->iv", M, t).reshape(tau.shape)
     delta, dinv, _ = phase_tables(pb)
     M = dinv if which == "inverse" else delta
     return np.einsum("...ij,j...->i...", M[pb.phase], tau)
