@@ -124,6 +124,25 @@ lsh_status lsh_set_reference(lsh_ctx* ctx, const double* A0);
 lsh_status lsh_set_phases(lsh_ctx* ctx, const uint8_t* phase, int mem, int nphase,
                           const double* moduli);
 
+/*
+ * Microstructure given voxel by voxel (instead of lsh_set_phases), isotropic
+ * at every voxel: m is [ncoef][z][y][x] in host or device memory, element type
+ * dtype (LSH_F64 or LSH_F32):
+ *   scalar      ncoef = 1: a_beta, A_beta = a_beta Id;
+ *   elasticity  ncoef = 2: bulk and shear moduli (K_beta, mu_beta), Mandel
+ *               stiffness K m m^T + 2 mu (Id - m m^T / 3), m = (1,1,1,0,0,0).
+ * Needs the reference set first, isotropic (scalar A0 = a0 Id, else
+ * LSH_EINVAL), and a bound workspace; the voxel data are converted during the
+ * call into the short form of (A_beta - A0)^{-1} (Section 3.1, eq. 13), so
+ * changing A0 afterwards asks for the moduli again (LSH_ESTATE at solve time).
+ * Hypothesis (2) per voxel: A_beta = A0 exactly (outside I0), or
+ * a_beta - a0 nonzero, or K_beta - K0 and mu_beta - mu0 nonzero and of one sign;
+ * differences below 1e-12 of the moduli, and non-finite values, give
+ * LSH_EHYP2 with the context unchanged.  Host data are checked on the host,
+ * device data by a counting kernel before anything is written.
+ */
+lsh_status lsh_set_voxel_moduli(lsh_ctx* ctx, const void* m, int dtype, int mem, int ncoef);
+
 /* Discrete Green operator: truncated (eqs. 14/15 with the Nyquist rule of
  * Section 3.2.1), filtered (Section 3.2.2), consistent (eq. 11, stored; needs a
  * bound table, see below) or finite-difference (Section 3.2.3, scalar physics
@@ -173,6 +192,22 @@ lsh_status lsh_get_field(lsh_ctx* ctx, int load, int which, void* dst, int dtype
 /* Mean stress A0 p_l + <tau_l> of the last solve, host FP64 array nload x c.
  * With the c unit loads, row l is column l of the homogenised matrix A*_h. */
 lsh_status lsh_get_effective(lsh_ctx* ctx, double* sigma_mean);
+
+/*
+ * Derivative of J = sum_lm W_lm p_l . A*_h p_m over the loads of the last solve
+ * (W: host FP64 nload x nload, symmetrised as (W + W^T)/2) with respect to the
+ * isotropic coefficients of every voxel.  The operator M of eq. (13) is
+ * symmetric and only its local block (A_beta - A0)^{-1} depends on A_beta, so
+ * with A*_h p = A0 p + <tau_p> (Theorem 4)
+ *   dJ/dA_beta = (1/V) sum_lm W_lm sym(eps_l (x) eps_m),  eps = p - Gamma tau,
+ * which costs one operator pass per load and no further solve.  Written to
+ * grad (device, [ncoef][z][y][x], LSH_F64 or LSH_F32):
+ *   scalar      dJ/da  = tr(dJ/dA_beta);
+ *   elasticity  dJ/dK  = m^T (dJ/dA_beta) m,  dJ/dmu = 2 (tr - m^T (.) m / 3).
+ * Valid for phase maps and per-voxel moduli alike (the derivative is then the
+ * one of an isotropic perturbation of each voxel).  LSH_ESTATE without a solve.
+ */
+lsh_status lsh_gradient(lsh_ctx* ctx, const double* W, void* grad, int dtype);
 
 /*
  * Matrix-free operator of eq. (13): out_l = 1_{I0} ((A - A0)^{-1} tau_l + Gamma tau_l)

@@ -314,6 +314,7 @@ struct XinvArgs {
   float* rout;            // FP32 residual (refinement)
   const T* ptab;          // [nphase][2 c c + 5], see phase_row
   const uint8_t* phase;
+  const T* vcoef;         // per-voxel mode: [2][nvox] (a_inv, b_inv), else null
   const double* loads;    // [load][c]
   const LoadState* st;
   double* partials;
@@ -341,6 +342,31 @@ __device__ __forceinline__ T phase_row(const T* tb, int which, bool iso, int j, 
   return r;
 }
 
+// Local operator of one voxel: a row of the phase table, or (per-voxel mode)
+// the short form a_inv Id + b_inv m m^T of (A_beta - A0)^{-1} with its
+// inverse a_dir = 1/a_inv, b_dir = -b_inv / (a_inv (a_inv + 3 b_inv)).
+// a_inv = 0 marks a voxel outside I0.
+template <typename T>
+struct Loc {
+  const T* tb;
+  T in, ai, bi;
+};
+
+template <typename T, int C>
+__device__ __forceinline__ T loc_row(const Loc<T>& L, bool vm, int which, bool iso, int j, const T (&v)[C]) {
+  if (!vm) return phase_row<T, C>(L.tb, which, iso, j, v);
+  T a = L.ai, b = L.bi;
+  if (which == 1) {
+    const bool z = a == T(0);
+    const T ad = z ? T(0) : T(1) / a;
+    b = (C == 6 && !z) ? -b / (a * (a + T(3) * b)) : T(0);
+    a = ad;
+  }
+  T r = a * v[j];
+  if (C == 6 && j < 3) r += b * (v[0] + v[1] + v[2]);
+  return r;
+}
+
 template <typename T, int MX, int P, int C>
 __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
   constexpr int TR = MX / P;
@@ -361,6 +387,7 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
   const long long vrc = valid ? vr : 0;
   cpx<T>* lrow = lds + slot * MX;
   const bool iso = a.iso != 0;
+  const bool vm = a.vcoef != nullptr;
 
   // all components' spectrum rows are loaded before the first transform
   cpx<T> gam[C][P];
@@ -426,16 +453,26 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
         t1[j] = tv.y;
       }
     }
-    const uint16_t ph2 = *reinterpret_cast<const uint16_t*>(a.phase + vox);
-    const T* tb0 = tab + (ph2 & 0xff) * TABW;
-    const T* tb1 = tab + (ph2 >> 8) * TABW;
-    const T in0 = tb0[2 * C * C], in1 = tb1[2 * C * C];
+    Loc<T> L0, L1;
+    if (vm) {
+      const cpx<T> ai = *reinterpret_cast<const cpx<T>*>(a.vcoef + vox);
+      const cpx<T> bi = *reinterpret_cast<const cpx<T>*>(a.vcoef + g.nvox + vox);
+      L0 = Loc<T>{nullptr, ai.x != T(0) ? T(1) : T(0), ai.x, bi.x};
+      L1 = Loc<T>{nullptr, ai.y != T(0) ? T(1) : T(0), ai.y, bi.y};
+    } else {
+      const uint16_t ph2 = *reinterpret_cast<const uint16_t*>(a.phase + vox);
+      const T* tb0 = tab + (ph2 & 0xff) * TABW;
+      const T* tb1 = tab + (ph2 >> 8) * TABW;
+      L0 = Loc<T>{tb0, tb0[2 * C * C], T(0), T(0)};
+      L1 = Loc<T>{tb1, tb1[2 * C * C], T(0), T(0)};
+    }
+    const T in0 = L0.in, in1 = L1.in;
     cpx<T> res[C];
     if (a.mode == XI_APPLY || a.mode == XI_CG) {
 #pragma unroll
       for (int j = 0; j < C; ++j)
-        res[j] = cpx<T>{in0 * (phase_row<T, C>(tb0, 0, iso, j, t0) + g0[j]),
-                        in1 * (phase_row<T, C>(tb1, 0, iso, j, t1) + g1[j])};
+        res[j] = cpx<T>{in0 * (loc_row<T, C>(L0, vm, 0, iso, j, t0) + g0[j]),
+                        in1 * (loc_row<T, C>(L1, vm, 0, iso, j, t1) + g1[j])};
 #pragma unroll
       for (int j = 0; j < C; ++j) part += (double)t0[j] * res[j].x + (double)t1[j] * res[j].y;
     } else if (a.mode == XI_BASIC) {
@@ -448,16 +485,16 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
       }
 #pragma unroll
       for (int j = 0; j < C; ++j) {
-        res[j] = cpx<T>{in0 * phase_row<T, C>(tb0, 1, iso, j, u0), in1 * phase_row<T, C>(tb1, 1, iso, j, u1)};
-        const double rx = in0 * (u0[j] - phase_row<T, C>(tb0, 0, iso, j, t0));
-        const double ry = in1 * (u1[j] - phase_row<T, C>(tb1, 0, iso, j, t1));
+        res[j] = cpx<T>{in0 * loc_row<T, C>(L0, vm, 1, iso, j, u0), in1 * loc_row<T, C>(L1, vm, 1, iso, j, u1)};
+        const double rx = in0 * (u0[j] - loc_row<T, C>(L0, vm, 0, iso, j, t0));
+        const double ry = in1 * (u1[j] - loc_row<T, C>(L1, vm, 0, iso, j, t1));
         part += rx * rx + ry * ry;
       }
     } else if (a.mode == XI_IRRES || a.mode == XI_RESNORM) {
 #pragma unroll
       for (int j = 0; j < C; ++j) {
-        res[j] = cpx<T>{in0 * (pl[j] - phase_row<T, C>(tb0, 0, iso, j, t0) - g0[j]),
-                        in1 * (pl[j] - phase_row<T, C>(tb1, 0, iso, j, t1) - g1[j])};
+        res[j] = cpx<T>{in0 * (pl[j] - loc_row<T, C>(L0, vm, 0, iso, j, t0) - g0[j]),
+                        in1 * (pl[j] - loc_row<T, C>(L1, vm, 0, iso, j, t1) - g1[j])};
         part += (double)res[j].x * res[j].x + (double)res[j].y * res[j].y;
       }
     } else {  // XI_STRAIN: p - Gamma tau everywhere
@@ -644,12 +681,13 @@ __global__ __launch_bounds__(256) void k_xflush(const long long nvec, T* __restr
   }
 }
 
-// x = 0;  r = 1_{I0} p_l;  partial ||r||^2
+// x = 0;  r = 1_{I0} p_l;  partial ||r||^2 (I0 from the phase flags, or from
+// a_inv != 0 in per-voxel mode)
 template <typename T>
 __global__ __launch_bounds__(256) void k_cginit(const Geo g, T* __restrict__ x, T* __restrict__ r,
                                                 const uint8_t* __restrict__ phase, const uint8_t* __restrict__ i0,
-                                                const double* __restrict__ loads, double* __restrict__ partials,
-                                                const int pstride) {
+                                                const double* __restrict__ vcoef, const double* __restrict__ loads,
+                                                double* __restrict__ partials, const int pstride) {
   __shared__ double red[4];
   const int l = blockIdx.y;
   const long long F = field_elems(g);
@@ -661,7 +699,8 @@ __global__ __launch_bounds__(256) void k_cginit(const Geo g, T* __restrict__ x, 
     if (e < F) {
       const int j = (int)(e / g.nvox);
       const long long vox = e - (long long)j * g.nvox;
-      const T val = i0[phase[vox]] ? static_cast<T>(loads[l * g.c + j]) : T(0);
+      const bool inside = vcoef != nullptr ? vcoef[vox] != 0.0 : i0[phase[vox]] != 0;
+      const T val = inside ? static_cast<T>(loads[l * g.c + j]) : T(0);
       if (x != nullptr) x[(long long)l * F + e] = T(0);
       if (r != nullptr) r[(long long)l * F + e] = val;
       part += (double)val * val;
@@ -710,6 +749,109 @@ __global__ __launch_bounds__(256) void k_mean(const Geo g, const T* __restrict__
   }
   const double s = block_sum<256>(part, red);
   if (threadIdx.x == 0) partials[(long long)grp * pstride + blockIdx.x] = s;
+}
+
+// ----------------------------------------------------------------------------
+// Per-voxel isotropic moduli.  Input m[ncoef][nvox]: a (scalar, A = a Id) or
+// bulk and shear moduli (K, mu) (elasticity, Mandel form).  Against the
+// isotropic reference (a0, or K0 and mu0), (A - A0)^{-1} = a_inv Id + b_inv m m^T
+// with a_inv = 1/(a - a0), b_inv = 0 (scalar) or a_inv = 1/(2 dmu),
+// b_inv = 1/(9 dK) - 1/(6 dmu) (elasticity).  Hypothesis (2): A - A0 is zero
+// (voxel outside I0, a_inv = b_inv = 0) or definite: a - a0 != 0, or dK and
+// dmu nonzero of one sign.  Differences below 1e-12 of the moduli count as
+// singular.  With out64 == null the kernel only counts violations (one partial
+// per workgroup) over voxels [v0, vend); otherwise it writes the coefficients
+// (FP64, and FP32 when out32 is given).
+// ----------------------------------------------------------------------------
+template <typename TI>
+__global__ __launch_bounds__(256) void k_voxset(const long long v0, const long long vend, const long long nvox,
+                                                const int elastic, const TI* __restrict__ m, const double a0,
+                                                const double K0, const double mu0, double* __restrict__ out64,
+                                                float* __restrict__ out32, double* __restrict__ partials) {
+  __shared__ double red[4];
+  const long long v = v0 + (long long)blockIdx.x * 256 + threadIdx.x;
+  double bad = 0.0;
+  if (v < vend) {
+    double ai = 0.0, bi = 0.0;
+    if (!elastic) {
+      const double a = (double)m[v];
+      const double d = a - a0;
+      if (!isfinite(a)) bad = 1.0;
+      else if (d != 0.0) {
+        if (fabs(d) <= 1e-12 * (fabs(a) + fabs(a0))) bad = 1.0;
+        else ai = 1.0 / d;
+      }
+    } else {
+      const double K = (double)m[v], mu = (double)m[nvox + v];
+      const double dK = K - K0, dm = mu - mu0;
+      if (!isfinite(K) || !isfinite(mu)) {
+        bad = 1.0;
+      } else if (dK != 0.0 || dm != 0.0) {
+        const bool tiny = fabs(dK) <= 1e-12 * (fabs(K) + fabs(K0)) || fabs(dm) <= 1e-12 * (fabs(mu) + fabs(mu0));
+        if (tiny || (dK > 0.0) != (dm > 0.0)) {
+          bad = 1.0;
+        } else {
+          ai = 1.0 / (2.0 * dm);
+          bi = 1.0 / (9.0 * dK) - 1.0 / (6.0 * dm);
+        }
+      }
+    }
+    if (out64 != nullptr) {
+      out64[v] = ai;
+      out64[nvox + v] = bi;
+      if (out32 != nullptr) {
+        out32[v] = (float)ai;
+        out32[nvox + v] = (float)bi;
+      }
+    }
+  }
+  if (out64 == nullptr) {
+    const double s = block_sum<256>(bad, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Gradient of J = sum_lm W_lm p_l . A*_h p_m with respect to the isotropic
+// coefficients of every voxel, from the strain estimates eps_l = p_l - Gamma tau_l
+// of the solved loads (eps[load][c][nvox]):
+//   scalar:      dJ/da  = (1/V) sum_lm W_lm eps_l . eps_m
+//   elasticity:  dJ/dK  = (1/V) sum_lm W_lm tr eps_l tr eps_m,
+//                dJ/dmu = (2/V) sum_lm W_lm (eps_l . eps_m - tr eps_l tr eps_m / 3)
+// (Mandel dot products).  W is symmetric; its zero entries are skipped.
+// ----------------------------------------------------------------------------
+template <int C, typename TO>
+__global__ __launch_bounds__(256) void k_grad(const Geo g, const int nload, const double* __restrict__ eps,
+                                              const double* __restrict__ W, TO* __restrict__ grad) {
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (v >= g.nvox) return;
+  const long long F = field_elems(g);
+  double ee = 0.0, tt = 0.0;
+  for (int l = 0; l < nload; ++l) {
+    double el[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) el[j] = eps[(long long)l * F + (long long)j * g.nvox + v];
+    for (int m = l; m < nload; ++m) {
+      const double w = (m == l ? 1.0 : 2.0) * W[l * nload + m];
+      if (w == 0.0) continue;
+      double dot = 0.0, trm = 0.0;
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const double em = (m == l) ? el[j] : eps[(long long)m * F + (long long)j * g.nvox + v];
+        dot += el[j] * em;
+        if (C == 6 && j < 3) trm += em;
+      }
+      ee += w * dot;
+      if (C == 6) tt += w * (el[0] + el[1] + el[2]) * trm;
+    }
+  }
+  const double iv = 1.0 / (double)g.nvox;
+  if (C == 6) {
+    grad[v] = static_cast<TO>(tt * iv);
+    grad[g.nvox + v] = static_cast<TO>(2.0 * (ee - tt / 3.0) * iv);
+  } else {
+    grad[v] = static_cast<TO>(ee * iv);
+  }
 }
 
 template <typename TI, typename TO>

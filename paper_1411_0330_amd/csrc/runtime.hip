@@ -110,10 +110,10 @@ struct KTimer {
 // are split by element type (FP32 / FP64).
 const char* kClassNames[] = {"xfwd_f32",   "xfwd_f64",   "y_f32",   "y_f64",   "zgamma_f32",
                              "zgamma_f64", "xinv_f32",   "xinv_f64", "cg_update_f32", "cg_update_f64",
-                             "scalars",    "init",       "mean",     "copy"};
+                             "scalars",    "init",       "mean",     "copy",          "gradient"};
 enum KClass {
   K_XFWD = 0, K_Y = 2, K_ZG = 4, K_XINV = 6, K_CGUPD = 8,  // + 1 for FP64
-  K_SCAL = 10, K_INIT, K_MEAN, K_COPY, K_NCLASS
+  K_SCAL = 10, K_INIT, K_MEAN, K_COPY, K_GRAD, K_NCLASS
 };
 template <typename T> constexpr int kcls(int base) { return base + (sizeof(T) == 8 ? 1 : 0); }
 
@@ -143,14 +143,15 @@ struct lsh_ctx {
   size_t gtab_size = 0;
   int series = 8;
   int iso = 0;  // every phase matrix has the short form (see phase_row)
+  bool mat_voxel = false;  // material given per voxel (lsh_set_voxel_moduli) instead of per phase
   int tune[2][NPASS] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // kernel-shape variant per (FP32/FP64, pass)
 
   // workspace
   char* ws = nullptr;
   size_t ws_need = 0, ws_size = 0;
   struct {
-    size_t x64, r64, p64, d32, r32, p32, s64m, s64n, s32m, s32n, phase, i0, ptab64, ptab32, tw64, tw32, wt64, wt32,
-        loads, st_out, st_in, partials, sums, end;
+    size_t x64, r64, p64, d32, r32, p32, s64m, s64n, s32m, s32n, phase, i0, ptab64, ptab32, vc64, vc32, tw64, tw32,
+        wt64, wt32, loads, wgrad, st_out, st_in, partials, sums, end;
   } off{};
   long long pstride = 0, nsums = 0;
   int twoff[3] = {0, 0, 0};
@@ -297,6 +298,8 @@ void compute_layout(lsh_ctx* ctx) {
   const int tabw = 2 * ctx->c * ctx->c + 5;
   ctx->off.ptab64 = take(sizeof(double) * kMaxPhases * tabw);
   ctx->off.ptab32 = take(sizeof(float) * kMaxPhases * tabw);
+  ctx->off.vc64 = take(sizeof(double) * 2 * V);
+  ctx->off.vc32 = mixed ? take(sizeof(float) * 2 * V) : 0;
   const int ntw = ctx->n[0] + ctx->n[1] + ctx->n[2];
   ctx->twoff[0] = 0;
   ctx->twoff[1] = ctx->n[0];
@@ -307,6 +310,7 @@ void compute_layout(lsh_ctx* ctx) {
   ctx->off.wt64 = take(2 * sizeof(double) * 3 * ctx->wstride);
   ctx->off.wt32 = take(2 * sizeof(float) * 3 * ctx->wstride);
   ctx->off.loads = take(sizeof(double) * L * c);
+  ctx->off.wgrad = take(sizeof(double) * L * L);
   ctx->off.st_out = take(sizeof(LoadState) * L);
   ctx->off.st_in = take(sizeof(LoadState) * L);
   // partial sums: the largest grid of any reducing kernel, per group
@@ -426,7 +430,7 @@ lsh_status build_tables(lsh_ctx* ctx) {
     }
     ctx->h_i0[p] = 1;
   }
-  ctx->iso = all_iso ? 1 : 0;
+  ctx->iso = (all_iso || ctx->mat_voxel) ? 1 : 0;
   for (size_t i = 0; i < ctx->h_ptab64.size(); ++i) ctx->h_ptab32[i] = (float)ctx->h_ptab64[i];
 
   // Green parameters
@@ -510,8 +514,8 @@ lsh_status validate_phases(lsh_ctx* ctx) {
 
 lsh_status prepare(lsh_ctx* ctx) {
   if (!ctx->have_ref) return fail(ctx, LSH_ESTATE, "reference medium not set");
-  if (!ctx->have_phase) return fail(ctx, LSH_ESTATE, "phases not set");
-  if (ctx->tables_dirty) STCHK(validate_phases(ctx));
+  if (!ctx->have_phase) return fail(ctx, LSH_ESTATE, "material (phases or per-voxel moduli) not set");
+  if (ctx->tables_dirty && !ctx->mat_voxel) STCHK(validate_phases(ctx));
   if (!ctx->ws) return fail(ctx, LSH_ESTATE, "no workspace bound");
   if (ctx->green == LSH_GREEN_CONSISTENT && !ctx->gtab)
     return fail(ctx, LSH_ESTATE, "the consistent operator needs a bound table (lsh_bind_green_table)");
@@ -519,7 +523,7 @@ lsh_status prepare(lsh_ctx* ctx) {
     lsh_status s = upload_consts(ctx);
     if (s != LSH_OK) return s;
   }
-  if (ctx->phase_dirty) {
+  if (ctx->phase_dirty && !ctx->mat_voxel) {
     const size_t V = (size_t)ctx->geo.nvox;
     if (ctx->phase_dev_src) {
       HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.phase, ctx->phase_dev_src, V, hipMemcpyDeviceToDevice, ctx->stream));
@@ -546,6 +550,7 @@ template <> struct Sel<double> {
   static const cpx<double>* tw(lsh_ctx* c, int a) { return c->ptr<cpx<double>>(c->off.tw64) + c->twoff[a]; }
   static const cpx<double>* wt(lsh_ctx* c) { return c->ptr<cpx<double>>(c->off.wt64); }
   static const double* ptab(lsh_ctx* c) { return c->ptr<double>(c->off.ptab64); }
+  static const double* vc(lsh_ctx* c) { return c->mat_voxel ? c->ptr<double>(c->off.vc64) : nullptr; }
   static const double* gtab(lsh_ctx* c) { return reinterpret_cast<const double*>(c->gtab); }
 };
 template <> struct Sel<float> {
@@ -554,6 +559,7 @@ template <> struct Sel<float> {
   static const cpx<float>* tw(lsh_ctx* c, int a) { return c->ptr<cpx<float>>(c->off.tw32) + c->twoff[a]; }
   static const cpx<float>* wt(lsh_ctx* c) { return c->ptr<cpx<float>>(c->off.wt32); }
   static const float* ptab(lsh_ctx* c) { return c->ptr<float>(c->off.ptab32); }
+  static const float* vc(lsh_ctx* c) { return c->mat_voxel ? c->ptr<float>(c->off.vc32) : nullptr; }
   static const float* gtab(lsh_ctx* c) {
     if (!c->gtab) return nullptr;
     const long long nk = main_cpx(c->geo) / c->c + nyq_cpx(c->geo) / c->c;
@@ -647,6 +653,7 @@ lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T*
   a.rout = rout;
   a.ptab = Sel<T>::ptab(ctx);
   a.phase = ctx->ptr<uint8_t>(ctx->off.phase);
+  a.vcoef = Sel<T>::vc(ctx);
   a.loads = ctx->ptr<double>(ctx->off.loads) + (long long)l0 * ctx->c;
   a.st = st;
   a.partials = partials;
@@ -654,7 +661,8 @@ lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T*
   a.scale = static_cast<T>(1.0 / (double)g.nvox);
   const double nl = std::min(ctx->nact, nload);
   const double cvs = (double)ctx->F * sizeof(T);
-  double bytes = cvs + 2.0 * sizeof(T) * (double)nyq_cpx(g) + (double)g.nvox;  // spectrum + phase ids
+  // spectrum + material (phase ids, or two coefficients per voxel)
+  double bytes = cvs + 2.0 * sizeof(T) * (double)nyq_cpx(g) + (ctx->mat_voxel ? 2.0 * sizeof(T) : 1.0) * g.nvox;
   if (mode != XI_STRAIN) bytes += cvs;                                          // the field transformed
   if (mode == XI_IRRES) bytes += 4.0 * ctx->F;                                  // FP32 residual out
   else if (mode != XI_RESNORM) bytes += cvs;                                    // real output
@@ -679,7 +687,7 @@ lsh_status cg_init(lsh_ctx* ctx, int nload, T* x, T* r, LoadState* st, double to
   {
     Scope sc(ctx, K_INIT);
     hipLaunchKernelGGL((k_cginit<T>), dim3(nb, nload), dim3(256), 0, ctx->stream, g, x, r,
-                       ctx->ptr<uint8_t>(ctx->off.phase), ctx->ptr<uint8_t>(ctx->off.i0),
+                       ctx->ptr<uint8_t>(ctx->off.phase), ctx->ptr<uint8_t>(ctx->off.i0), Sel<double>::vc(ctx),
                        ctx->ptr<double>(ctx->off.loads), ctx->ptr<double>(ctx->off.partials), (int)ctx->pstride);
     STCHK(check_launch(ctx, 0, "init"));
   }
@@ -857,6 +865,74 @@ lsh_status effective(lsh_ctx* ctx, int nload) {
   return LSH_OK;
 }
 
+// Isotropic reference of per-voxel mode: a0 (scalar, A0 = a0 Id) or (K0, mu0).
+bool isotropic_reference(const lsh_ctx* ctx, double* a0, double* K0, double* mu0) {
+  const int c = ctx->c;
+  if (ctx->physics == LSH_ELASTIC) {
+    const double lam0 = ctx->A0[1];
+    *mu0 = 0.5 * ctx->A0[3 * 6 + 3];
+    *K0 = lam0 + 2.0 * *mu0 / 3.0;
+    *a0 = 0.0;
+    return true;
+  }
+  *a0 = ctx->A0[0];
+  *K0 = *mu0 = 0.0;
+  for (int i = 0; i < c; ++i)
+    for (int j = 0; j < c; ++j)
+      if (std::fabs(ctx->A0[i * c + j] - (i == j ? *a0 : 0.0)) > 1e-14 * std::fabs(*a0)) return false;
+  return true;
+}
+
+// Hypothesis (2) for one voxel of per-voxel mode (the rule of k_voxset).
+bool voxel_admissible(bool elastic, double x, double y, double a0, double K0, double mu0) {
+  if (!elastic) {
+    const double d = x - a0;
+    if (!std::isfinite(x)) return false;
+    return d == 0.0 || std::fabs(d) > 1e-12 * (std::fabs(x) + std::fabs(a0));
+  }
+  if (!std::isfinite(x) || !std::isfinite(y)) return false;
+  const double dK = x - K0, dm = y - mu0;
+  if (dK == 0.0 && dm == 0.0) return true;
+  const bool tiny = std::fabs(dK) <= 1e-12 * (std::fabs(x) + std::fabs(K0)) ||
+                    std::fabs(dm) <= 1e-12 * (std::fabs(y) + std::fabs(mu0));
+  return !tiny && ((dK > 0.0) == (dm > 0.0));
+}
+
+template <typename TI>
+lsh_status voxel_setup(lsh_ctx* ctx, const TI* m, bool count_only, long long* nbad) {
+  double a0, K0, mu0;
+  isotropic_reference(ctx, &a0, &K0, &mu0);
+  const long long V = ctx->geo.nvox;
+  const int nb = (int)((V + 255) / 256);
+  const int el = ctx->physics == LSH_ELASTIC ? 1 : 0;
+  if (count_only) {
+    // one partial per workgroup; the partials buffer holds at least L c pstride doubles
+    const long long cap = (long long)ctx->max_loads * ctx->c * ctx->pstride;
+    double* parts = ctx->ptr<double>(ctx->off.partials);
+    std::vector<double> h;
+    long long bad = 0;
+    for (long long b0 = 0; b0 < nb; b0 += cap) {
+      const long long nbk = std::min<long long>(cap, nb - b0);
+      const long long v0 = b0 * 256;
+      hipLaunchKernelGGL((k_voxset<TI>), dim3((unsigned)nbk), dim3(256), 0, ctx->stream, v0,
+                         std::min(V, v0 + nbk * 256), V, el, m, a0, K0, mu0, nullptr, nullptr, parts);
+      STCHK(check_launch(ctx, 0, "voxel check"));
+      h.resize((size_t)nbk);
+      HIPCHK(hipMemcpyAsync(h.data(), parts, sizeof(double) * nbk, hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      for (double x : h) bad += (long long)x;
+    }
+    *nbad = bad;
+    return LSH_OK;
+  }
+  float* o32 = ctx->precision == LSH_MIXED ? ctx->ptr<float>(ctx->off.vc32) : nullptr;
+  hipLaunchKernelGGL((k_voxset<TI>), dim3(nb), dim3(256), 0, ctx->stream, 0LL, V, V, el, m, a0, K0, mu0,
+                     ctx->ptr<double>(ctx->off.vc64), o32, ctx->ptr<double>(ctx->off.partials));
+  STCHK(check_launch(ctx, 0, "voxel moduli"));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return LSH_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -928,7 +1004,8 @@ lsh_status lsh_bind_workspace(lsh_ctx* ctx, void* dev_ptr, size_t bytes) {
   if (bytes < ctx->ws_need)
     return fail(ctx, LSH_ENOMEM, "workspace too small: need " + std::to_string(ctx->ws_need) + " bytes");
   if (ctx->have_phase && ctx->phase_host.empty())
-    return fail(ctx, LSH_ESTATE, "device phase map must be set again after rebinding the workspace");
+    return fail(ctx, LSH_ESTATE,
+                "a device phase map or per-voxel moduli must be set again after rebinding the workspace");
   ctx->ws = static_cast<char*>(dev_ptr);
   ctx->ws_size = bytes;
   ctx->graph_epoch++;
@@ -966,6 +1043,7 @@ lsh_status lsh_set_reference(lsh_ctx* ctx, const double* A0) {
   }
   ctx->A0.assign(A0, A0 + c * c);
   ctx->have_ref = true;
+  if (ctx->mat_voxel) ctx->have_phase = false;  // per-voxel coefficients were formed against the old A0
   ctx->tables_dirty = true;
   ctx->have_solution = false;
   return LSH_OK;
@@ -997,10 +1075,109 @@ lsh_status lsh_set_phases(lsh_ctx* ctx, const uint8_t* phase, int mem, int nphas
   }
   ctx->nphase = nphase;
   ctx->moduli.assign(moduli, moduli + (size_t)nphase * c * c);
+  ctx->mat_voxel = false;
   ctx->have_phase = true;
   ctx->phase_dirty = true;
   ctx->tables_dirty = true;
   ctx->have_solution = false;
+  return LSH_OK;
+}
+
+lsh_status lsh_set_voxel_moduli(lsh_ctx* ctx, const void* m, int dtype, int mem, int ncoef) {
+  if (!ctx) return LSH_EINVAL;
+  if (!m) return fail(ctx, LSH_EINVAL, "null moduli");
+  if (dtype != LSH_F64 && dtype != LSH_F32) return fail(ctx, LSH_EINVAL, "bad dtype");
+  if (mem != LSH_HOST && mem != LSH_DEVICE) return fail(ctx, LSH_EINVAL, "bad memory space");
+  const bool el = ctx->physics == LSH_ELASTIC;
+  if (ncoef != (el ? 2 : 1))
+    return fail(ctx, LSH_EINVAL, el ? "elasticity takes two coefficients per voxel (K, mu)"
+                                    : "scalar problems take one coefficient per voxel");
+  if (!ctx->have_ref) return fail(ctx, LSH_ESTATE, "set the reference medium before per-voxel moduli");
+  double a0, K0, mu0;
+  if (!isotropic_reference(ctx, &a0, &K0, &mu0))
+    return fail(ctx, LSH_EINVAL, "per-voxel moduli need an isotropic reference A0 = a0 Id");
+  if (!ctx->ws) return fail(ctx, LSH_ESTATE, "bind the workspace before setting per-voxel moduli");
+  const long long V = ctx->geo.nvox;
+  const size_t es = dtype == LSH_F64 ? sizeof(double) : sizeof(float);
+  const void* src = m;
+  if (mem == LSH_HOST) {
+    for (long long v = 0; v < V; ++v) {
+      double x, y = 0.0;
+      if (dtype == LSH_F64) {
+        x = static_cast<const double*>(m)[v];
+        if (el) y = static_cast<const double*>(m)[V + v];
+      } else {
+        x = static_cast<const float*>(m)[v];
+        if (el) y = static_cast<const float*>(m)[V + v];
+      }
+      if (!voxel_admissible(el, x, y, a0, K0, mu0))
+        return fail(ctx, LSH_EHYP2, "voxel " + std::to_string(v) +
+                                        ": A - A0 is neither zero nor definite, or not finite (hypothesis (2))");
+    }
+    // staged through the FP64 spectrum buffer (at least c nvox doubles)
+    HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.s64m, m, es * ncoef * V, hipMemcpyHostToDevice, ctx->stream));
+    src = ctx->ws + ctx->off.s64m;
+  } else {
+    long long nbad = 0;
+    if (dtype == LSH_F64) STCHK(voxel_setup<double>(ctx, static_cast<const double*>(m), true, &nbad));
+    else STCHK(voxel_setup<float>(ctx, static_cast<const float*>(m), true, &nbad));
+    if (nbad > 0)
+      return fail(ctx, LSH_EHYP2, std::to_string(nbad) +
+                                      " voxels have A - A0 neither zero nor definite, or not finite (hypothesis (2))");
+  }
+  if (dtype == LSH_F64) STCHK(voxel_setup<double>(ctx, static_cast<const double*>(src), false, nullptr));
+  else STCHK(voxel_setup<float>(ctx, static_cast<const float*>(src), false, nullptr));
+  ctx->mat_voxel = true;
+  ctx->nphase = 0;
+  ctx->phase_host.clear();
+  ctx->phase_dev_src = nullptr;
+  ctx->have_phase = true;
+  ctx->phase_dirty = false;
+  ctx->tables_dirty = true;
+  ctx->have_solution = false;
+  return LSH_OK;
+}
+
+lsh_status lsh_gradient(lsh_ctx* ctx, const double* W, void* grad, int dtype) {
+  if (!ctx) return LSH_EINVAL;
+  if (!W || !grad) return fail(ctx, LSH_EINVAL, "null weights or gradient buffer");
+  if (dtype != LSH_F64 && dtype != LSH_F32) return fail(ctx, LSH_EINVAL, "bad dtype");
+  if (!ctx->have_solution) return fail(ctx, LSH_ESTATE, "no solution");
+  const int L = ctx->last_nload;
+  std::vector<double> w((size_t)L * L);
+  for (int i = 0; i < L; ++i)
+    for (int j = 0; j < L; ++j) {
+      if (!std::isfinite(W[i * L + j])) return fail(ctx, LSH_EINVAL, "non-finite weight");
+      w[(size_t)i * L + j] = 0.5 * (W[i * L + j] + W[j * L + i]);
+    }
+  ctx->nact = 1 << 30;
+  // strain estimates p_l - Gamma tau_l of every solved load, in the FP64 spectrum buffer
+  double* x = ctx->ptr<double>(ctx->off.x64);
+  double* eps = reinterpret_cast<double*>(Sel<double>::sm(ctx));
+  STCHK(forward_part<double>(ctx, 0, L, XF_PLAIN, x, nullptr, nullptr, nullptr, nullptr, true));
+  STCHK(inverse_x<double>(ctx, 0, L, XI_STRAIN, x, eps, nullptr, nullptr, nullptr, nullptr));
+  HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.wgrad, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice,
+                        ctx->stream));
+  const Geo& g = ctx->geo;
+  const int nb = (int)((g.nvox + 255) / 256);
+  const double* wd = ctx->ptr<double>(ctx->off.wgrad);
+  {
+    Scope sc(ctx, K_GRAD, (double)L * ctx->F * 8.0 + (ctx->c == 6 ? 2.0 : 1.0) * g.nvox * (dtype == LSH_F64 ? 8 : 4));
+#define LSH_GRAD(CC, TO) \
+  hipLaunchKernelGGL((k_grad<CC, TO>), dim3(nb), dim3(256), 0, ctx->stream, g, L, eps, wd, static_cast<TO*>(grad))
+    if (dtype == LSH_F64) {
+      if (ctx->c == 2) LSH_GRAD(2, double);
+      else if (ctx->c == 3) LSH_GRAD(3, double);
+      else LSH_GRAD(6, double);
+    } else {
+      if (ctx->c == 2) LSH_GRAD(2, float);
+      else if (ctx->c == 3) LSH_GRAD(3, float);
+      else LSH_GRAD(6, float);
+    }
+#undef LSH_GRAD
+    STCHK(check_launch(ctx, 0, "gradient"));
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
   return LSH_OK;
 }
 

@@ -271,3 +271,30 @@ def elastic_rsa_workload(n: int = 256, seed: int = 0, green: str = "filtered",
     return Workload("elastic_rsa3d", "elastic", ph, np.stack([Cm, Ci]),
                     elastic_isotropic_mandel(lam0, mu0), green, unit_loads(6), tol,
                     {"fraction": float(ph.mean()), "spheres": int(len(centres)), "seed": seed})
+
+
+@dataclass
+class GradientWorkload:
+    """Per-voxel elasticity for sensitivity studies: a smoothed Gaussian field
+    theta sets Young's modulus E = 1 + 9 sigmoid(theta) at fixed Poisson's
+    ratio; the reference medium (E0, nu0), the loads and the weights W of the
+    scalar J = sum_lm W_lm p_l . C* p_m are part of the workload."""
+    theta: np.ndarray       # (NZ, NY, NX)
+    nu: float
+    A0: np.ndarray          # (6, 6) Mandel
+    green: str
+    loads: np.ndarray       # (nload, 6)
+    W: np.ndarray           # (nload, nload)
+    tol: float
+
+
+def gradient_workload(n: int = 192, corr_length: float = 2.0, seed: int = 0) -> GradientWorkload:
+    """192^3 by default; theta with correlation length 2 voxels, nu = 0.3,
+    reference E0 = 0.5, nu0 = 0.3, filtered operator, loads e_1 and the Mandel
+    shear unit e_6 with W = diag(1, 1/2), so that J = C*_1111 + C*_1212, FP64
+    tolerance 1e-10."""
+    theta = gaussian_random_field((n, n, n), corr_length, seed)
+    lam0, mu0 = lame_from_young(0.5, 0.3)
+    loads = unit_loads(6)[[0, 5]]
+    return GradientWorkload(theta, 0.3, elastic_isotropic_mandel(lam0, mu0), "filtered", loads,
+                            np.diag([1.0, 0.5]), 1e-10)

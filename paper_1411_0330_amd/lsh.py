@@ -53,6 +53,8 @@ _SIGS = {
     "lsh_bind_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "lsh_set_reference": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "lsh_set_phases": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)]),
+    "lsh_set_voxel_moduli": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    "lsh_gradient": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p, C.c_int]),
     "lsh_set_green": (C.c_int, [C.c_void_p, C.c_int]),
     "lsh_green_table_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "lsh_bind_green_table": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
@@ -192,6 +194,44 @@ class Context:
         return self._check(self.lib.lsh_set_phases(self.h, C.c_void_p(ph.ctypes.data), HOST, nphase,
                                                    _dptr(moduli)))
 
+    def set_voxel_moduli(self, coef):
+        """Per-voxel isotropic coefficients (ncoef, *shape): a (scalar) or
+        (K, mu) (elasticity); a torch tensor on the device or a host array,
+        float64 or float32."""
+        ncoef = 2 if self.physics == "elastic" else 1
+        if hasattr(coef, "data_ptr"):
+            import torch
+            assert coef.dtype in (torch.float64, torch.float32)
+            coef = coef.contiguous()
+            code = F64 if coef.dtype == torch.float64 else F32
+            mem = DEVICE if coef.is_cuda else HOST
+            ptr = coef.data_ptr()
+            keep = coef
+        else:
+            keep = np.ascontiguousarray(coef)
+            if keep.dtype not in (np.float64, np.float32):
+                keep = keep.astype(np.float64)
+            code = F64 if keep.dtype == np.float64 else F32
+            mem, ptr = HOST, keep.ctypes.data
+        if tuple(keep.shape) != (ncoef,) + self.shape:
+            raise ValueError(f"expected coefficients of shape {(ncoef,) + self.shape}, got {tuple(keep.shape)}")
+        st = self._check(self.lib.lsh_set_voxel_moduli(self.h, C.c_void_p(ptr), code, mem, ncoef))
+        self.solves = getattr(self, "solves", 0) + 1
+        return st
+
+    def gradient(self, W, dtype="f64"):
+        """dJ/d(coefficients) for J = sum_lm W_lm p_l . A* p_m over the loads of
+        the last solve: a device tensor (ncoef, *shape)."""
+        import torch
+        W = np.ascontiguousarray(np.atleast_2d(W), dtype=np.float64)
+        if W.shape != (self.nload, self.nload):
+            raise ValueError(f"W must be {self.nload} x {self.nload}")
+        ncoef = 2 if self.physics == "elastic" else 1
+        out = torch.empty((ncoef,) + self.shape, dtype=torch.float64 if dtype == "f64" else torch.float32,
+                          device=self.device)
+        self._check(self.lib.lsh_gradient(self.h, _dptr(W), C.c_void_p(out.data_ptr()), F64 if dtype == "f64" else F32))
+        return out
+
     def set_green(self, variant, series=None):
         """Select the Green operator; the consistent one gets a table buffer
         (owned by this object) and optionally its series cut nmax."""
@@ -217,6 +257,7 @@ class Context:
                                 C.byref(summ))
         self._check(st, allow=allow)
         self.nload = nload
+        self.solves = getattr(self, "solves", 0) + 1
         return {
             "status": st,
             "iterations": [r.iterations for r in reps],

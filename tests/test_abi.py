@@ -139,3 +139,47 @@ def test_green_operator_validation():
     st, h = _create(lib, 2, (8, 8))
     assert lib.lsh_set_green(h, L.FD) == L.OK
     lib.lsh_destroy(h)
+
+
+def test_voxel_moduli_and_gradient_validation():
+    # error paths only: each returns before any device work
+    lib = L.load()
+    dp = lambda a: np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(C.POINTER(C.c_double))
+    st, h = _create(lib, 2, (8, 8))
+    good = np.full((1, 8, 8), 3.0)
+    vp = C.c_void_p(good.ctypes.data)
+    assert lib.lsh_set_voxel_moduli(h, vp, L.F64, L.HOST, 1) == L.ESTATE       # no reference yet
+    assert lib.lsh_set_reference(h, dp(np.eye(2))) == L.OK
+    assert lib.lsh_set_voxel_moduli(h, vp, L.F64, L.HOST, 1) == L.ESTATE       # no workspace
+    b = C.c_size_t()
+    lib.lsh_workspace_bytes(h, C.byref(b))
+    assert lib.lsh_bind_workspace(h, C.c_void_p(4096 * 1024), b.value) == L.OK
+    assert lib.lsh_set_voxel_moduli(h, vp, L.F64, L.HOST, 2) == L.EINVAL       # scalar: one coefficient
+    assert lib.lsh_set_voxel_moduli(h, vp, 7, L.HOST, 1) == L.EINVAL
+    assert lib.lsh_set_voxel_moduli(h, None, L.F64, L.HOST, 1) == L.EINVAL
+    bad = good.copy()
+    bad[0, 2, 3] = 1.0 + 1e-14          # a - a0 nonzero but below the singularity threshold
+    assert lib.lsh_set_voxel_moduli(h, C.c_void_p(bad.ctypes.data), L.F64, L.HOST, 1) == L.EHYP2
+    bad[0, 2, 3] = np.nan
+    assert lib.lsh_set_voxel_moduli(h, C.c_void_p(bad.ctypes.data), L.F64, L.HOST, 1) == L.EHYP2
+    assert lib.lsh_set_reference(h, dp([[1.0, 0.2], [0.2, 1.0]])) == L.OK
+    assert lib.lsh_set_voxel_moduli(h, vp, L.F64, L.HOST, 1) == L.EINVAL       # anisotropic A0
+    W = np.eye(1)
+    g = np.zeros(64)
+    assert lib.lsh_gradient(h, dp(W), C.c_void_p(g.ctypes.data), L.F64) == L.ESTATE   # no solution
+    assert lib.lsh_gradient(h, None, C.c_void_p(g.ctypes.data), L.F64) == L.EINVAL
+    lib.lsh_destroy(h)
+    # elasticity: (K, mu) of opposite signs against the reference is indefinite
+    st, h = _create(lib, 3, (4, 4, 4), L.ELASTIC)
+    lam0, mu0 = I.lame_from_young(0.5, 0.3)
+    assert lib.lsh_set_reference(h, dp(I.elastic_isotropic_mandel(lam0, mu0))) == L.OK
+    lib.lsh_workspace_bytes(h, C.byref(b))
+    assert lib.lsh_bind_workspace(h, C.c_void_p(4096 * 1024), b.value) == L.OK
+    K0 = lam0 + 2 * mu0 / 3
+    m = np.stack([np.full((4, 4, 4), 2.0), np.full((4, 4, 4), 1.0)])
+    m[0, 1, 1, 1] = 0.5 * K0
+    assert lib.lsh_set_voxel_moduli(h, C.c_void_p(m.ctypes.data), L.F64, L.HOST, 1) == L.EINVAL
+    assert lib.lsh_set_voxel_moduli(h, C.c_void_p(m.ctypes.data), L.F64, L.HOST, 2) == L.EHYP2
+    m32 = m.astype(np.float32)
+    assert lib.lsh_set_voxel_moduli(h, C.c_void_p(m32.ctypes.data), L.F32, L.HOST, 2) == L.EHYP2
+    lib.lsh_destroy(h)
