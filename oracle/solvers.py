@@ -78,3 +78,108 @@ def basic(pb: op.Problem, p, tol: float = 1e-10, maxit: int = 10000, history=Non
         if rel <= tol:
             break
     return {"tau": tau, "iters": it, "rel_res": rel}
+
+
+def minres(pb: op.Problem, p, tol: float = 1e-10, maxit: int = 1000, history=None):
+    """MINRES of Paige and Saunders (1975) on L tau = b, tau_0 = 0, for the
+    symmetric but possibly indefinite system that eq. (13) becomes when A0 is
+    not softer than every phase.
+
+    Lanczos vectors v_k (v_1 = b/||b||) tridiagonalise L; Givens rotations
+    (c_k, s_k) reduce the tridiagonal matrix to upper bidiagonal form, and the
+    iterate minimises ||b - L tau||_2 over the Krylov space.  With the
+    rotation of the previous step applied to the new column (beta_k, alpha_k,
+    beta_{k+1}):
+        delta2_k = c_{k-1} delta1_k + s_{k-1} alpha_k
+        gamma1_k = s_{k-1} delta1_k - c_{k-1} alpha_k
+        eps_{k+1} = s_{k-1} beta_{k+1},  delta1_{k+1} = -c_{k-1} beta_{k+1}
+        gamma2_k = hypot(gamma1_k, beta_{k+1}),  c_k = gamma1_k/gamma2_k,
+        s_k = beta_{k+1}/gamma2_k,  t_k = c_k phi_{k-1},  phi_k = s_k phi_{k-1}
+        w_k = (v_k - delta2_k w_{k-1} - eps_k w_{k-2}) / gamma2_k,
+        tau_k = tau_{k-1} + t_k w_k,
+    starting from c_0 = -1, s_0 = 0, delta1_1 = 0, phi_0 = ||b||; phi_k is the
+    residual norm ||b - L tau_k||_2, which never increases.  ``history``
+    receives phi_k / ||b|| after each iteration."""
+    b = op.rhs(pb, p)
+    bnorm = math.sqrt(op.dot(b, b))
+    x = np.zeros_like(b)
+    if bnorm == 0.0:
+        return {"tau": x, "iters": 0, "rel_res": 0.0}
+    v_prev = np.zeros_like(b)
+    v = b / bnorm
+    w1 = np.zeros_like(b)      # w_{k-1}
+    w2 = np.zeros_like(b)      # w_{k-2}
+    beta = 0.0                 # beta_k (beta_1 v_0 = 0)
+    c_prev, s_prev = -1.0, 0.0
+    delta1 = 0.0
+    eps = 0.0                  # eps_k
+    phi = bnorm
+    it = 0
+    while it < maxit:
+        q = op.apply(pb, v)
+        it += 1
+        alpha = op.dot(v, q)
+        q = q - alpha * v - beta * v_prev
+        beta_next = math.sqrt(op.dot(q, q))
+        delta2 = c_prev * delta1 + s_prev * alpha
+        gamma1 = s_prev * delta1 - c_prev * alpha
+        eps_next = s_prev * beta_next
+        delta1_next = -c_prev * beta_next
+        gamma2 = math.hypot(gamma1, beta_next)
+        if gamma2 == 0.0:
+            break
+        c, s = gamma1 / gamma2, beta_next / gamma2
+        t = c * phi
+        phi = s * phi
+        w = (v - delta2 * w1 - eps * w2) / gamma2
+        x += t * w
+        if history is not None:
+            history.append(abs(phi) / bnorm)
+        if abs(phi) <= tol * bnorm or beta_next == 0.0:
+            break
+        v_prev, v = v, q / beta_next
+        w2, w1 = w1, w
+        beta, delta1, eps = beta_next, delta1_next, eps_next
+        c_prev, s_prev = c, s
+    true_r = b - op.apply(pb, x)
+    return {"tau": x, "iters": it, "rel_res": math.sqrt(op.dot(true_r, true_r)) / bnorm}
+
+
+def eyre_milton(pb: op.Problem, p, tol: float = 1e-10, maxit: int = 10000, history=None):
+    """Eyre--Milton scheme (Eyre and Milton, 1999) in polarisation form.
+
+    Adding (A - A0)^{-1} tau to both sides of eq. (13) after multiplication
+    by 2 A0 shows that its solution is the fixed point of
+        tau_{k+1} = (A - A0)(A + A0)^{-1} [tau_k + 2 A0 (p - Gamma tau_k)]
+    on I0 (tau = 0 elsewhere), tau_0 = 0.  With 0 <= A0^{1/2} Gamma A0^{1/2}
+    <= Id (truncated, filtered and consistent operators) the bracket is a
+    reflection-like map of norm at most one, so the iteration contracts by
+    max |(a - a0)/(a + a0)| (scalar, A0 = a0 Id) for any a0 > 0.  The residual
+    of iterate k is (p - Gamma tau_k) - (A - A0)^{-1} tau_k on I0; the loop
+    stops once its norm is at most tol ||b|| and returns tau_{k+1}."""
+    b = op.rhs(pb, p)
+    bnorm = math.sqrt(op.dot(b, b))
+    m = op.mask(pb)
+    tau = np.zeros_like(b)
+    if bnorm == 0.0:
+        return {"tau": tau, "iters": 0, "rel_res": 0.0}
+    delta, _, in_i0 = op.voxel_tables(pb)
+    A0 = np.asarray(pb.A0, dtype=np.float64)
+    M = np.zeros_like(delta)
+    M[in_i0] = delta[in_i0] @ np.linalg.inv(delta[in_i0] + 2.0 * A0)
+    pcol = np.asarray(p, dtype=np.float64).reshape((-1,) + (1,) * pb.d)
+    c = pb.c
+    it = 0
+    rel = math.inf
+    while it < maxit:
+        u = pcol - op.gamma_apply(pb, tau)
+        it += 1
+        res = m * (u - op.local_apply(pb, tau))
+        rel = math.sqrt(op.dot(res, res)) / bnorm
+        y = (tau + 2.0 * np.einsum("ij,j...->i...", A0, u)).reshape(c, -1)
+        tau = m * np.einsum("vij,jv->iv", M, y).reshape(tau.shape)
+        if history is not None:
+            history.append(rel)
+        if rel <= tol:
+            break
+    return {"tau": tau, "iters": it, "rel_res": rel}
