@@ -55,7 +55,7 @@ typedef enum {
 enum { LSH_SCALAR = 0, LSH_ELASTIC = 1 };            /* physics */
 enum { LSH_FP64 = 0, LSH_MIXED = 1 };                /* precision */
 enum { LSH_GREEN_TRUNCATED = 0, LSH_GREEN_FILTERED = 1, LSH_GREEN_CONSISTENT = 2, LSH_GREEN_FD = 3 };
-enum { LSH_SOLVER_BASIC = 0, LSH_SOLVER_CG = 1 };
+enum { LSH_SOLVER_BASIC = 0, LSH_SOLVER_CG = 1, LSH_SOLVER_MINRES = 2, LSH_SOLVER_EYRE_MILTON = 3 };
 enum { LSH_HOST = 0, LSH_DEVICE = 1 };               /* memory space of a pointer */
 enum { LSH_F64 = 0, LSH_F32 = 1 };                   /* element type of a field buffer */
 enum { LSH_FIELD_TAU = 0, LSH_FIELD_STRAIN = 1 };
@@ -163,11 +163,31 @@ lsh_status lsh_bind_green_table(lsh_ctx* ctx, void* dev_ptr, size_t bytes);
 lsh_status lsh_set_green_series(lsh_ctx* ctx, int nmax);
 
 /*
+ * MINRES keeps four FP64 fields per load (two Lanczos vectors, two search
+ * directions) in caller-owned device memory of lsh_solver_buffer_bytes bytes
+ * bound with lsh_bind_solver_buffer (256-byte aligned); the other solvers
+ * need none (0 bytes).
+ */
+lsh_status lsh_solver_buffer_bytes(const lsh_ctx* ctx, int solver, size_t* bytes);
+lsh_status lsh_bind_solver_buffer(lsh_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/*
  * Solve eq. (13) for nload (1..max_loads) macroscopic loads p_l (host,
- * nload x c row-major FP64; Mandel in elasticity) with the basic fixed-point
- * scheme or conjugate gradients, starting from tau = 0, until
- * ||b - L tau||_2 <= tol ||b||_2 with b = p on I0 (mixed precision: the FP64
- * refined residual), or maxit operator applications per load.
+ * nload x c row-major FP64; Mandel in elasticity), starting from tau = 0,
+ * until ||b - L tau||_2 <= tol ||b||_2 with b = p on I0 (mixed precision: the
+ * FP64 refined residual), or maxit operator applications per load, with
+ *   LSH_SOLVER_BASIC        the fixed point tau = (A - A0)(p - Gamma tau);
+ *   LSH_SOLVER_CG           conjugate gradients (Section 5);
+ *   LSH_SOLVER_MINRES       MINRES (Paige and Saunders), for the symmetric
+ *                           indefinite systems of an A0 between the phases;
+ *                           needs the solver buffer; the stopping test uses
+ *                           its recursive residual norm;
+ *   LSH_SOLVER_EYRE_MILTON  the fixed point tau = (A - A0)(A + A0)^{-1}
+ *                           (tau + 2 A0 (p - Gamma tau)) of the Eyre--Milton
+ *                           scheme, contracting for any SPD A0 (factor
+ *                           max |(a - a0)/(a + a0)| for scalar A0 = a0 Id).
+ * The basic, MINRES and Eyre--Milton iterations run in FP64 in either
+ * precision; CG in a mixed context uses FP32 fields with FP64 refinement.
  *   reports   host array of nload lsh_load_report (may be NULL).
  *   summary   host lsh_solve_report (may be NULL).
  * Returns LSH_OK, LSH_MAXIT (results valid, some load unconverged), or an error.

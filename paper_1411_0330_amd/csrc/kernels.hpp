@@ -50,7 +50,7 @@ __host__ __device__ inline long long main_cpx(const Geo& g) { return (long long)
 __host__ __device__ inline long long nyq_cpx(const Geo& g) { return (long long)g.c * g.nz * g.ny; }
 
 enum : int { XF_PLAIN = 0, XF_CG = 1, XF_IRX = 2 };
-enum : int { XI_APPLY = 0, XI_CG = 1, XI_BASIC = 2, XI_IRRES = 3, XI_RESNORM = 4, XI_STRAIN = 5 };
+enum : int { XI_APPLY = 0, XI_CG = 1, XI_BASIC = 2, XI_IRRES = 3, XI_RESNORM = 4, XI_STRAIN = 5, XI_EM = 6 };
 enum : int { Z_GAMMA = 0, Z_FWD = 1 };
 enum : int { SC_INIT = 0, SC_ALPHA = 1, SC_BETA = 2, SC_BASIC = 3, SC_OUTER = 4, SC_SUM = 5 };
 
@@ -320,6 +320,7 @@ struct XinvArgs {
   double* partials;
   int pstride;
   T scale;                // 1/N^d times the factor of the half-length route
+  T em2[9];               // 2 A0: c x c (scalar), or (4 mu0, 2 lambda0) of the isotropic elastic A0
 };
 
 // Row j of a per-phase c x c matrix applied to v.  Table row layout:
@@ -352,15 +353,37 @@ struct Loc {
   T in, ai, bi;
 };
 
+// which = 0: (A - A0)^{-1}; 1: the table's second matrix, i.e. (A - A0) for
+// the basic scheme or (A - A0)(A + A0)^{-1} for Eyre--Milton; per-voxel mode
+// forms the first (which 1) or the second (which 2, from 2 A0 = (ea, eb)) in place.
+// (A - A0)(A + A0)^{-1} = (Id + 2 A0 (A - A0)^{-1})^{-1}, with
+// 2 A0 (a_inv Id + b_inv m m^T) = 4 mu0 a_inv Id + (4 mu0 b_inv + 2 lambda0 (a_inv + 3 b_inv)) m m^T.
+template <typename T>
+__device__ __forceinline__ void iso_inverse(T& a, T& b, bool six) {
+  const bool z = a == T(0);
+  const T ad = z ? T(0) : T(1) / a;
+  b = (six && !z) ? -b / (a * (a + T(3) * b)) : T(0);
+  a = ad;
+}
+
 template <typename T, int C>
-__device__ __forceinline__ T loc_row(const Loc<T>& L, bool vm, int which, bool iso, int j, const T (&v)[C]) {
+__device__ __forceinline__ T loc_row(const Loc<T>& L, bool vm, int which, bool iso, int j, const T (&v)[C],
+                                     T ea = T(0), T eb = T(0)) {
   if (!vm) return phase_row<T, C>(L.tb, which, iso, j, v);
   T a = L.ai, b = L.bi;
   if (which == 1) {
-    const bool z = a == T(0);
-    const T ad = z ? T(0) : T(1) / a;
-    b = (C == 6 && !z) ? -b / (a * (a + T(3) * b)) : T(0);
-    a = ad;
+    iso_inverse(a, b, C == 6);
+  } else if (which == 2) {
+    if (C == 6) {
+      T al = T(1) + ea * a;
+      T be = ea * b + eb * (a + T(3) * b);
+      iso_inverse(al, be, true);
+      a = al;
+      b = be;
+    } else {
+      a = T(1) / (T(1) + ea * a);
+      b = T(0);
+    }
   }
   T r = a * v[j];
   if (C == 6 && j < 3) r += b * (v[0] + v[1] + v[2]);
@@ -486,6 +509,44 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
 #pragma unroll
       for (int j = 0; j < C; ++j) {
         res[j] = cpx<T>{in0 * loc_row<T, C>(L0, vm, 1, iso, j, u0), in1 * loc_row<T, C>(L1, vm, 1, iso, j, u1)};
+        const double rx = in0 * (u0[j] - loc_row<T, C>(L0, vm, 0, iso, j, t0));
+        const double ry = in1 * (u1[j] - loc_row<T, C>(L1, vm, 0, iso, j, t1));
+        part += rx * rx + ry * ry;
+      }
+    } else if (a.mode == XI_EM) {
+      // new tau = (A - A0)(A + A0)^{-1} (tau + 2 A0 u), u = p - Gamma tau;
+      // residual u - (A - A0)^{-1} tau
+      T u0[C], u1[C], w0[C], w1[C];
+#pragma unroll
+      for (int m = 0; m < C; ++m) {
+        u0[m] = pl[m] - g0[m];
+        u1[m] = pl[m] - g1[m];
+      }
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        T e0 = 0, e1 = 0;
+        if (C == 6) {
+          e0 = a.em2[0] * u0[j];
+          e1 = a.em2[0] * u1[j];
+          if (j < 3) {
+            e0 += a.em2[1] * (u0[0] + u0[1] + u0[2]);
+            e1 += a.em2[1] * (u1[0] + u1[1] + u1[2]);
+          }
+        } else {
+#pragma unroll
+          for (int m = 0; m < C; ++m) {
+            e0 += a.em2[j * C + m] * u0[m];
+            e1 += a.em2[j * C + m] * u1[m];
+          }
+        }
+        w0[j] = t0[j] + e0;
+        w1[j] = t1[j] + e1;
+      }
+      const int wm = vm ? 2 : 1;
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        res[j] = cpx<T>{in0 * loc_row<T, C>(L0, vm, wm, iso, j, w0, a.em2[0], a.em2[1]),
+                        in1 * loc_row<T, C>(L1, vm, wm, iso, j, w1, a.em2[0], a.em2[1])};
         const double rx = in0 * (u0[j] - loc_row<T, C>(L0, vm, 0, iso, j, t0));
         const double ry = in1 * (u1[j] - loc_row<T, C>(L1, vm, 0, iso, j, t1));
         part += rx * rx + ry * ry;
@@ -858,84 +919,6 @@ template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void k_convert(const long long n, const TI* __restrict__ in, TO* __restrict__ out) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i < n) out[i] = static_cast<TO>(in[i]);
-}
-
-// Deterministic final reduction of the partials of group blockIdx.x, then the
-// scalar update of the solver (one workgroup per group).
-static __global__ __launch_bounds__(256) void k_scal(const int mode, const double* __restrict__ partials, const int pstride,
-                                              const int nparts, LoadState* __restrict__ st,
-                                              double* __restrict__ sums, const double tol) {
-  __shared__ double red[256];
-  const int grp = blockIdx.x;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += 256) s += partials[(long long)grp * pstride + i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  const double S = red[0];
-  if (mode == SC_SUM) {
-    sums[grp] = S;
-    return;
-  }
-  LoadState& L = st[grp];
-  if (mode == SC_INIT) {
-    L.bb = S;
-    L.rr = S;
-    L.res2 = S;
-    L.tol2 = tol * tol * S;
-    L.alpha = 0.0;
-    L.beta = 0.0;
-    L.pq = 0.0;
-    L.iters = 0;
-    L.first = 1;
-    L.pending = 0;
-    L.status = isfinite(S) ? kStatusOk : kStatusNumeric;
-    L.active = (S > 0.0 && isfinite(S)) ? 1 : 0;
-    return;
-  }
-  if (!L.active) return;
-  if (mode == SC_ALPHA) {
-    L.pq = S;
-    // p.Lp may be negative when A0 lies between the phases (indefinite
-    // system): CG proceeds; it breaks down only when p.Lp vanishes.
-    // the previous step (if any) was applied to x by this iteration's x pass
-    L.pending = 0;
-    if (!isfinite(S)) {
-      L.status = kStatusNumeric;
-      L.active = 0;
-    } else if (S == 0.0) {
-      L.status = kStatusBreakdown;
-      L.active = 0;
-    } else {
-      L.alpha = L.rr / S;
-      L.first = 0;
-      L.pending = 1;
-    }
-  } else if (mode == SC_BETA) {
-    L.iters += 1;
-    if (!isfinite(S)) {
-      L.status = kStatusNumeric;
-      L.active = 0;
-      return;
-    }
-    L.beta = S / L.rr;
-    L.rr = S;
-    L.res2 = S;
-    if (S <= L.tol2) L.active = 0;
-  } else if (mode == SC_BASIC || mode == SC_OUTER) {
-    L.iters += 1;
-    L.res2 = S;
-    if (!isfinite(S)) {
-      L.status = kStatusNumeric;
-      L.active = 0;
-    } else if (S <= L.tol2) {
-      L.active = 0;
-    }
-  }
 }
 
 }  // namespace lsh

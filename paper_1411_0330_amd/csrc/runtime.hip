@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "dispatch.hpp"
+#include "solver_kernels.hpp"
 #include "lsh.h"
 
 using namespace lsh;
@@ -144,6 +145,9 @@ struct lsh_ctx {
   int series = 8;
   int iso = 0;  // every phase matrix has the short form (see phase_row)
   bool mat_voxel = false;  // material given per voxel (lsh_set_voxel_moduli) instead of per phase
+  bool tab_em = false;     // second table matrix: (A-A0)(A+A0)^{-1} (Eyre--Milton) instead of A-A0
+  char* sbuf = nullptr;    // bound solver buffer (MINRES fields)
+  size_t sbuf_size = 0;
   int tune[2][NPASS] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // kernel-shape variant per (FP32/FP64, pass)
 
   // workspace
@@ -151,7 +155,7 @@ struct lsh_ctx {
   size_t ws_need = 0, ws_size = 0;
   struct {
     size_t x64, r64, p64, d32, r32, p32, s64m, s64n, s32m, s32n, phase, i0, ptab64, ptab32, vc64, vc32, tw64, tw32,
-        wt64, wt32, loads, wgrad, st_out, st_in, partials, sums, end;
+        wt64, wt32, loads, wgrad, st_out, st_in, mstate, partials, sums, end;
   } off{};
   long long pstride = 0, nsums = 0;
   int twoff[3] = {0, 0, 0};
@@ -313,6 +317,7 @@ void compute_layout(lsh_ctx* ctx) {
   ctx->off.wgrad = take(sizeof(double) * L * L);
   ctx->off.st_out = take(sizeof(LoadState) * L);
   ctx->off.st_in = take(sizeof(LoadState) * L);
+  ctx->off.mstate = take(sizeof(MinresState) * L);
   // partial sums: the largest grid of any reducing kernel, per group
   long long pmax = xinv_blocks(ctx->geo, 2);
   pmax = std::max(pmax, (F + 1023) / 1024 + 1);
@@ -407,14 +412,29 @@ lsh_status build_tables(lsh_ctx* ctx) {
       return fail(ctx, LSH_EHYP2,
                   "phase " + std::to_string(p) + ": A - A0 is neither zero nor definite (hypothesis (2))");
     if (!invert(c, D, Dinv)) return fail(ctx, LSH_EHYP2, "phase " + std::to_string(p) + ": A - A0 is singular");
+    // second matrix: A - A0 (basic scheme) or (A - A0)(A + A0)^{-1} (Eyre--Milton)
+    double S2[36];
+    if (ctx->tab_em) {
+      double Sum[36], SumInv[36];
+      for (int i = 0; i < c * c; ++i) Sum[i] = D[i] + 2.0 * ctx->A0[i];
+      if (!invert(c, Sum, SumInv)) return fail(ctx, LSH_EHYP2, "phase " + std::to_string(p) + ": A + A0 is singular");
+      for (int i = 0; i < c; ++i)
+        for (int j = 0; j < c; ++j) {
+          double a = 0.0;
+          for (int k = 0; k < c; ++k) a += D[i * c + k] * SumInv[k * c + j];
+          S2[i * c + j] = a;
+        }
+    } else {
+      for (int i = 0; i < c * c; ++i) S2[i] = D[i];
+    }
     for (int i = 0; i < c * c; ++i) {
       row[i] = Dinv[i];
-      row[c * c + i] = D[i];
+      row[c * c + i] = S2[i];
     }
     row[2 * c * c] = 1.0;
     // short form a Id + b m m^T (m: normal Mandel components; b = 0 for scalar)
     for (int which = 0; which < 2; ++which) {
-      const double* M = which == 0 ? Dinv : D;
+      const double* M = which == 0 ? Dinv : S2;
       const bool el = ctx->physics == LSH_ELASTIC;
       const double b = el ? M[1] : 0.0;
       const double a = M[0] - b;
@@ -659,6 +679,13 @@ lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T*
   a.partials = partials;
   a.pstride = (int)ctx->pstride;
   a.scale = static_cast<T>(1.0 / (double)g.nvox);
+  for (int i = 0; i < 9; ++i) a.em2[i] = T(0);
+  if (ctx->physics == LSH_ELASTIC) {
+    a.em2[0] = static_cast<T>(2.0 * ctx->A0[3 * 6 + 3]);   // 4 mu0
+    a.em2[1] = static_cast<T>(2.0 * ctx->A0[1]);           // 2 lambda0
+  } else {
+    for (int i = 0; i < ctx->c * ctx->c; ++i) a.em2[i] = static_cast<T>(2.0 * ctx->A0[i]);
+  }
   const double nl = std::min(ctx->nact, nload);
   const double cvs = (double)ctx->F * sizeof(T);
   // spectrum + material (phase ids, or two coefficients per voxel)
@@ -803,8 +830,9 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
   return cg_flush<T>(ctx, nload, x, p, st);
 }
 
+// Fixed-point schemes on tau in place: basic (XI_BASIC) or Eyre--Milton (XI_EM).
 lsh_status basic_loop(lsh_ctx* ctx, int nload, double* x, LoadState* st, size_t st_off, int maxit,
-                      std::vector<LoadState>& hst) {
+                      std::vector<LoadState>& hst, int ximode = XI_BASIC) {
   const int period = check_period(ctx, nload);
   STCHK(read_states(ctx, st_off, nload, hst));
   bool any = false;
@@ -814,16 +842,95 @@ lsh_status basic_loop(lsh_ctx* ctx, int nload, double* x, LoadState* st, size_t 
   auto iteration = [&]() -> lsh_status {
     STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, x, nullptr, nullptr, nullptr, st, true));
     int np = 0;
-    STCHK(inverse_x<double>(ctx, 0, nload, XI_BASIC, x, x, nullptr, st, ctx->ptr<double>(ctx->off.partials), &np));
+    STCHK(inverse_x<double>(ctx, 0, nload, ximode, x, x, nullptr, st, ctx->ptr<double>(ctx->off.partials), &np));
     return scal(ctx, SC_BASIC, nload, np, st, 0.0);
   };
   for (int it = 0; it < maxit; ++it) {
-    STCHK(run_iteration(ctx, 2, (long long)nload, iteration));
+    STCHK(run_iteration(ctx, 2, (long long)nload * 8 + ximode, iteration));
     if ((it + 1) % period == 0 || it + 1 == maxit) {
       STCHK(read_states(ctx, st_off, nload, hst));
       any = false;
       ctx->nact = 0;
       for (auto& s : hst) any |= s.active != 0, ctx->nact += s.active != 0;
+      if (!any) break;
+    }
+  }
+  return LSH_OK;
+}
+
+// MINRES on x64 with the Lanczos and direction fields in the bound solver
+// buffer (v_{k-1}, v_k, w_{k-1}, w_{k-2}); q = L v_k lands in the FP64
+// spectrum buffer.  The four fields rotate roles between steps, so the steps
+// are queued eagerly (no graph capture).
+lsh_status mr_loop(lsh_ctx* ctx, int nload, double tol, int maxit, std::vector<LoadState>& hst) {
+  const long long F = ctx->F;
+  const long long LF = (long long)ctx->max_loads * F;
+  double* f[4];
+  for (int i = 0; i < 4; ++i) f[i] = reinterpret_cast<double*>(ctx->sbuf) + i * LF;
+  double* vp = f[0];
+  double* v = f[1];
+  double* w1 = f[2];
+  double* w2 = f[3];
+  double* x = ctx->ptr<double>(ctx->off.x64);
+  LoadState* st = ctx->ptr<LoadState>(ctx->off.st_out);
+  MinresState* ms = ctx->ptr<MinresState>(ctx->off.mstate);
+  double* parts = ctx->ptr<double>(ctx->off.partials);
+  // x = 0, v = b and ||b||^2; then v = b/||b|| and the rotation state
+  STCHK(cg_init<double>(ctx, nload, x, v, st, tol));
+  {
+    Scope sc(ctx, K_INIT);
+    hipLaunchKernelGGL(k_mr_start, dim3((unsigned)((F + 255) / 256), nload), dim3(256), 0, ctx->stream, F, v, vp, w1,
+                       w2, st);
+    STCHK(check_launch(ctx, 0, "minres start"));
+  }
+  {
+    Scope sc(ctx, K_SCAL);
+    hipLaunchKernelGGL(k_mr_scal, dim3(nload), dim3(256), 0, ctx->stream, (int)MR_INIT, parts, (int)ctx->pstride, 0,
+                       st, ms);
+    STCHK(check_launch(ctx, 0, "minres init"));
+  }
+  const int period = check_period(ctx, nload);
+  STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
+  ctx->nact = 0;
+  bool any = false;
+  for (auto& sv : hst) any |= sv.active != 0, ctx->nact += sv.active != 0;
+  if (!any) return LSH_OK;
+  double* q = reinterpret_cast<double*>(Sel<double>::sm(ctx));
+  const int nbe = (int)((F + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
+  for (int it = 0; it < maxit; ++it) {
+    STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, v, nullptr, nullptr, nullptr, st, true));
+    int np = 0;
+    STCHK(inverse_x<double>(ctx, 0, nload, XI_CG, v, q, nullptr, st, parts, &np));
+    {
+      Scope sc(ctx, K_SCAL);
+      hipLaunchKernelGGL(k_mr_scal, dim3(nload), dim3(256), 0, ctx->stream, (int)MR_ALPHA, parts, (int)ctx->pstride,
+                         np, st, ms);
+      STCHK(check_launch(ctx, 0, "minres alpha"));
+    }
+    {
+      Scope sc(ctx, kcls<double>(K_CGUPD), std::min(ctx->nact, nload) * 4.0 * (double)F * 8.0);
+      hipLaunchKernelGGL(k_mr_lanczos, dim3(nbe, nload), dim3(256), 0, ctx->stream, F, q, v, vp, st, ms, parts,
+                         (int)ctx->pstride);
+      STCHK(check_launch(ctx, 0, "minres lanczos"));
+    }
+    {
+      Scope sc(ctx, K_SCAL);
+      hipLaunchKernelGGL(k_mr_scal, dim3(nload), dim3(256), 0, ctx->stream, (int)MR_ROT, parts, (int)ctx->pstride,
+                         nbe, st, ms);
+      STCHK(check_launch(ctx, 0, "minres rotation"));
+    }
+    {
+      Scope sc(ctx, kcls<double>(K_CGUPD), std::min(ctx->nact, nload) * 8.0 * (double)F * 8.0);
+      hipLaunchKernelGGL(k_mr_update, dim3(nbe, nload), dim3(256), 0, ctx->stream, F, v, vp, w1, w2, x, ms);
+      STCHK(check_launch(ctx, 0, "minres update"));
+    }
+    std::swap(v, vp);    // v_{k+1} now in the old v_{k-1} slot
+    std::swap(w1, w2);   // w_k now in the old w_{k-2} slot
+    if ((it + 1) % period == 0 || it + 1 == maxit) {
+      STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
+      any = false;
+      ctx->nact = 0;
+      for (auto& sv : hst) any |= sv.active != 0, ctx->nact += sv.active != 0;
       if (!any) break;
     }
   }
@@ -1223,10 +1330,32 @@ lsh_status lsh_set_green_series(lsh_ctx* ctx, int nmax) {
   return LSH_OK;
 }
 
+lsh_status lsh_solver_buffer_bytes(const lsh_ctx* ctx, int solver, size_t* bytes) {
+  if (!ctx || !bytes) return LSH_EINVAL;
+  if (solver < LSH_SOLVER_BASIC || solver > LSH_SOLVER_EYRE_MILTON) return LSH_EINVAL;
+  *bytes = solver == LSH_SOLVER_MINRES ? align_up(4 * sizeof(double) * (size_t)ctx->max_loads * ctx->F) : 0;
+  return LSH_OK;
+}
+
+lsh_status lsh_bind_solver_buffer(lsh_ctx* ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return LSH_EINVAL;
+  size_t need = 0;
+  lsh_solver_buffer_bytes(ctx, LSH_SOLVER_MINRES, &need);
+  if (!dev_ptr) return fail(ctx, LSH_EINVAL, "null solver buffer");
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % kAlign != 0)
+    return fail(ctx, LSH_EINVAL, "solver buffer not 256-byte aligned");
+  if (bytes < need) return fail(ctx, LSH_ENOMEM, "solver buffer too small: need " + std::to_string(need) + " bytes");
+  ctx->sbuf = static_cast<char*>(dev_ptr);
+  ctx->sbuf_size = bytes;
+  return LSH_OK;
+}
+
 lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, double tol, int maxit,
                      lsh_load_report* reports, lsh_solve_report* summary) {
   if (!ctx) return LSH_EINVAL;
-  if (solver != LSH_SOLVER_BASIC && solver != LSH_SOLVER_CG) return fail(ctx, LSH_EINVAL, "unknown solver");
+  if (solver != LSH_SOLVER_BASIC && solver != LSH_SOLVER_CG && solver != LSH_SOLVER_MINRES &&
+      solver != LSH_SOLVER_EYRE_MILTON)
+    return fail(ctx, LSH_EINVAL, "unknown solver");
   if (nload < 1 || nload > ctx->max_loads) return fail(ctx, LSH_EINVAL, "nload out of range");
   if (!loads) return fail(ctx, LSH_EINVAL, "null loads");
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(ctx, LSH_EINVAL, "tol must be positive");
@@ -1234,6 +1363,15 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
   const int c = ctx->c;
   for (int i = 0; i < nload * c; ++i)
     if (!std::isfinite(loads[i])) return fail(ctx, LSH_EINVAL, "non-finite load");
+  if (solver == LSH_SOLVER_MINRES && !ctx->sbuf)
+    return fail(ctx, LSH_ESTATE, "MINRES needs a bound solver buffer (lsh_solver_buffer_bytes)");
+  if (solver == LSH_SOLVER_BASIC || solver == LSH_SOLVER_EYRE_MILTON) {
+    const bool em = solver == LSH_SOLVER_EYRE_MILTON;
+    if (ctx->tab_em != em) {
+      ctx->tab_em = em;
+      ctx->tables_dirty = true;
+    }
+  }
   STCHK(prepare(ctx));
   ctx->nact = 1 << 30;
   const auto t0 = std::chrono::steady_clock::now();
@@ -1254,9 +1392,14 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
   bool residual_known = false;
   std::vector<double> res2(nload, 0.0), bb(nload, 0.0);
 
-  if (solver == LSH_SOLVER_BASIC) {
+  if (solver == LSH_SOLVER_BASIC || solver == LSH_SOLVER_EYRE_MILTON) {
     STCHK(cg_init<double>(ctx, nload, x64, nullptr, sto, tol));
-    STCHK(basic_loop(ctx, nload, x64, sto, ctx->off.st_out, maxit, hst));
+    STCHK(basic_loop(ctx, nload, x64, sto, ctx->off.st_out, maxit, hst,
+                     solver == LSH_SOLVER_BASIC ? XI_BASIC : XI_EM));
+    STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
+    for (int l = 0; l < nload; ++l) iters[l] = hst[l].iters, apps64 += hst[l].iters;
+  } else if (solver == LSH_SOLVER_MINRES) {
+    STCHK(mr_loop(ctx, nload, tol, maxit, hst));
     STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
     for (int l = 0; l < nload; ++l) iters[l] = hst[l].iters, apps64 += hst[l].iters;
   } else if (ctx->precision == LSH_FP64) {

@@ -1,0 +1,242 @@
+// Solver-scalar kernels (non-template, one instance in the library): the
+// deterministic reductions and scalar updates of CG, the fixed-point schemes
+// and the refinement, and the MINRES recurrences with their vector kernels.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace lsh {
+
+// ----------------------------------------------------------------------------
+// MINRES (Paige--Saunders) on the FP64 fields: per-load rotation state and the
+// two vector kernels of one step, around the operator application q = L v_k.
+// ----------------------------------------------------------------------------
+struct MinresState {
+  double alpha, beta, c, s, delta1, eps, phi;  // recurrences (beta = beta_k, eps = eps_k)
+  double delta2, epsk, gamma2, t, inv_beta;    // coefficients of this step's vector update
+  int apply, pad;
+};
+
+enum : int { MR_INIT = 0, MR_ALPHA = 1, MR_ROT = 2 };
+
+// v = b / ||b||, v_prev = w_{k-1} = w_{k-2} = 0 on the loads that iterate
+static __global__ __launch_bounds__(256) void k_mr_start(const long long F, double* __restrict__ v,
+                                                  double* __restrict__ vp, double* __restrict__ w1,
+                                                  double* __restrict__ w2, const LoadState* __restrict__ st) {
+  const int l = blockIdx.y;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= F) return;
+  const long long o = (long long)l * F + i;
+  const double sc = st[l].bb > 0.0 ? 1.0 / sqrt(st[l].bb) : 0.0;
+  v[o] *= sc;
+  vp[o] = 0.0;
+  w1[o] = 0.0;
+  w2[o] = 0.0;
+}
+
+// vp = q - alpha v - beta vp (the unnormalised v_{k+1}); partial ||vp||^2
+static __global__ __launch_bounds__(256) void k_mr_lanczos(const long long F, const double* __restrict__ q,
+                                                    const double* __restrict__ v, double* __restrict__ vp,
+                                                    const LoadState* __restrict__ st,
+                                                    const MinresState* __restrict__ ms, double* __restrict__ partials,
+                                                    const int pstride) {
+  __shared__ double red[4];
+  const int l = blockIdx.y;
+  if (!st[l].active) return;
+  const double al = ms[l].alpha, be = ms[l].beta;
+  double part = 0.0;
+  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kEwUnroll; ++u) {
+    const long long i = b0 + (long long)u * 256;
+    if (i < F) {
+      const long long o = (long long)l * F + i;
+      const double z = q[o] - al * v[o] - be * vp[o];
+      vp[o] = z;
+      part += z * z;
+    }
+  }
+  const double sum = block_sum<256>(part, red);
+  if (threadIdx.x == 0) partials[(long long)l * pstride + blockIdx.x] = sum;
+}
+
+// w_k = (v_k - delta2 w_{k-1} - eps_k w_{k-2}) / gamma2 into the w_{k-2} slot,
+// x += t w_k, and v_{k+1} = vp / beta_{k+1} in place
+static __global__ __launch_bounds__(256) void k_mr_update(const long long F, const double* __restrict__ v,
+                                                   double* __restrict__ vp, const double* __restrict__ w1,
+                                                   double* __restrict__ w2, double* __restrict__ x,
+                                                   const MinresState* __restrict__ ms) {
+  const int l = blockIdx.y;
+  const MinresState& m = ms[l];
+  if (!m.apply) return;
+  const double ig = 1.0 / m.gamma2;
+  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kEwUnroll; ++u) {
+    const long long i = b0 + (long long)u * 256;
+    if (i < F) {
+      const long long o = (long long)l * F + i;
+      const double w = (v[o] - m.delta2 * w1[o] - m.epsk * w2[o]) * ig;
+      w2[o] = w;
+      x[o] += m.t * w;
+      vp[o] *= m.inv_beta;
+    }
+  }
+}
+
+__device__ __forceinline__ double group_sum(const double* __restrict__ partials, int pstride, int nparts, int grp,
+                                            double* red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 256) s += partials[(long long)grp * pstride + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// Scalar steps of MINRES (one workgroup per load).  MR_ROT applies the
+// previous rotation to the new tridiagonal column (beta_k, alpha_k,
+// beta_{k+1}), forms the next rotation, the step t_k = c_k phi_{k-1} and the
+// residual norm phi_k = s_k phi_{k-1}; the load stops at |phi_k| <= tol ||b||,
+// at beta_{k+1} = 0 (exact solution) or, with gamma2 = 0, on breakdown.
+static __global__ __launch_bounds__(256) void k_mr_scal(const int mode, const double* __restrict__ partials,
+                                                        const int pstride, const int nparts,
+                                                        LoadState* __restrict__ st, MinresState* __restrict__ ms) {
+  __shared__ double red[256];
+  const int l = blockIdx.x;
+  const double S = mode == MR_INIT ? 0.0 : group_sum(partials, pstride, nparts, l, red);
+  if (threadIdx.x != 0) return;
+  LoadState& L = st[l];
+  MinresState& M = ms[l];
+  if (mode == MR_INIT) {
+    M.alpha = M.beta = M.delta1 = M.eps = 0.0;
+    M.c = -1.0;
+    M.s = 0.0;
+    M.phi = sqrt(L.bb);
+    M.delta2 = M.epsk = M.t = M.inv_beta = 0.0;
+    M.gamma2 = 1.0;
+    M.apply = 0;
+    return;
+  }
+  if (mode == MR_ALPHA) {
+    if (L.active) M.alpha = S;
+    return;
+  }
+  M.apply = 0;
+  if (!L.active) return;
+  if (!isfinite(S) || !isfinite(M.alpha)) {
+    L.status = kStatusNumeric;
+    L.active = 0;
+    return;
+  }
+  const double bn = sqrt(S);
+  const double delta2 = M.c * M.delta1 + M.s * M.alpha;
+  const double gamma1 = M.s * M.delta1 - M.c * M.alpha;
+  const double eps_next = M.s * bn;
+  const double delta1_next = -M.c * bn;
+  const double gamma2 = hypot(gamma1, bn);
+  L.iters += 1;
+  if (gamma2 == 0.0) {
+    L.status = kStatusBreakdown;
+    L.active = 0;
+    return;
+  }
+  const double c = gamma1 / gamma2, s = bn / gamma2;
+  M.delta2 = delta2;
+  M.epsk = M.eps;
+  M.gamma2 = gamma2;
+  M.t = c * M.phi;
+  M.phi = s * M.phi;
+  M.inv_beta = bn > 0.0 ? 1.0 / bn : 0.0;
+  M.apply = 1;
+  M.beta = bn;
+  M.delta1 = delta1_next;
+  M.eps = eps_next;
+  M.c = c;
+  M.s = s;
+  L.res2 = M.phi * M.phi;
+  if (L.res2 <= L.tol2 || bn == 0.0) L.active = 0;
+}
+
+// Deterministic final reduction of the partials of group blockIdx.x, then the
+// scalar update of the solver (one workgroup per group).
+static __global__ __launch_bounds__(256) void k_scal(const int mode, const double* __restrict__ partials, const int pstride,
+                                              const int nparts, LoadState* __restrict__ st,
+                                              double* __restrict__ sums, const double tol) {
+  __shared__ double red[256];
+  const int grp = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 256) s += partials[(long long)grp * pstride + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double S = red[0];
+  if (mode == SC_SUM) {
+    sums[grp] = S;
+    return;
+  }
+  LoadState& L = st[grp];
+  if (mode == SC_INIT) {
+    L.bb = S;
+    L.rr = S;
+    L.res2 = S;
+    L.tol2 = tol * tol * S;
+    L.alpha = 0.0;
+    L.beta = 0.0;
+    L.pq = 0.0;
+    L.iters = 0;
+    L.first = 1;
+    L.pending = 0;
+    L.status = isfinite(S) ? kStatusOk : kStatusNumeric;
+    L.active = (S > 0.0 && isfinite(S)) ? 1 : 0;
+    return;
+  }
+  if (!L.active) return;
+  if (mode == SC_ALPHA) {
+    L.pq = S;
+    // p.Lp may be negative when A0 lies between the phases (indefinite
+    // system): CG proceeds; it breaks down only when p.Lp vanishes.
+    // the previous step (if any) was applied to x by this iteration's x pass
+    L.pending = 0;
+    if (!isfinite(S)) {
+      L.status = kStatusNumeric;
+      L.active = 0;
+    } else if (S == 0.0) {
+      L.status = kStatusBreakdown;
+      L.active = 0;
+    } else {
+      L.alpha = L.rr / S;
+      L.first = 0;
+      L.pending = 1;
+    }
+  } else if (mode == SC_BETA) {
+    L.iters += 1;
+    if (!isfinite(S)) {
+      L.status = kStatusNumeric;
+      L.active = 0;
+      return;
+    }
+    L.beta = S / L.rr;
+    L.rr = S;
+    L.res2 = S;
+    if (S <= L.tol2) L.active = 0;
+  } else if (mode == SC_BASIC || mode == SC_OUTER) {
+    L.iters += 1;
+    L.res2 = S;
+    if (!isfinite(S)) {
+      L.status = kStatusNumeric;
+      L.active = 0;
+    } else if (S <= L.tol2) {
+      L.active = 0;
+    }
+  }
+}
+
+}  // namespace lsh

@@ -23,13 +23,13 @@ STATUS_NAMES = {0: "OK", 1: "MAXIT", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4:
 SCALAR, ELASTIC = 0, 1
 FP64, MIXED = 0, 1
 TRUNCATED, FILTERED, CONSISTENT, FD = 0, 1, 2, 3
-BASIC, CG = 0, 1
+BASIC, CG, MINRES, EYRE_MILTON = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
 F64, F32 = 0, 1
 TAU, STRAIN = 0, 1
 
 GREEN = {"truncated": TRUNCATED, "filtered": FILTERED, "consistent": CONSISTENT, "fd": FD}
-SOLVERS = {"basic": BASIC, "cg": CG}
+SOLVERS = {"basic": BASIC, "cg": CG, "minres": MINRES, "eyre_milton": EYRE_MILTON}
 PHYSICS = {"scalar": SCALAR, "elastic": ELASTIC}
 PRECISION = {"fp64": FP64, "mixed": MIXED}
 
@@ -59,6 +59,8 @@ _SIGS = {
     "lsh_green_table_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "lsh_bind_green_table": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "lsh_set_green_series": (C.c_int, [C.c_void_p, C.c_int]),
+    "lsh_solver_buffer_bytes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_size_t)]),
+    "lsh_bind_solver_buffer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "lsh_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_double, C.c_int,
                             C.POINTER(LoadReport), C.POINTER(SolveReport)]),
     "lsh_get_field": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int]),
@@ -248,8 +250,18 @@ class Context:
         return self._check(self.lib.lsh_set_green(self.h, code))
 
     # -- solve ---------------------------------------------------------
+    def _solver_buffer(self, code):
+        b = C.c_size_t()
+        self._check(self.lib.lsh_solver_buffer_bytes(self.h, code, C.byref(b)))
+        if b.value and getattr(self, "solver_buffer", None) is None:
+            import torch
+            self.solver_buffer = torch.empty(b.value + 256, dtype=torch.uint8, device=self.device)
+            ptr = (self.solver_buffer.data_ptr() + 255) // 256 * 256
+            self._check(self.lib.lsh_bind_solver_buffer(self.h, C.c_void_p(ptr), b.value))
+
     def solve(self, loads, solver="cg", tol=1e-10, maxit=1000, allow=(OK, MAXIT)):
         loads = np.ascontiguousarray(np.atleast_2d(loads), dtype=np.float64)
+        self._solver_buffer(SOLVERS[solver])
         nload = loads.shape[0]
         reps = (LoadReport * nload)()
         summ = SolveReport()
