@@ -253,6 +253,46 @@ lsh_status lsh_forward_dft(lsh_ctx* ctx, int nload, const void* field, void* spe
 lsh_status lsh_spectrum_bytes(const lsh_ctx* ctx, int dtype, size_t* bytes);
 
 /*
+ * Kernel shapes.  The transform passes over 128- and 256-point axes are
+ * compiled in four workgroup shapes each (pencils per workgroup and points
+ * per thread); pass 0..3 = x forward, y, z with Green operator, x inverse, for
+ * the FP32 (fp64 = 0) or FP64 (fp64 = 1) kernels.  Every shape computes the
+ * same result; only speed differs.  lsh_get_variants writes the 8 current
+ * choices (FP32 passes, then FP64).  The environment variable LSH_TUNE (for
+ * example "zg32=1,xinv64=2") sets them when the context is created.
+ */
+lsh_status lsh_set_variant(lsh_ctx* ctx, int pass, int fp64, int variant);
+lsh_status lsh_get_variants(const lsh_ctx* ctx, int32_t* variants);
+
+/*
+ * Autotuner: times every shape of every pass that has several (the others
+ * held at their current choice) with HIP events over operator applications
+ * of nload loads on the context's own buffers, and keeps the fastest.
+ * With cache_path (may be NULL) the choice is looked up first in, and
+ * afterwards written to, a text file with one line per key: device, grid,
+ * components, precision, nload, Green operator and material form.  A cache
+ * hit runs nothing on the GPU (*from_cache = 1).  Needs a prepared context
+ * (reference and material set); invalidates the last solution.  variants
+ * (may be NULL) receives the 8 choices as lsh_get_variants.
+ */
+lsh_status lsh_autotune(lsh_ctx* ctx, int nload, const char* cache_path, int32_t* variants, int* from_cache);
+
+/*
+ * Ensembles: solve n independent contexts (distinct, typically one
+ * microstructure each, each on its own HIP stream of default priority) with
+ * lsh_solve from a pool of nthreads host threads (< 1: 4), so that the work of
+ * small grids overlaps on the GPU.  Per context i: nloads[i], loads[i],
+ * reports[i] (array of nloads[i] lsh_load_report, or reports NULL),
+ * summaries[i] and statuses[i] (each array may be NULL).  Returns the first
+ * error status, else LSH_MAXIT if any context stopped at maxit, else LSH_OK.
+ * Contexts sharing one stream are still correct but serialise.
+ */
+lsh_status lsh_solve_many(int n, lsh_ctx* const* ctxs, int solver, const int32_t* nloads,
+                          const double* const* loads, double tol, int maxit,
+                          lsh_load_report* const* reports, lsh_solve_report* summaries,
+                          int32_t* statuses, int nthreads);
+
+/*
  * Iteration graphs (default on): the kernels of one solver iteration are
  * captured once into a HIP graph (on a private stream of default priority)
  * and the graph is replayed on the context's stream for every iteration.

@@ -8,8 +8,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <atomic>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dispatch.hpp"
@@ -972,6 +977,76 @@ lsh_status effective(lsh_ctx* ctx, int nload) {
   return LSH_OK;
 }
 
+// ------------------------- kernel-shape tuning ---------------------------
+// Passes compiled in several shapes: the 128/256-point axes.
+bool pass_has_variants(const lsh_ctx* ctx, int pass) {
+  switch (pass) {
+    case PASS_XFWD:
+    case PASS_XINV: return ctx->geo.mx == 64 || ctx->geo.mx == 128;
+    case PASS_Y: return ctx->n[1] == 128 || ctx->n[1] == 256;
+    case PASS_ZG: return ctx->c != 2 && (ctx->n[2] == 128 || ctx->n[2] == 256);
+    default: return false;
+  }
+}
+
+int pass_class(int pass, bool fp64) {
+  const int base = pass == PASS_XFWD ? K_XFWD : pass == PASS_Y ? K_Y : pass == PASS_ZG ? K_ZG : K_XINV;
+  return base + (fp64 ? 1 : 0);
+}
+
+// One operator application on the workspace's own fields (timing input):
+// FP64 x64 -> FP64 spectrum, FP32 d -> FP32 spectrum.
+template <typename T>
+lsh_status timing_apply(lsh_ctx* ctx, int nload, T* tau) {
+  T* out = reinterpret_cast<T*>(Sel<T>::sm(ctx));
+  STCHK(forward_part<T>(ctx, 0, nload, XF_PLAIN, tau, nullptr, nullptr, nullptr, nullptr, true));
+  return inverse_x<T>(ctx, 0, nload, XI_APPLY, tau, out, nullptr, nullptr, nullptr, nullptr);
+}
+
+std::string tune_key(const lsh_ctx* ctx, int nload) {
+  std::ostringstream k;
+  k << "gfx950 " << ctx->n[0] << "x" << ctx->n[1] << "x" << ctx->n[2] << " c" << ctx->c
+    << (ctx->precision == LSH_MIXED ? " mixed" : " fp64") << " L" << nload << " green" << ctx->green
+    << (ctx->mat_voxel ? " voxel" : (ctx->iso ? " iso" : " full"));
+  return k.str();
+}
+
+// Cache file: one line per key, "<key> = v00 v01 v02 v03 v10 v11 v12 v13"
+// (FP32 passes xfwd y zg xinv, then FP64).
+std::map<std::string, std::vector<int>> read_tune_cache(const char* path) {
+  std::map<std::string, std::vector<int>> m;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t eq = line.find(" = ");
+    if (eq == std::string::npos) continue;
+    std::istringstream vs(line.substr(eq + 3));
+    std::vector<int> v;
+    int x;
+    while (vs >> x) v.push_back(x);
+    if (v.size() != 2 * NPASS) continue;
+    bool ok = true;
+    for (int y : v) ok &= (y >= 0 && y < kVariants);
+    if (ok) m[line.substr(0, eq)] = v;
+  }
+  return m;
+}
+
+bool write_tune_cache(const char* path, const std::map<std::string, std::vector<int>>& m) {
+  const std::string tmp = std::string(path) + ".tmp" + std::to_string((long long)std::hash<std::thread::id>()(std::this_thread::get_id()) % 100000);
+  {
+    std::ofstream f(tmp);
+    if (!f) return false;
+    for (const auto& kv : m) {
+      f << kv.first << " =";
+      for (int v : kv.second) f << " " << v;
+      f << "\n";
+    }
+    if (!f) return false;
+  }
+  return std::rename(tmp.c_str(), path) == 0;
+}
+
 // Isotropic reference of per-voxel mode: a0 (scalar, A0 = a0 Id) or (K0, mu0).
 bool isotropic_reference(const lsh_ctx* ctx, double* a0, double* K0, double* mu0) {
   const int c = ctx->c;
@@ -1634,6 +1709,146 @@ lsh_status lsh_forward_dft(lsh_ctx* ctx, int nload, const void* field, void* spe
   ctx->have_solution = false;
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return LSH_OK;
+}
+
+lsh_status lsh_set_variant(lsh_ctx* ctx, int pass, int fp64, int variant) {
+  if (!ctx) return LSH_EINVAL;
+  if (pass < 0 || pass >= NPASS || variant < 0 || variant >= kVariants) return fail(ctx, LSH_EINVAL, "bad pass or variant");
+  ctx->tune[fp64 ? 1 : 0][pass] = variant;
+  ctx->graph_epoch++;
+  return LSH_OK;
+}
+
+lsh_status lsh_get_variants(const lsh_ctx* ctx, int32_t* variants) {
+  if (!ctx || !variants) return LSH_EINVAL;
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < NPASS; ++q) variants[p * NPASS + q] = ctx->tune[p][q];
+  return LSH_OK;
+}
+
+lsh_status lsh_autotune(lsh_ctx* ctx, int nload, const char* cache_path, int32_t* variants, int* from_cache) {
+  if (!ctx) return LSH_EINVAL;
+  if (nload < 1 || nload > ctx->max_loads) return fail(ctx, LSH_EINVAL, "nload out of range");
+  STCHK(prepare(ctx));
+  const std::string key = tune_key(ctx, nload);
+  std::map<std::string, std::vector<int>> cache;
+  if (from_cache) *from_cache = 0;
+  if (cache_path) {
+    cache = read_tune_cache(cache_path);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < NPASS; ++q) ctx->tune[p][q] = it->second[p * NPASS + q];
+      ctx->graph_epoch++;
+      if (from_cache) *from_cache = 1;
+      if (variants) lsh_get_variants(ctx, variants);
+      return LSH_OK;
+    }
+  }
+  // search: each pass of each precision in turn, the others at their current choice
+  const bool saved_timing = ctx->timing;
+  drain_timers(ctx);
+  ctx->timing = true;
+  ctx->nact = 1 << 30;
+  const int reps = 3;
+  for (int prec = ctx->precision == LSH_MIXED ? 0 : 1; prec < 2; ++prec) {
+    const bool fp64 = prec == 1;
+    const long long n = (long long)nload * ctx->F;
+    if (fp64) {
+      hipLaunchKernelGGL((k_fill<double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n,
+                         ctx->ptr<double>(ctx->off.x64));
+    } else {
+      hipLaunchKernelGGL((k_fill<float>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n,
+                         ctx->ptr<float>(ctx->off.d32));
+    }
+    STCHK(check_launch(ctx, 0, "fill"));
+    for (int pass = 0; pass < NPASS; ++pass) {
+      if (!pass_has_variants(ctx, pass)) continue;
+      const int cls = pass_class(pass, fp64);
+      double best_t = 1e300;
+      int best_v = ctx->tune[prec][pass];
+      for (int v = 0; v < kVariants; ++v) {
+        ctx->tune[prec][pass] = v;
+        // one warm-up application, then the timed ones
+        if (fp64) STCHK(timing_apply<double>(ctx, nload, ctx->ptr<double>(ctx->off.x64)));
+        else STCHK(timing_apply<float>(ctx, nload, ctx->ptr<float>(ctx->off.d32)));
+        drain_timers(ctx);
+        const double t0 = ctx->tsum[cls];
+        const long long c0 = ctx->tcount[cls];
+        for (int r = 0; r < reps; ++r) {
+          if (fp64) STCHK(timing_apply<double>(ctx, nload, ctx->ptr<double>(ctx->off.x64)));
+          else STCHK(timing_apply<float>(ctx, nload, ctx->ptr<float>(ctx->off.d32)));
+        }
+        drain_timers(ctx);
+        const long long dc = ctx->tcount[cls] - c0;
+        const double t = dc > 0 ? (ctx->tsum[cls] - t0) / (double)dc : 1e300;
+        if (t < best_t) {
+          best_t = t;
+          best_v = v;
+        }
+      }
+      ctx->tune[prec][pass] = best_v;
+    }
+  }
+  // timing sums of the search are not the caller's
+  for (int k = 0; k < K_NCLASS; ++k) {
+    ctx->tsum[k] = 0.0;
+    ctx->tbytes[k] = 0.0;
+    ctx->tcount[k] = 0;
+  }
+  ctx->timing = saved_timing;
+  ctx->graph_epoch++;
+  ctx->have_solution = false;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (cache_path) {
+    std::vector<int> v(2 * NPASS);
+    for (int p = 0; p < 2; ++p)
+      for (int q = 0; q < NPASS; ++q) v[p * NPASS + q] = ctx->tune[p][q];
+    cache = read_tune_cache(cache_path);   // entries other processes may have added meanwhile
+    cache[key] = v;
+    if (!write_tune_cache(cache_path, cache)) return fail(ctx, LSH_EINVAL, std::string("cannot write ") + cache_path);
+  }
+  if (variants) lsh_get_variants(ctx, variants);
+  return LSH_OK;
+}
+
+lsh_status lsh_solve_many(int n, lsh_ctx* const* ctxs, int solver, const int32_t* nloads, const double* const* loads,
+                          double tol, int maxit, lsh_load_report* const* reports, lsh_solve_report* summaries,
+                          int32_t* statuses, int nthreads) {
+  if (n < 1 || !ctxs || !nloads || !loads) return LSH_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i] || !loads[i]) return LSH_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(ctxs[i], LSH_EINVAL, "a context appears twice in one ensemble solve");
+  }
+  if (nthreads < 1) nthreads = 4;
+  nthreads = std::min(nthreads, n);
+  std::vector<lsh_status> st(n, LSH_OK);
+  std::atomic<int> next{0};
+  auto worker = [&]() {
+    while (true) {
+      const int i = next.fetch_add(1);
+      if (i >= n) break;
+      lsh_ctx* c = ctxs[i];
+      // the worker runs on the device that holds the context's workspace
+      if (c->ws) {
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, c->ws) == hipSuccess) (void)hipSetDevice(attr.device);
+      }
+      st[i] = lsh_solve(c, solver, nloads[i], loads[i], tol, maxit, reports ? reports[i] : nullptr,
+                        summaries ? &summaries[i] : nullptr);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nthreads; ++t) pool.emplace_back(worker);
+  for (auto& th : pool) th.join();
+  lsh_status overall = LSH_OK;
+  for (int i = 0; i < n; ++i) {
+    if (statuses) statuses[i] = st[i];
+    if (st[i] < 0 && overall >= 0) overall = st[i];
+    if (st[i] == LSH_MAXIT && overall == LSH_OK) overall = LSH_MAXIT;
+  }
+  return overall;
 }
 
 lsh_status lsh_set_graphs(lsh_ctx* ctx, int enable) {

@@ -239,4 +239,11 @@ static __global__ __launch_bounds__(256) void k_scal(const int mode, const doubl
   }
 }
 
+// Deterministic smooth test pattern (kernel-shape timing inputs).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(const long long n, T* __restrict__ x) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] = static_cast<T>(1.0 + 1e-3 * (double)(i % 977));
+}
+
 }  // namespace lsh

@@ -298,3 +298,28 @@ def gradient_workload(n: int = 192, corr_length: float = 2.0, seed: int = 0) -> 
     loads = unit_loads(6)[[0, 5]]
     return GradientWorkload(theta, 0.3, elastic_isotropic_mandel(lam0, mu0), "filtered", loads,
                             np.diag([1.0, 0.5]), 1e-10)
+
+
+@dataclass
+class EnsembleMember:
+    """One realisation of a stochastic-homogenisation ensemble: a cube of n^3
+    voxels with per-voxel scalar conductivity a and its reference a0."""
+    n: int
+    a: np.ndarray           # (n, n, n)
+    a0: float
+
+
+def ensemble_workload(members: int = 48, sizes=(64, 96, 128, 160), corr_length: float = 4.0,
+                      sigma_log: float = 1.0, seed: int = 0):
+    """Members with sizes drawn uniformly from ``sizes``; a = exp(sigma_log g)
+    with g a periodic Gaussian field of correlation length ``corr_length``
+    voxels (one seed per member); reference a0 = min(a)/2, so that A - A0 is
+    positive definite everywhere.  The loads are the three unit gradients."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(members):
+        n = int(rng.choice(np.asarray(sizes)))
+        g = gaussian_random_field((n, n, n), corr_length, seed=seed * 100003 + i + 1)
+        a = np.exp(sigma_log * g)
+        out.append(EnsembleMember(n, a, 0.5 * float(a.min())))
+    return out

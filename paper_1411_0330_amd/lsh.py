@@ -68,6 +68,13 @@ _SIGS = {
     "lsh_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "lsh_forward_dft": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "lsh_spectrum_bytes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_size_t)]),
+    "lsh_set_variant": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    "lsh_get_variants": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "lsh_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int)]),
+    "lsh_solve_many": (C.c_int, [C.c_int, C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int32),
+                                 C.POINTER(C.POINTER(C.c_double)), C.c_double, C.c_int,
+                                 C.POINTER(C.POINTER(LoadReport)), C.POINTER(SolveReport), C.POINTER(C.c_int32),
+                                 C.c_int]),
     "lsh_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "lsh_set_graphs": (C.c_int, [C.c_void_p, C.c_int]),
     "lsh_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
@@ -333,6 +340,24 @@ class Context:
         return main, nyq
 
     # -- graphs and timing ---------------------------------------------
+    def set_variant(self, pass_, fp64, variant):
+        return self._check(self.lib.lsh_set_variant(self.h, int(pass_), int(bool(fp64)), int(variant)))
+
+    def variants(self):
+        """Current kernel shapes: {"fp32": [xfwd, y, zg, xinv], "fp64": [...]}."""
+        v = (C.c_int32 * 8)()
+        self._check(self.lib.lsh_get_variants(self.h, v))
+        return {"fp32": list(v[:4]), "fp64": list(v[4:])}
+
+    def autotune(self, nload=None, cache=None):
+        """Pick the fastest kernel shape per pass (lsh_autotune); returns
+        (variants, from_cache)."""
+        v = (C.c_int32 * 8)()
+        hit = C.c_int(0)
+        path = None if cache is None else os.fspath(cache).encode()
+        self._check(self.lib.lsh_autotune(self.h, int(nload or self.max_loads), path, v, C.byref(hit)))
+        return {"fp32": list(v[:4]), "fp64": list(v[4:])}, bool(hit.value)
+
     def set_graphs(self, enable=True):
         self._check(self.lib.lsh_set_graphs(self.h, 1 if enable else 0))
 
@@ -349,6 +374,38 @@ class Context:
         n = C.c_int()
         self._check(self.lib.lsh_kernel_times(self.h, names, ms, cnt, by, cap, C.byref(n)))
         return {names[i].decode(): (ms[i], int(cnt[i]), by[i]) for i in range(min(n.value, cap))}
+
+
+def solve_many(ctxs, loads, solver="cg", tol=1e-10, maxit=1000, threads=4, allow=(OK, MAXIT)):
+    """Solve several contexts concurrently (lsh_solve_many): ``loads[i]`` is
+    the (nload_i, c) array of context i.  Returns one report dict per context,
+    as Context.solve."""
+    lib = load()
+    n = len(ctxs)
+    arrs = [np.ascontiguousarray(np.atleast_2d(l), dtype=np.float64) for l in loads]
+    handles = (C.c_void_p * n)(*[c.h.value for c in ctxs])
+    nl = (C.c_int32 * n)(*[a.shape[0] for a in arrs])
+    lp = (C.POINTER(C.c_double) * n)(*[_dptr(a) for a in arrs])
+    reps = [(LoadReport * a.shape[0])() for a in arrs]
+    rp = (C.POINTER(LoadReport) * n)(*[C.cast(r, C.POINTER(LoadReport)) for r in reps])
+    summ = (SolveReport * n)()
+    sts = (C.c_int32 * n)()
+    for c in ctxs:
+        c._solver_buffer(SOLVERS[solver])
+    st = lib.lsh_solve_many(n, handles, SOLVERS[solver], nl, lp, float(tol), int(maxit), rp, summ, sts, int(threads))
+    out = []
+    for i, c in enumerate(ctxs):
+        c._check(sts[i], allow=allow)
+        c.nload = arrs[i].shape[0]
+        c.solves = getattr(c, "solves", 0) + 1
+        out.append({"status": sts[i], "iterations": [r.iterations for r in reps[i]],
+                    "load_status": [r.status for r in reps[i]],
+                    "rel_residual": [r.rel_residual for r in reps[i]],
+                    "applications_fp64": summ[i].applications_fp64, "applications_fp32": summ[i].applications_fp32,
+                    "outer_iterations": summ[i].outer_iterations, "seconds": summ[i].seconds})
+    if st not in allow and all(s in allow for s in sts):
+        raise LshError(st, "ensemble solve failed")
+    return out
 
 
 def header_symbols(header_path=None):

@@ -183,3 +183,25 @@ def test_voxel_moduli_and_gradient_validation():
     m32 = m.astype(np.float32)
     assert lib.lsh_set_voxel_moduli(h, C.c_void_p(m32.ctypes.data), L.F32, L.HOST, 2) == L.EHYP2
     lib.lsh_destroy(h)
+
+
+def test_variant_and_ensemble_validation():
+    lib = L.load()
+    st, h = _create(lib, 3, (8, 8, 8))
+    v = (C.c_int32 * 8)()
+    assert lib.lsh_get_variants(h, v) == L.OK and list(v) == [0] * 8
+    assert lib.lsh_set_variant(h, 2, 0, 3) == L.OK
+    assert lib.lsh_get_variants(h, v) == L.OK and v[2] == 3
+    assert lib.lsh_set_variant(h, 4, 0, 1) == L.EINVAL
+    assert lib.lsh_set_variant(h, 0, 1, 4) == L.EINVAL
+    # a context listed twice, and an empty ensemble, are refused before any work
+    handles = (C.c_void_p * 2)(h.value, h.value)
+    nl = (C.c_int32 * 2)(1, 1)
+    loads = np.ones(3)
+    lp = (C.POINTER(C.c_double) * 2)(loads.ctypes.data_as(C.POINTER(C.c_double)),
+                                     loads.ctypes.data_as(C.POINTER(C.c_double)))
+    assert lib.lsh_solve_many(2, handles, L.CG, nl, lp, 1e-6, 10, None, None, None, 2) == L.EINVAL
+    assert lib.lsh_solve_many(0, handles, L.CG, nl, lp, 1e-6, 10, None, None, None, 2) == L.EINVAL
+    # autotune needs the reference and material first
+    assert lib.lsh_autotune(h, 1, None, None, None) == L.ESTATE
+    lib.lsh_destroy(h)
