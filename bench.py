@@ -45,6 +45,13 @@ def parse():
     ap.add_argument("--no-small", action="store_true", help="skip the 64^2 launch-bound leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device copy (y = 1.0 * x) to calibrate HBM counters")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel shapes")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (default: the package's tune_cache.txt, written by the autotuner on MI355X)")
+    ap.add_argument("--ensemble", action="store_true",
+                    help="instead: the 48-member lognormal ensemble, sequential vs concurrent streams")
+    ap.add_argument("--gradient", action="store_true",
+                    help="instead: forward + backward of the 192^3 sensitivity workload (FP64)")
     return ap.parse_args()
 
 
@@ -181,12 +188,100 @@ def cpu_baseline(w, target_s=20.0):
     }
 
 
+def bench_ensemble(args):
+    """48 lognormal members (64/96/128/160), mixed CG to 1e-6, three loads each:
+    all members solved one after another, then by the concurrent scheduler."""
+    import numpy as np
+    import torch
+
+    from paper_1411_0330_amd import inputs as I
+    from paper_1411_0330_amd import lsh
+
+    lsh.load()
+    log("building the 48-member ensemble")
+    members = I.ensemble_workload()
+    ctxs = []
+    for m in members:
+        c = lsh.Context((m.n,) * 3, "scalar", "mixed", max_loads=3, stream=torch.cuda.Stream())
+        c.set_reference(m.a0 * np.eye(3))
+        c.set_voxel_moduli(torch.from_numpy(m.a[None]).to("cuda:0"))
+        c.set_green("filtered")
+        ctxs.append(c)
+    loads = [np.eye(3)] * len(ctxs)
+    lsh.solve_many(ctxs, loads, "cg", tol=1e-6, maxit=3000, threads=4)      # warm-up
+    res = {}
+    for threads in (1, 4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = lsh.solve_many(ctxs, loads, "cg", tol=1e-6, maxit=3000, threads=threads)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        apps = sum((r["applications_fp32"] + r["applications_fp64"]) * m.n ** 3 for r, m in zip(reps, members))
+        res[threads] = (dt, apps, max(max(r["rel_residual"]) for r in reps))
+        log(f"threads {threads}: {dt:.3f} s, {apps / dt:.3e} voxel-it/s")
+    dt, apps, worst = res[4]
+    print(json.dumps({
+        "metric": "ensemble voxel-iterations/s (48 lognormal members, mixed CG 1e-6)",
+        "value": apps / dt, "unit": "voxel-iterations/s", "n_gpus": 1, "higher_is_better": True,
+        "seconds": dt, "sequential_seconds": res[1][0], "concurrency_speedup": res[1][0] / dt,
+        "worst_rel_residual": worst, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "48 cubes, sizes uniform over 64/96/128/160 (seed 0), a = exp(g), g a periodic "
+                               "Gaussian field of correlation length 4, a0 = min(a)/2, filtered, 3 unit loads",
+                   "voxels": int(sum(m.n ** 3 for m in members)), "streams": 4}}), flush=True)
+
+
+def bench_gradient(args):
+    """Forward (batched FP64 solve of e1 and the Mandel shear unit) and backward
+    (lsh_gradient through torch.autograd) of J = C*_1111 + C*_1212 at 192^3."""
+    import torch
+
+    from paper_1411_0330_amd import inputs as I
+    from paper_1411_0330_amd import lsh
+    from paper_1411_0330_amd.autograd import homogenized_gram, young_to_bulk_shear
+
+    lsh.load()
+    w = I.gradient_workload(192)
+    ctx = lsh.Context(w.theta.shape, "elastic", "fp64", max_loads=2)
+    ctx.set_reference(w.A0)
+    ctx.set_green(w.green)
+    Wt = torch.tensor(w.W, device="cuda:0")
+    theta = torch.tensor(w.theta, device="cuda:0")
+
+    def step():
+        th = theta.clone().requires_grad_(True)
+        E = 1.0 + 9.0 * torch.sigmoid(th)
+        K, mu = young_to_bulk_shear(E, w.nu)
+        G = homogenized_gram(torch.stack([K, mu]), ctx, w.loads, tol=w.tol, maxit=3000)
+        J = (Wt * G).sum()
+        J.backward()
+        return J, th.grad
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nrep = max(1, args.steps)
+    for _ in range(nrep):
+        J, g = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / nrep
+    print(json.dumps({
+        "metric": "sensitivity dJ/dtheta, 192^3 elasticity FP64 (forward solve + backward)",
+        "value": dt, "unit": "s per forward+backward", "higher_is_better": False, "n_gpus": 1,
+        "J": J.item(), "grad_abs_max": float(g.abs().max()), "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "theta periodic Gaussian field (correlation 2), E = 1 + 9 sigmoid(theta), nu = 0.3, "
+                               "E0 = 0.5 nu0 = 0.3, filtered, loads e1 and e6, J = C*_1111 + C*_1212, tol 1e-10"}}),
+          flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: this build runs on a single GPU; --gpus must be 1 "
               "(the multi-GPU slab decomposition is a design note, not built).", file=sys.stderr)
         sys.exit(2)
+    if args.ensemble:
+        return bench_ensemble(args)
+    if args.gradient:
+        return bench_gradient(args)
 
     import numpy as np
     import torch
@@ -214,6 +309,14 @@ def main():
     ctx = lsh.Context(shape, "elastic", "mixed", max_loads=nload, device=dev)
     ctx.set_reference(w.A0)
     ctx.set_green(w.green)
+    tuned = None
+    if not args.no_autotune:
+        ctx.set_phases(phase_dev, w.moduli)
+        cache = args.tune_cache or os.path.join(ROOT, "paper_1411_0330_amd", "tune_cache.txt")
+        t0 = time.perf_counter()
+        variants, hit = ctx.autotune(nload, cache)
+        tuned = {"variants": variants, "cache_hit": hit, "seconds": round(time.perf_counter() - t0, 2)}
+        log(f"autotune: {tuned}")
     log(f"warmup {args.warmup} step(s)")
     if args.warmup > 0:
         run_steps(ctx, lsh, w, phase_dev, args.warmup, args)
@@ -257,6 +360,8 @@ def main():
                        "outer_refinements": rep["outer_iterations"], "per_load": rep["iterations"],
                        "final_rel_residual_fp64": rep["rel_residual"]},
     }
+    if tuned:
+        out["kernel_shapes"] = tuned
     if ktimes:
         out["roofline"] = roofline_from(ktimes)
         out["kernels"] = {k: {"ms": round(v[0], 3), "launches": v[1],

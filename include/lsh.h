@@ -267,7 +267,10 @@ lsh_status lsh_get_variants(const lsh_ctx* ctx, int32_t* variants);
 /*
  * Autotuner: times every shape of every pass that has several (the others
  * held at their current choice) with HIP events over operator applications
- * of nload loads on the context's own buffers, and keeps the fastest.
+ * of nload loads on the context's own buffers, in the modes the solvers run
+ * (the CG modes for FP32 fields of a mixed context and FP64 fields of an FP64
+ * context, the refinement modes for the FP64 passes of a mixed context), and
+ * keeps the fastest.
  * With cache_path (may be NULL) the choice is looked up first in, and
  * afterwards written to, a text file with one line per key: device, grid,
  * components, precision, nload, Green operator and material form.  A cache

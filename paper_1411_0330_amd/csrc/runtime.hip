@@ -994,13 +994,30 @@ int pass_class(int pass, bool fp64) {
   return base + (fp64 ? 1 : 0);
 }
 
-// One operator application on the workspace's own fields (timing input):
-// FP64 x64 -> FP64 spectrum, FP32 d -> FP32 spectrum.
-template <typename T>
-lsh_status timing_apply(lsh_ctx* ctx, int nload, T* tau) {
-  T* out = reinterpret_cast<T*>(Sel<T>::sm(ctx));
-  STCHK(forward_part<T>(ctx, 0, nload, XF_PLAIN, tau, nullptr, nullptr, nullptr, nullptr, true));
-  return inverse_x<T>(ctx, 0, nload, XI_APPLY, tau, out, nullptr, nullptr, nullptr, nullptr);
+// One operator application in the modes the solvers run, on the workspace's
+// own fields (timing input): the CG modes (x += alpha p and p = r + beta p
+// fused into the x pass, q and p.q out of the last) for FP32 fields of a mixed
+// context and FP64 fields of an FP64 context, the refinement modes (x64 += d,
+// FP64 residual to FP32) for the FP64 passes of a mixed context.
+lsh_status timing_iteration(lsh_ctx* ctx, int nload, bool fp64) {
+  double* parts = ctx->ptr<double>(ctx->off.partials);
+  if (!fp64) {
+    LoadState* st = ctx->ptr<LoadState>(ctx->off.st_in);
+    float* q = reinterpret_cast<float*>(Sel<float>::sm(ctx));
+    STCHK(forward_part<float>(ctx, 0, nload, XF_CG, ctx->ptr<float>(ctx->off.r32), ctx->ptr<float>(ctx->off.p32),
+                              ctx->ptr<float>(ctx->off.d32), nullptr, st, true));
+    return inverse_x<float>(ctx, 0, nload, XI_CG, ctx->ptr<float>(ctx->off.p32), q, nullptr, st, parts, nullptr);
+  }
+  LoadState* st = ctx->ptr<LoadState>(ctx->off.st_out);
+  double* x = ctx->ptr<double>(ctx->off.x64);
+  if (ctx->precision == LSH_MIXED) {
+    STCHK(forward_part<double>(ctx, 0, nload, XF_IRX, nullptr, x, nullptr, ctx->ptr<float>(ctx->off.d32), st, true));
+    return inverse_x<double>(ctx, 0, nload, XI_IRRES, x, nullptr, ctx->ptr<float>(ctx->off.r32), st, parts, nullptr);
+  }
+  double* q = reinterpret_cast<double*>(Sel<double>::sm(ctx));
+  STCHK(forward_part<double>(ctx, 0, nload, XF_CG, ctx->ptr<double>(ctx->off.r64), ctx->ptr<double>(ctx->off.p64), x,
+                             nullptr, st, true));
+  return inverse_x<double>(ctx, 0, nload, XI_CG, ctx->ptr<double>(ctx->off.p64), q, nullptr, st, parts, nullptr);
 }
 
 std::string tune_key(const lsh_ctx* ctx, int nload) {
@@ -1751,17 +1768,36 @@ lsh_status lsh_autotune(lsh_ctx* ctx, int nload, const char* cache_path, int32_t
   ctx->timing = true;
   ctx->nact = 1 << 30;
   const int reps = 3;
+  // inputs: smooth finite fields, and load states that take the full CG path
+  // (active, not the first step, a pending x update; zero steps keep the
+  // fields bounded)
+  {
+    const long long n = (long long)nload * ctx->F;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    std::vector<double*> f64 = {ctx->ptr<double>(ctx->off.x64)};
+    std::vector<float*> f32;
+    if (ctx->precision == LSH_MIXED) {
+      f32 = {ctx->ptr<float>(ctx->off.d32), ctx->ptr<float>(ctx->off.r32), ctx->ptr<float>(ctx->off.p32)};
+    } else {
+      f64.push_back(ctx->ptr<double>(ctx->off.r64));
+      f64.push_back(ctx->ptr<double>(ctx->off.p64));
+    }
+    for (double* f : f64) hipLaunchKernelGGL((k_fill<double>), dim3(nb), dim3(256), 0, ctx->stream, n, f);
+    for (float* f : f32) hipLaunchKernelGGL((k_fill<float>), dim3(nb), dim3(256), 0, ctx->stream, n, f);
+    STCHK(check_launch(ctx, 0, "fill"));
+    LoadState s0{};
+    s0.rr = s0.pq = s0.bb = s0.res2 = 1.0;
+    s0.active = 1;
+    s0.pending = 1;
+    std::vector<LoadState> hs((size_t)nload, s0);
+    HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.st_in, hs.data(), sizeof(LoadState) * nload, hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.st_out, hs.data(), sizeof(LoadState) * nload, hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
   for (int prec = ctx->precision == LSH_MIXED ? 0 : 1; prec < 2; ++prec) {
     const bool fp64 = prec == 1;
-    const long long n = (long long)nload * ctx->F;
-    if (fp64) {
-      hipLaunchKernelGGL((k_fill<double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n,
-                         ctx->ptr<double>(ctx->off.x64));
-    } else {
-      hipLaunchKernelGGL((k_fill<float>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n,
-                         ctx->ptr<float>(ctx->off.d32));
-    }
-    STCHK(check_launch(ctx, 0, "fill"));
     for (int pass = 0; pass < NPASS; ++pass) {
       if (!pass_has_variants(ctx, pass)) continue;
       const int cls = pass_class(pass, fp64);
@@ -1770,15 +1806,11 @@ lsh_status lsh_autotune(lsh_ctx* ctx, int nload, const char* cache_path, int32_t
       for (int v = 0; v < kVariants; ++v) {
         ctx->tune[prec][pass] = v;
         // one warm-up application, then the timed ones
-        if (fp64) STCHK(timing_apply<double>(ctx, nload, ctx->ptr<double>(ctx->off.x64)));
-        else STCHK(timing_apply<float>(ctx, nload, ctx->ptr<float>(ctx->off.d32)));
+        STCHK(timing_iteration(ctx, nload, fp64));
         drain_timers(ctx);
         const double t0 = ctx->tsum[cls];
         const long long c0 = ctx->tcount[cls];
-        for (int r = 0; r < reps; ++r) {
-          if (fp64) STCHK(timing_apply<double>(ctx, nload, ctx->ptr<double>(ctx->off.x64)));
-          else STCHK(timing_apply<float>(ctx, nload, ctx->ptr<float>(ctx->off.d32)));
-        }
+        for (int r = 0; r < reps; ++r) STCHK(timing_iteration(ctx, nload, fp64));
         drain_timers(ctx);
         const long long dc = ctx->tcount[cls] - c0;
         const double t = dc > 0 ? (ctx->tsum[cls] - t0) / (double)dc : 1e300;
