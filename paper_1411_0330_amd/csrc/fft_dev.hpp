@@ -272,6 +272,83 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[P], int t, cpx<T>* lds, i
   }
 }
 
+// The same transform on C pencils held by the same threads (v[j] = pencil j):
+// each stage reads its twiddles once for all pencils; the exchanges run pencil
+// by pencil through the one exchange buffer.
+template <int N, int P, int NS, int DIR, typename T, int C>
+__device__ __forceinline__ void fft_stages_multi(cpx<T> (&v)[C][P], int t, cpx<T>* lds, int es,
+                                                 const cpx<T>* __restrict__ tw, int tstride) {
+  if constexpr (NS < N) {
+    constexpr int P2 = pow2_part(P);
+    constexpr int R = (NS == 1) ? P : ((N / NS < P2) ? N / NS : P2);
+    static_assert(N % (NS * R) == 0, "pencil length must be a multiple of the stage spans");
+    constexpr int TT = N / P;
+    constexpr int G = P / R;  // butterflies per thread
+    constexpr bool last = (NS * R == N);
+    cpx<T> w[G][R];
+    if constexpr (NS > 1) {
+      static_for<0, G>([&](auto i_) {
+        constexpr int i = decltype(i_)::value;
+        const int k = (t + TT * i) % NS;
+        static_for<1, R>([&](auto r_) {
+          constexpr int r = decltype(r_)::value;
+          cpx<T> x = tw[(r * k * (N / (NS * R))) * tstride];
+          if constexpr (DIR > 0) x.y = -x.y;
+          w[i][r] = x;
+        });
+      });
+    }
+    static_for<0, C>([&](auto j_) {
+      constexpr int j = decltype(j_)::value;
+      static_for<0, G>([&](auto i_) {
+        constexpr int i = decltype(i_)::value;
+        cpx<T> u[R];
+        static_for<0, R>([&](auto r_) {
+          constexpr int r = decltype(r_)::value;
+          u[r] = v[j][i + r * G];
+        });
+        if constexpr (NS > 1) {
+          static_for<1, R>([&](auto r_) {
+            constexpr int r = decltype(r_)::value;
+            u[r] = cmul(u[r], w[i][r]);
+          });
+        }
+        dft<R, DIR>(u);
+        if constexpr (last) {
+          static_for<0, R>([&](auto r_) {
+            constexpr int r = decltype(r_)::value;
+            v[j][i + r * G] = u[r];
+          });
+        } else {
+          const int b = t + TT * i;
+          const int base = (b / NS) * NS * R + b % NS;
+          static_for<0, R>([&](auto r_) {
+            constexpr int r = decltype(r_)::value;
+            lds[(base + r * NS) * es] = u[r];
+          });
+        }
+      });
+      if constexpr (!last) {
+        __syncthreads();
+        static_for<0, P>([&](auto q_) {
+          constexpr int q = decltype(q_)::value;
+          v[j][q] = lds[(t + TT * q) * es];
+        });
+        __syncthreads();
+      }
+    });
+    if constexpr (!last) fft_stages_multi<N, P, NS * R, DIR, T, C>(v, t, lds, es, tw, tstride);
+  }
+}
+
+template <int N, int P, int DIR, typename T, int C>
+__device__ __forceinline__ void fft_pencil_multi(cpx<T> (&v)[C][P], int t, cpx<T>* lds, int es,
+                                                 const cpx<T>* __restrict__ tw, int tstride) {
+  static_assert(N == 1 || (P <= N && N % P == 0 && odd_part(N) == odd_part(P)),
+                "points per thread must divide the pencil length and carry its odd factor");
+  fft_stages_multi<N, P, 1, DIR, T, C>(v, t, lds, es, tw, tstride);
+}
+
 template <int N, int P, int DIR, typename T>
 __device__ __forceinline__ void fft_pencil(cpx<T> (&v)[P], int t, cpx<T>* lds, int es, const cpx<T>* __restrict__ tw,
                                            int tstride) {

@@ -88,9 +88,11 @@ __global__ __launch_bounds__(256) void k_xfwd(const Geo g, const int mode, const
   constexpr int TR = MX / P;
   constexpr int RPW = 256 / TR;
   __shared__ cpx<T> lds[RPW * MX];
+  __shared__ cpx<T> twl[2 * MX];
   const int l = blockIdx.y;
   if (st != nullptr && !st[l].active) return;
   const int tid = threadIdx.x;
+  for (int i = tid; i < 2 * MX; i += 256) twl[i] = twx[i];   // twiddles of the row length, staged in LDS
   const int slot = tid / TR, t = tid % TR;
   const long long rows = (long long)g.c * g.nz * g.ny;
   const long long row = (long long)blockIdx.x * RPW + slot;
@@ -149,7 +151,8 @@ __global__ __launch_bounds__(256) void k_xfwd(const Geo g, const int mode, const
   }
 
   cpx<T>* lrow = lds + slot * MX;
-  fft_pencil<MX, P, -1, T>(v, t, lrow, 1, twx, 2);
+  __syncthreads();
+  fft_pencil<MX, P, -1, T>(v, t, lrow, 1, twl, 2);
 
   // unpack the half-length transform: X[k] = E[k] + W_nx^k O[k]
 #pragma unroll
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(256) void k_xfwd(const Geo g, const int mode, const
       const cpx<T> zm = lrow[MX - k];
       const cpx<T> a = cpx<T>{z.x + zm.x, z.y - zm.y};   // Z + conj(Zm)
       const cpx<T> b = cpx<T>{z.x - zm.x, z.y + zm.y};   // Z - conj(Zm)
-      const cpx<T> wo = cmul(twx[k], mul_neg_i(b));
+      const cpx<T> wo = cmul(twl[k], mul_neg_i(b));
       if (valid) smain[so + k] = cpx<T>{T(0.5) * (a.x + wo.x), T(0.5) * (a.y + wo.y)};
     }
   }
@@ -184,9 +187,11 @@ __global__ __launch_bounds__(TX*(NY / P)) void k_y(const Geo g, cpx<T>* __restri
                                                   const LoadState* __restrict__ st, const int main_tiles) {
   constexpr int TY = NY / P;
   __shared__ cpx<T> lds[TX * NY];
+  __shared__ cpx<T> twl[NY];
   const int l = blockIdx.y;
   if (st != nullptr && !st[l].active) return;
   const int tid = threadIdx.x;
+  for (int i = tid; i < NY; i += TX * TY) twl[i] = twy[i];
   cpx<T>* base;
   long long es_g;
   cpx<T>* lp;
@@ -217,7 +222,8 @@ __global__ __launch_bounds__(TX*(NY / P)) void k_y(const Geo g, cpx<T>* __restri
   cpx<T> v[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) v[i] = valid ? base[(long long)(t + TY * i) * es_g] : cpx<T>{0, 0};
-  fft_pencil<NY, P, DIR, T>(v, t, lp, es_l, twy, 1);
+  __syncthreads();
+  fft_pencil<NY, P, DIR, T>(v, t, lp, es_l, twl, 1);
   if (valid) {
 #pragma unroll
     for (int i = 0; i < P; ++i) base[(long long)(t + TY * i) * es_g] = v[i];
@@ -234,9 +240,11 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
                                                    const LoadState* __restrict__ st, const int main_tiles) {
   constexpr int TZ = NZ / P;
   __shared__ cpx<T> lds[TX * NZ];
+  __shared__ cpx<T> twl[NZ];
   const int l = blockIdx.y;
   if (st != nullptr && !st[l].active) return;
   const int tid = threadIdx.x;
+  for (int i = tid; i < NZ; i += TX * TZ) twl[i] = twz[i];
   const int xl = tid % TX, t = tid / TX;
   cpx<T>* base;
   long long es_g, cstride;
@@ -268,8 +276,8 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
 #pragma unroll
     for (int i = 0; i < P; ++i)
       v[j][i] = valid ? base[j * cstride + (long long)(t + TZ * i) * es_g] : cpx<T>{0, 0};
-#pragma unroll
-  for (int j = 0; j < C; ++j) fft_pencil<NZ, P, -1, T>(v[j], t, lp, TX, twz, 1);
+  __syncthreads();
+  fft_pencil_multi<NZ, P, -1, T, C>(v, t, lp, TX, twl, 1);
   if (zmode == Z_GAMMA) {
     if (valid) {
 #pragma unroll
@@ -286,8 +294,7 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
         for (int j = 0; j < C; ++j) v[j][i] = w[j];
       }
     }
-#pragma unroll
-    for (int j = 0; j < C; ++j) fft_pencil<NZ, P, 1, T>(v[j], t, lp, TX, twz, 1);
+    fft_pencil_multi<NZ, P, 1, T, C>(v, t, lp, TX, twl, 1);
   }
   if (valid) {
 #pragma unroll
@@ -396,6 +403,7 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
   constexpr int RPW = 256 / TR;
   constexpr int TABW = 2 * C * C + 5;
   __shared__ cpx<T> lds[RPW * MX];
+  __shared__ cpx<T> twl[2 * MX];
   __shared__ T tab[kMaxPhases * TABW];
   __shared__ double red[4];
   const Geo& g = a.g;
@@ -403,6 +411,7 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
   if (a.st != nullptr && !a.st[l].active) return;
   const int tid = threadIdx.x;
   for (int i = tid; i < a.nphase * TABW; i += 256) tab[i] = a.ptab[i];
+  for (int i = tid; i < 2 * MX; i += 256) twl[i] = a.twx[i];
   const int slot = tid / TR, t = tid % TR;
   const long long vrows = (long long)g.nz * g.ny;
   const long long vr = (long long)blockIdx.x * RPW + slot;
@@ -423,32 +432,28 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
     for (int i = 0; i < P; ++i) gam[j][i] = sm[t + TR * i];
     nqs[j] = a.snyq[(long long)l * nyq_cpx(g) + srow];
   }
+  // repack each component's half spectrum as the half-length complex
+  // transform 2Z = 2E + i 2O, then the inverse transforms of all components
 #pragma unroll
   for (int j = 0; j < C; ++j) {
-    cpx<T> v[P];
-#pragma unroll
-    for (int i = 0; i < P; ++i) v[i] = gam[j][i];
     const cpx<T> nq = nqs[j];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < P; ++i) lrow[t + TR * i] = v[i];
+    for (int i = 0; i < P; ++i) lrow[t + TR * i] = gam[j][i];
     __syncthreads();
-    // repack the half spectrum as the half-length complex transform 2Z = 2E + i 2O
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const int k = t + TR * i;
-      const cpx<T> xk = v[i];
+      const cpx<T> xk = gam[j][i];
       const cpx<T> xm = (k == 0) ? nq : lrow[MX - k];
       const cpx<T> e = cpx<T>{xk.x + xm.x, xk.y - xm.y};          // 2E = X + conj(Xm)
       const cpx<T> d = cpx<T>{xk.x - xm.x, xk.y + xm.y};          // X - conj(Xm)
-      const cpx<T> o = cmulc(d, a.twx[k]);                        // 2O = (X - conj Xm) W^{-k}
-      v[i] = cadd(e, mul_i(o));
+      const cpx<T> o = cmulc(d, twl[k]);                          // 2O = (X - conj Xm) W^{-k}
+      gam[j][i] = cadd(e, mul_i(o));
     }
-    __syncthreads();
-    fft_pencil<MX, P, 1, T>(v, t, lrow, 1, a.twx, 2);
-#pragma unroll
-    for (int i = 0; i < P; ++i) gam[j][i] = v[i];
   }
+  __syncthreads();
+  fft_pencil_multi<MX, P, 1, T, C>(gam, t, lrow, 1, twl, 2);
 
   // the route above returns N^d times the inverse DFT: a.scale = 1/N^d
   const T sc = a.scale;
