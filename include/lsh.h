@@ -256,7 +256,10 @@ lsh_status lsh_spectrum_bytes(const lsh_ctx* ctx, int dtype, size_t* bytes);
  * Kernel shapes.  The transform passes over 128- and 256-point axes are
  * compiled in four workgroup shapes each (pencils per workgroup and points
  * per thread); pass 0..3 = x forward, y, z with Green operator, x inverse, for
- * the FP32 (fp64 = 0) or FP64 (fp64 = 1) kernels.  Every shape computes the
+ * the FP32 (fp64 = 0) or FP64 (fp64 = 1) kernels.  The z pass has a fifth
+ * shape (4): one workgroup per wave-vector tile handles every load, forming
+ * the operator matrices once (FP32, truncated, filtered and consistent
+ * operators; otherwise shape 0 runs).  Every shape computes the
  * same result; only speed differs.  lsh_get_variants writes the 8 current
  * choices (FP32 passes, then FP64).  The environment variable LSH_TUNE (for
  * example "zg32=1,xinv64=2") sets them when the context is created.

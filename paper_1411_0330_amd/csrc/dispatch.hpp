@@ -71,7 +71,25 @@ struct XfwdArgs {
 //                            3 = a quarter.
 // Shapes that break a limit (threads, LDS, points) fall back to the default.
 constexpr int kVariants = 4;
+// The z pass has one more shape: 4 = all loads of a tile in one workgroup with
+// the operator matrices formed once (FP32 fields, operators other than the
+// finite-difference one, 128- and 256-point z axes; elsewhere it falls back
+// to shape 0).
+constexpr int kVariantsZ = 5;
 enum : int { PASS_XFWD = 0, PASS_Y = 1, PASS_ZG = 2, PASS_XINV = 3, NPASS = 4 };
+constexpr int pass_variants(int pass) { return pass == PASS_ZG ? kVariantsZ : kVariants; }
+
+// multi-load z pass shape: points per thread (registers hold the operator
+// matrices of every point) and at most 512 threads
+template <typename T, int C> constexpr int p_zm(int n) {
+  if (odd_part(n) > 1) return p_odd<T>(n, 2);
+  return cmin(C == 6 ? 4 : 8, n);
+}
+template <typename T> constexpr int tx_zm(int n, int p) {
+  int tx = tx_strided<T>(n, p);
+  while (tx > 1 && tx * (n / p) > 512) tx /= 2;
+  return tx;
+}
 
 template <typename T> int launch_xfwd(hipStream_t s, const XfwdArgs<T>& a, int nload, int variant = 0);
 template <typename T> int launch_y(hipStream_t s, const Geo& g, int dir, cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw,

@@ -284,6 +284,186 @@ __device__ __forceinline__ void bd_apply_real(const BD<T>& s, T inv2mu, T kappa,
   o[5] = r2 * (s12 * inv2mu - kappa * d12);
 }
 
+// ----------------------------------------------------------------------------
+// The operator at one wave-vector as a real symmetric c x c matrix (upper
+// triangle, row-major, c(c+1)/2 entries): truncated, filtered and consistent
+// operators (the finite-difference one is complex Hermitian and stays with
+// green_apply).  Used where one matrix serves several loads.
+// ----------------------------------------------------------------------------
+// Mandel matrix of (B t + t B)/(2 mu0) - kappa D:t.  With the tensor
+// (d_ik B_jl + d_il B_jk + d_jk B_il + d_jl B_ik)/(4 mu0) - kappa D_ijkl and
+// weights 1 (normal) and sqrt 2 (shear) per Mandel index.
+template <typename T>
+__device__ __forceinline__ void bd_matrix(const BD<T>& s, T inv2mu, T kappa, T (&G)[21]) {
+  constexpr T r2 = T(1.4142135623730950488);
+  const T im = T(2) * inv2mu, h = inv2mu, k2 = T(2) * kappa;
+  // row 0: (11, .)
+  G[0] = s.b11 * im - kappa * s.d1111;
+  G[1] = -kappa * s.d1122;
+  G[2] = -kappa * s.d1133;
+  G[3] = -r2 * kappa * s.d1123;
+  G[4] = r2 * (s.b13 * h - kappa * s.d1113);
+  G[5] = r2 * (s.b12 * h - kappa * s.d1112);
+  // row 1: (22, .)
+  G[6] = s.b22 * im - kappa * s.d2222;
+  G[7] = -kappa * s.d2233;
+  G[8] = r2 * (s.b23 * h - kappa * s.d2223);
+  G[9] = -r2 * kappa * s.d2213;
+  G[10] = r2 * (s.b12 * h - kappa * s.d2221);
+  // row 2: (33, .)
+  G[11] = s.b33 * im - kappa * s.d3333;
+  G[12] = r2 * (s.b23 * h - kappa * s.d3332);
+  G[13] = r2 * (s.b13 * h - kappa * s.d3331);
+  G[14] = -r2 * kappa * s.d3312;
+  // rows 3..5: shear-shear
+  G[15] = (s.b22 + s.b33) * h - k2 * s.d2233;
+  G[16] = s.b12 * h - k2 * s.d3312;
+  G[17] = s.b13 * h - k2 * s.d2213;
+  G[18] = (s.b11 + s.b33) * h - k2 * s.d1133;
+  G[19] = s.b23 * h - k2 * s.d1123;
+  G[20] = (s.b11 + s.b22) * h - k2 * s.d1122;
+}
+
+template <typename T, int C>
+__device__ __forceinline__ void green_matrix(const GreenParams& gp, const GreenTabs<T>& tb, const int (&k)[3],
+                                             long long tidx, T (&G)[C * (C + 1) / 2]) {
+  constexpr int NE = C * (C + 1) / 2;
+  if (gp.variant == kGreenConsistent) {
+    const T* e = tb.tab + tidx * NE;
+#pragma unroll
+    for (int q = 0; q < NE; ++q) G[q] = e[q];
+    return;
+  }
+  bool nyq = false, zero = true;
+  T xi[3] = {T(0), T(0), T(0)};
+  constexpr int D = (C == 6) ? 3 : C;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const int n = gp.n[a];
+    const int kc = (k[a] <= n / 2) ? k[a] : k[a] - n;
+    xi[a] = static_cast<T>(kc);
+    nyq |= ((n & 1) == 0) && (k[a] == n / 2);
+    zero &= (k[a] == 0);
+  }
+  if (gp.variant == kGreenTruncated && (nyq || zero)) {
+    // A0^{-1} at the Nyquist frequencies, zero at k = 0
+    int q = 0;
+#pragma unroll
+    for (int i = 0; i < C; ++i)
+#pragma unroll
+      for (int j = i; j < C; ++j) {
+        T v = T(0);
+        if (nyq) {
+          if constexpr (C == 6) v = (i == j ? static_cast<T>(gp.s0_diag) : T(0)) + ((i < 3 && j < 3) ? static_cast<T>(gp.s0_vol) : T(0));
+          else v = static_cast<T>(gp.a0inv[3 * i + j]);
+        }
+        G[q++] = v;
+      }
+    return;
+  }
+  if constexpr (C == 6) {
+    BD<T> s;
+    bd_zero(s);
+    if (gp.variant == kGreenTruncated) {
+      bd_add(s, T(1), xi[0], xi[1], xi[2]);
+    } else {
+      cpx<T> wa[3];
+      T x0[3], x1[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        wa[a] = tb.w[a * tb.wstride + k[a]];
+        x0[a] = static_cast<T>(k[a]);
+        x1[a] = static_cast<T>(k[a] - gp.n[a]);
+      }
+      const T wxy[4] = {wa[0].x * wa[1].x, wa[0].y * wa[1].x, wa[0].x * wa[1].y, wa[0].y * wa[1].y};
+#pragma unroll
+      for (int alias = 0; alias < 8; ++alias) {
+        const T w = wxy[alias & 3] * ((alias & 4) ? wa[2].y : wa[2].x);
+        bd_add(s, w, (alias & 1) ? x1[0] : x0[0], (alias & 2) ? x1[1] : x0[1], (alias & 4) ? x1[2] : x0[2]);
+      }
+    }
+    bd_matrix(s, static_cast<T>(0.5 / gp.mu0), static_cast<T>(gp.kappa), G);
+  } else {
+    T A[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) A[i][j] = static_cast<T>(gp.a0[3 * i + j]);
+    T M[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) M[i][j] = 0;
+    if (gp.variant == kGreenTruncated) {
+      T den = 0;
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) den += xi[i] * A[i][j] * xi[j];
+      const T inv = T(1) / den;
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) M[i][j] = xi[i] * xi[j] * inv;
+    } else {
+      cpx<T> wa[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) wa[a] = tb.w[a * tb.wstride + k[a]];
+#pragma unroll
+      for (int alias = 0; alias < (1 << D); ++alias) {
+        T w = 1;
+        T x[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const bool lo = (alias >> a) & 1;
+          w *= lo ? wa[a].y : wa[a].x;
+          x[a] = static_cast<T>(lo ? k[a] - gp.n[a] : k[a]);
+        }
+        T den = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j) den += x[i] * A[i][j] * x[j];
+        if (w != T(0) && den > T(0)) {
+          const T f = w * recip(den);
+#pragma unroll
+          for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) M[i][j] += f * x[i] * x[j];
+        }
+      }
+    }
+    int q = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = i; j < D; ++j) G[q++] = M[i][j];
+  }
+}
+
+// Symmetric matrix (upper triangle, row-major) applied to a complex c-vector.
+template <typename T, int C>
+__device__ __forceinline__ void sym_apply(const T (&G)[C * (C + 1) / 2], cpx<T> (&v)[C]) {
+  cpx<T> o[C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) o[i] = cpx<T>{0, 0};
+  int q = 0;
+#pragma unroll
+  for (int i = 0; i < C; ++i)
+#pragma unroll
+    for (int j = i; j < C; ++j) {
+      const T g = G[q++];
+      o[i].x += g * v[j].x;
+      o[i].y += g * v[j].y;
+      if (j != i) {
+        o[j].x += g * v[i].x;
+        o[j].y += g * v[i].y;
+      }
+    }
+#pragma unroll
+  for (int i = 0; i < C; ++i) v[i] = o[i];
+}
+
 template <typename T>
 __device__ __forceinline__ void green_elastic(const GreenParams& gp, const GreenTabs<T>& tb, const int (&k)[3],
                                               cpx<T> (&v)[6]) {
@@ -333,16 +513,10 @@ __device__ __forceinline__ void green_elastic(const GreenParams& gp, const Green
       bd_add(s, w, (alias & 1) ? x1[0] : x0[0], (alias & 2) ? x1[1] : x0[1], (alias & 4) ? x1[2] : x0[2]);
     }
   }
-  T re[6], im[6], ore[6], oim[6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    re[i] = v[i].x;
-    im[i] = v[i].y;
-  }
-  bd_apply_real(s, inv2mu, kappa, re, ore);
-  bd_apply_real(s, inv2mu, kappa, im, oim);
-#pragma unroll
-  for (int i = 0; i < 6; ++i) v[i] = cpx<T>{ore[i], oim[i]};
+  // the Mandel matrix once, applied to the real and imaginary parts together
+  T G[21];
+  bd_matrix(s, inv2mu, kappa, G);
+  sym_apply<T, 6>(G, v);
 }
 
 // Dispatch on the operator; `tidx` is the wave-vector's position in the

@@ -16,6 +16,20 @@ static int z_inst(hipStream_t s, const Geo& g, const GreenParams& gp, const Gree
   return main_tiles + nyq_tiles;
 }
 
+template <typename T, int NZ, int C>
+static int zm_inst(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, cpx<T>* sm,
+                   cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload) {
+  constexpr int P = p_zm<T, C>(NZ);
+  constexpr int TX = tx_zm<T>(NZ, P);
+  constexpr int NT = TX * (NZ / P);
+  const int xtiles = (g.mx + TX - 1) / TX;
+  const int main_tiles = g.ny * xtiles;
+  const int nyq_tiles = (g.ny + TX - 1) / TX;
+  hipLaunchKernelGGL((k_zgm<T, NZ, P, TX, C>), dim3(main_tiles + nyq_tiles, 1), dim3(NT), 0, s, g, gp, tb, sm, sn,
+                     tw, st, main_tiles, nload);
+  return main_tiles + nyq_tiles;
+}
+
 template <typename T, int NZ, int C, int V>
 static int z_var(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, int zmode, cpx<T>* sm,
                  cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload) {
@@ -31,6 +45,10 @@ static int z_var(hipStream_t s, const Geo& g, const GreenParams& gp, const Green
 template <typename T, int NZ, int C>
 static int z_one(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, int zmode, cpx<T>* sm,
                  cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload, int variant = 0) {
+  if constexpr (sizeof(T) == 4 && (NZ == 128 || NZ == 256) && C != 2) {
+    if (variant == 4 && zmode == Z_GAMMA && gp.variant != kGreenFD)
+      return zm_inst<T, NZ, C>(s, g, gp, tb, sm, sn, tw, st, nload);
+  }
   if constexpr (NZ == 128 || NZ == 256) {
     switch (variant) {
       case 1: return z_var<T, NZ, C, 1>(s, g, gp, tb, zmode, sm, sn, tw, st, nload);

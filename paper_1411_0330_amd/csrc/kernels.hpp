@@ -305,6 +305,92 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
 }
 
 // ----------------------------------------------------------------------------
+// The same z pass for every load of a tile in one workgroup (truncated,
+// filtered and consistent operators): the operator matrices of the thread's
+// wave-vectors are formed once and applied to each load in turn, so the alias
+// sums (or the stored-table reads) are shared by all loads.
+// ----------------------------------------------------------------------------
+template <typename T, int NZ, int P, int TX, int C>
+__global__ __launch_bounds__(TX*(NZ / P)) void k_zgm(const Geo g, const GreenParams gp, const GreenTabs<T> tb,
+                                                    cpx<T>* __restrict__ smain, cpx<T>* __restrict__ snyq,
+                                                    const cpx<T>* __restrict__ twz, const LoadState* __restrict__ st,
+                                                    const int main_tiles, const int nload) {
+  constexpr int TZ = NZ / P;
+  constexpr int NE = C * (C + 1) / 2;
+  __shared__ cpx<T> lds[TX * NZ];
+  __shared__ cpx<T> twl[NZ];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NZ; i += TX * TZ) twl[i] = twz[i];
+  const int xl = tid % TX, t = tid / TX;
+  cpx<T>* base;
+  long long es_g, cstride, lstride;
+  int kx, ky;
+  bool valid;
+  if ((int)blockIdx.x < main_tiles) {
+    const int xtiles = (g.mx + TX - 1) / TX;
+    const int xc = blockIdx.x % xtiles;
+    ky = blockIdx.x / xtiles;
+    kx = xc * TX + xl;
+    valid = kx < g.mx;
+    base = smain + (long long)ky * g.mx + (valid ? kx : 0);
+    es_g = (long long)g.ny * g.mx;
+    cstride = (long long)g.nz * g.ny * g.mx;
+    lstride = main_cpx(g);
+  } else {
+    ky = (blockIdx.x - main_tiles) * TX + xl;
+    kx = g.mx;
+    valid = ky < g.ny;
+    base = snyq + (valid ? ky : 0);
+    es_g = g.ny;
+    cstride = (long long)g.nz * g.ny;
+    lstride = nyq_cpx(g);
+  }
+  T G[P][NE];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int kz = t + TZ * i;
+    const int k[3] = {kx, ky, kz};
+    const long long tidx = (kx < g.mx) ? ((long long)kz * g.ny + ky) * g.mx + kx
+                                       : (long long)g.nz * g.ny * g.mx + (long long)kz * g.ny + ky;
+    if (valid) {
+      green_matrix<T, C>(gp, tb, k, tidx, G[i]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < NE; ++q) G[i][q] = T(0);
+    }
+  }
+  cpx<T>* lp = lds + xl;
+  __syncthreads();
+  for (int l = 0; l < nload; ++l) {
+    if (st != nullptr && !st[l].active) continue;   // the same for every thread of the workgroup
+    cpx<T>* b = base + (long long)l * lstride;
+    cpx<T> v[C][P];
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        v[j][i] = valid ? b[j * cstride + (long long)(t + TZ * i) * es_g] : cpx<T>{0, 0};
+    fft_pencil_multi<NZ, P, -1, T, C>(v, t, lp, TX, twl, 1);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      cpx<T> w[C];
+#pragma unroll
+      for (int j = 0; j < C; ++j) w[j] = v[j][i];
+      sym_apply<T, C>(G[i], w);
+#pragma unroll
+      for (int j = 0; j < C; ++j) v[j][i] = w[j];
+    }
+    fft_pencil_multi<NZ, P, 1, T, C>(v, t, lp, TX, twl, 1);
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < C; ++j)
+#pragma unroll
+        for (int i = 0; i < P; ++i) b[j * cstride + (long long)(t + TZ * i) * es_g] = v[j][i];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
 // x inverse: C2R, scaling, local term and solver epilogue
 // ----------------------------------------------------------------------------
 template <typename T>

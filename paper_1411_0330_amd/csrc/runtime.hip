@@ -613,7 +613,7 @@ void tune_from_env(lsh_ctx* ctx) {
       const int val = std::atoi(item.c_str() + eq + 1);
       for (int p = 0; p < NPASS; ++p)
         for (int prec = 0; prec < 2; ++prec)
-          if (key == std::string(names[p]) + (prec ? "64" : "32") && val >= 0 && val < kVariants)
+          if (key == std::string(names[p]) + (prec ? "64" : "32") && val >= 0 && val < pass_variants(p))
             ctx->tune[prec][p] = val;
     }
     pos = end + 1;
@@ -1043,7 +1043,7 @@ std::map<std::string, std::vector<int>> read_tune_cache(const char* path) {
     while (vs >> x) v.push_back(x);
     if (v.size() != 2 * NPASS) continue;
     bool ok = true;
-    for (int y : v) ok &= (y >= 0 && y < kVariants);
+    for (size_t i = 0; i < v.size(); ++i) ok &= (v[i] >= 0 && v[i] < pass_variants((int)(i % NPASS)));
     if (ok) m[line.substr(0, eq)] = v;
   }
   return m;
@@ -1730,7 +1730,8 @@ lsh_status lsh_forward_dft(lsh_ctx* ctx, int nload, const void* field, void* spe
 
 lsh_status lsh_set_variant(lsh_ctx* ctx, int pass, int fp64, int variant) {
   if (!ctx) return LSH_EINVAL;
-  if (pass < 0 || pass >= NPASS || variant < 0 || variant >= kVariants) return fail(ctx, LSH_EINVAL, "bad pass or variant");
+  if (pass < 0 || pass >= NPASS || variant < 0 || variant >= pass_variants(pass))
+    return fail(ctx, LSH_EINVAL, "bad pass or variant");
   ctx->tune[fp64 ? 1 : 0][pass] = variant;
   ctx->graph_epoch++;
   return LSH_OK;
@@ -1803,7 +1804,7 @@ lsh_status lsh_autotune(lsh_ctx* ctx, int nload, const char* cache_path, int32_t
       const int cls = pass_class(pass, fp64);
       double best_t = 1e300;
       int best_v = ctx->tune[prec][pass];
-      for (int v = 0; v < kVariants; ++v) {
+      for (int v = 0; v < pass_variants(pass); ++v) {
         ctx->tune[prec][pass] = v;
         // one warm-up application, then the timed ones
         STCHK(timing_iteration(ctx, nload, fp64));

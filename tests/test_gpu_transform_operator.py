@@ -224,3 +224,41 @@ def test_fd_and_consistent_operators_match_oracle(lsh, physics, shape, variant, 
     out = ctx.apply(to_dev(tau, dtype)).cpu().numpy()
     ref = np.stack([op.apply(pb, tau[l]) for l in range(2)])
     assert rel_max_err(out, ref) <= (1e-12 if dtype == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("green", ["truncated", "filtered", "consistent"])
+@pytest.mark.parametrize("physics,shape,nload", [("scalar", (128, 8, 16), 3), ("elastic", (256, 4, 8), 4),
+                                                 ("elastic", (128, 16, 32), 1)])
+def test_multi_load_z_pass_matches_oracle(lsh, monkeypatch, physics, shape, nload, green):
+    # z pass shape 4: every load of a tile in one workgroup, operator matrices formed once
+    monkeypatch.setenv("LSH_TUNE", "zg32=4")
+    ph, moduli, A0 = _op_setup(physics, shape, green, "masked")
+    pb = problem(ph, moduli, A0, physics, green)
+    ctx = context(lsh, ph, moduli, A0, physics, green, precision="mixed", max_loads=nload)
+    if green == "consistent":
+        ctx.set_green(green, series=2)
+        pb.series = 2
+    assert ctx.variants()["fp32"][2] == 4
+    m = op.mask(pb)
+    tau = I.random_field(shape, pb.c, nload, seed=21) * m
+    out = ctx.apply(to_dev(tau, "f32")).cpu().numpy()
+    ref = np.stack([op.apply(pb, tau[l]) for l in range(nload)])
+    assert rel_max_err(out, ref) <= 1e-5
+
+
+def test_multi_load_z_pass_in_a_batched_solve(lsh, monkeypatch):
+    # loads converging at different steps: frozen loads are skipped inside the workgroup loop
+    ph = I.random_phases((128, 16, 16), 2, seed=5)
+    moduli = np.stack([ELAS[0], ELAS[1]])
+    loads = np.eye(6)[[0, 3, 5]] * np.array([[1.0], [1e-3], [5.0]])
+    res = {}
+    for tune in ("", "zg32=4"):
+        monkeypatch.setenv("LSH_TUNE", tune)
+        ctx = context(lsh, ph, moduli, C0, "elastic", "filtered", precision="mixed", max_loads=3)
+        rep = ctx.solve(loads, "cg", tol=1e-8, maxit=2000)
+        assert rep["status"] == lsh.OK
+        res[tune] = (ctx.effective().copy(), rep["iterations"])
+    A0_, it0 = res[""]
+    A4, it4 = res["zg32=4"]
+    assert rel_max_err(A4, A0_) <= 1e-7
+    assert all(abs(a - b) <= 3 for a, b in zip(it0, it4))
