@@ -28,6 +28,8 @@ FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
 UNITS = [
     ("k_x.hip", "k_x_f32.o", ["-DLSH_X_TYPE=float"]),
     ("k_x.hip", "k_x_f64.o", ["-DLSH_X_TYPE=double"]),
+    ("k_xc.hip", "k_xc_f32.o", ["-DLSH_XC_TYPE=float"]),
+    ("k_xc.hip", "k_xc_f64.o", ["-DLSH_XC_TYPE=double"]),
     ("k_y.hip", "k_y_f32.o", ["-DLSH_Y_TYPE=float"]),
     ("k_y.hip", "k_y_f64.o", ["-DLSH_Y_TYPE=double"]),
     ("k_z.hip", "k_z_f32.o", ["-DLSH_Z_TYPE=float"]),

@@ -96,7 +96,10 @@ template <typename T> int launch_y(hipStream_t s, const Geo& g, int dir, cpx<T>*
                                    const LoadState* st, int nload, int variant = 0);
 template <typename T> int launch_zg(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb,
                                     int zmode, cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw, const LoadState* st,
-                                    int nload, int variant = 0);
+                                    int nload, int variant = 0, double* qpart = nullptr, int pstride = 0);
+// x forward of conjugate gradients over all components of a voxel row (returns
+// the workgroups per load, i.e. the partials written per load)
+template <typename T> int launch_xfwdc(hipStream_t s, const XfwdcArgs<T>& a, int nload);
 template <typename T> int launch_xinv(hipStream_t s, const XinvArgs<T>& a, int nload, int variant = 0);
 
 // strided-pass shape of a variant: (pencils per workgroup, points per thread)
@@ -115,6 +118,11 @@ constexpr int rv_p(int mx, int p0, int v) {
 }
 
 // number of workgroups per load of the reducing passes (partials sizing)
+// workgroups per load of the z pass (partials of its spectral form), any shape
+template <typename T> inline long long zg_blocks_max(const Geo& g) {
+  // the narrowest tile of any shape: 1 pencil along x
+  return (long long)g.ny * g.mx + g.ny;
+}
 inline long long xinv_blocks(const Geo& g, int p) {
   const int tr = g.mx / p;
   const int rpw = 256 / tr;

@@ -50,7 +50,8 @@ __host__ __device__ inline long long main_cpx(const Geo& g) { return (long long)
 __host__ __device__ inline long long nyq_cpx(const Geo& g) { return (long long)g.c * g.nz * g.ny; }
 
 enum : int { XF_PLAIN = 0, XF_CG = 1, XF_IRX = 2 };
-enum : int { XI_APPLY = 0, XI_CG = 1, XI_BASIC = 2, XI_IRRES = 3, XI_RESNORM = 4, XI_STRAIN = 5, XI_EM = 6 };
+enum : int { XI_APPLY = 0, XI_CG = 1, XI_BASIC = 2, XI_IRRES = 3, XI_RESNORM = 4, XI_STRAIN = 5, XI_EM = 6,
+              XI_CGR = 7 };
 enum : int { Z_GAMMA = 0, Z_FWD = 1 };
 enum : int { SC_INIT = 0, SC_ALPHA = 1, SC_BETA = 2, SC_BASIC = 3, SC_OUTER = 4, SC_SUM = 5 };
 
@@ -178,6 +179,245 @@ __global__ __launch_bounds__(256) void k_xfwd(const Geo g, const int mode, const
   }
 }
 
+// Row j of a per-phase c x c matrix applied to v.  Table row layout:
+// [(A-A0)^{-1} (c*c) | (A-A0) (c*c) | in-I0 flag | a_inv b_inv a_dir b_dir]
+// where, when every phase is "isotropic", each matrix is a Id + b m m^T with
+// m the indicator of the three normal Mandel components (b = 0 for scalar
+// problems), and the short form is used.
+template <typename T, int C>
+__device__ __forceinline__ T phase_row(const T* tb, int which, bool iso, int j, const T (&v)[C]) {
+  if (iso) {
+    const T a = tb[2 * C * C + 1 + 2 * which], b = tb[2 * C * C + 2 + 2 * which];
+    T r = a * v[j];
+    if (C == 6 && j < 3) r += b * (v[0] + v[1] + v[2]);
+    return r;
+  }
+  const T* M = tb + which * C * C + j * C;
+  T r = 0;
+#pragma unroll
+  for (int m = 0; m < C; ++m) r += M[m] * v[m];
+  return r;
+}
+
+// Local operator of one voxel: a row of the phase table, or (per-voxel mode)
+// the short form a_inv Id + b_inv m m^T of (A_beta - A0)^{-1} with its
+// inverse a_dir = 1/a_inv, b_dir = -b_inv / (a_inv (a_inv + 3 b_inv)).
+// a_inv = 0 marks a voxel outside I0.
+template <typename T>
+struct Loc {
+  const T* tb;
+  T in, ai, bi;
+};
+
+// which = 0: (A - A0)^{-1}; 1: the table's second matrix, i.e. (A - A0) for
+// the basic scheme or (A - A0)(A + A0)^{-1} for Eyre--Milton; per-voxel mode
+// forms the first (which 1) or the second (which 2, from 2 A0 = (ea, eb)) in place.
+// (A - A0)(A + A0)^{-1} = (Id + 2 A0 (A - A0)^{-1})^{-1}, with
+// 2 A0 (a_inv Id + b_inv m m^T) = 4 mu0 a_inv Id + (4 mu0 b_inv + 2 lambda0 (a_inv + 3 b_inv)) m m^T.
+template <typename T>
+__device__ __forceinline__ void iso_inverse(T& a, T& b, bool six) {
+  const bool z = a == T(0);
+  const T ad = z ? T(0) : T(1) / a;
+  b = (six && !z) ? -b / (a * (a + T(3) * b)) : T(0);
+  a = ad;
+}
+
+// v . (A - A0)^{-1} v at one voxel (the local quadratic form)
+template <typename T, int C>
+__device__ __forceinline__ T loc_quad(const Loc<T>& L, bool vm, bool iso, const T (&v)[C]) {
+  if (vm || iso) {
+    const T a = vm ? L.ai : L.tb[2 * C * C + 1];
+    const T b = vm ? L.bi : L.tb[2 * C * C + 2];
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < C; ++j) s += v[j] * v[j];
+    T q = a * s;
+    if (C == 6) {
+      const T tr = v[0] + v[1] + v[2];
+      q += b * tr * tr;
+    }
+    return q;
+  }
+  T q = 0;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    T r = 0;
+#pragma unroll
+    for (int k = 0; k < C; ++k) r += L.tb[j * C + k] * v[k];
+    q += v[j] * r;
+  }
+  return q;
+}
+
+template <typename T, int C>
+__device__ __forceinline__ T loc_row(const Loc<T>& L, bool vm, int which, bool iso, int j, const T (&v)[C],
+                                     T ea = T(0), T eb = T(0)) {
+  if (!vm) return phase_row<T, C>(L.tb, which, iso, j, v);
+  T a = L.ai, b = L.bi;
+  if (which == 1) {
+    iso_inverse(a, b, C == 6);
+  } else if (which == 2) {
+    if (C == 6) {
+      T al = T(1) + ea * a;
+      T be = ea * b + eb * (a + T(3) * b);
+      iso_inverse(al, be, true);
+      a = al;
+      b = be;
+    } else {
+      a = T(1) / (T(1) + ea * a);
+      b = T(0);
+    }
+  }
+  T r = a * v[j];
+  if (C == 6 && j < 3) r += b * (v[0] + v[1] + v[2]);
+  return r;
+}
+
+// ----------------------------------------------------------------------------
+// x forward for conjugate gradients with all c components of a voxel row in one
+// thread group: x += alpha p (the previous step, when pending), p = r + beta p,
+// the R2C transforms of every component, and the local quadratic form
+// p . (A - A0)^{-1} p (one FP64 partial per workgroup).  With the spectral form
+// of the z pass this gives p . Lp before the inverse passes run.
+// ----------------------------------------------------------------------------
+template <typename T>
+struct XfwdcArgs {
+  Geo g;
+  const T* r;
+  T* p;
+  T* x;
+  cpx<T>* smain;
+  cpx<T>* snyq;
+  const cpx<T>* twx;
+  const LoadState* st;
+  int nphase, iso;
+  const T* ptab;
+  const uint8_t* phase;
+  const T* vcoef;
+  double* partials;
+  int pstride;
+};
+
+template <typename T, int MX, int P, int C>
+__global__ __launch_bounds__(256) void k_xfwdc(const XfwdcArgs<T> a) {
+  constexpr int TR = MX / P;
+  constexpr int RPW = 256 / TR;
+  constexpr int TABW = 2 * C * C + 5;   // phase table row, see phase_row
+  __shared__ cpx<T> lds[RPW * MX];
+  __shared__ cpx<T> twl[2 * MX];
+  __shared__ T tab[kMaxPhases * TABW];
+  __shared__ double red[4];
+  const Geo& g = a.g;
+  const int l = blockIdx.y;
+  if (!a.st[l].active) return;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < a.nphase * TABW; i += 256) tab[i] = a.ptab[i];
+  for (int i = tid; i < 2 * MX; i += 256) twl[i] = a.twx[i];
+  const int slot = tid / TR, t = tid % TR;
+  const long long vrows = (long long)g.nz * g.ny;
+  const long long vr = (long long)blockIdx.x * RPW + slot;
+  const bool valid = vr < vrows;
+  const long long vrc = valid ? vr : 0;
+  const long long fo = (long long)l * field_elems(g);
+  const bool first = a.st[l].first != 0;
+  const bool pend = a.st[l].pending != 0;
+  const T beta = static_cast<T>(a.st[l].beta);
+  const T alpha = static_cast<T>(a.st[l].alpha);
+  cpx<T> v[C][P];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const long long roff = fo + (long long)j * g.nvox + vrc * (2 * MX);
+    const cpx<T>* r2 = reinterpret_cast<const cpx<T>*>(a.r + roff);
+    cpx<T>* p2 = reinterpret_cast<cpx<T>*>(a.p + roff);
+    cpx<T>* x2 = reinterpret_cast<cpx<T>*>(a.x + roff);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int n = t + TR * i;
+      cpx<T> pv{0, 0};
+      if (valid) {
+        const cpx<T> rv = r2[n];
+        if (first) {
+          pv = rv;
+        } else {
+          const cpx<T> po = p2[n];
+          if (pend) {
+            const cpx<T> xo = x2[n];
+            x2[n] = cpx<T>{xo.x + alpha * po.x, xo.y + alpha * po.y};
+          }
+          pv = cpx<T>{rv.x + beta * po.x, rv.y + beta * po.y};
+        }
+        p2[n] = pv;
+      }
+      v[j][i] = pv;
+    }
+    // one component's rows at a time: bounds the registers the loads occupy
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __syncthreads();   // material table and twiddles staged
+  // local quadratic form on the voxel pairs this thread holds
+  double part = 0.0;
+  const bool iso = a.iso != 0;
+  const bool vm = a.vcoef != nullptr;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int n = t + TR * i;
+    const long long vox = vrc * (2 * MX) + 2 * n;
+    Loc<T> L0, L1;
+    if (vm) {
+      const cpx<T> ai = *reinterpret_cast<const cpx<T>*>(a.vcoef + vox);
+      const cpx<T> bi = *reinterpret_cast<const cpx<T>*>(a.vcoef + g.nvox + vox);
+      L0 = Loc<T>{nullptr, ai.x != T(0) ? T(1) : T(0), ai.x, bi.x};
+      L1 = Loc<T>{nullptr, ai.y != T(0) ? T(1) : T(0), ai.y, bi.y};
+    } else {
+      const uint16_t ph2 = *reinterpret_cast<const uint16_t*>(a.phase + vox);
+      const T* tb0 = tab + (ph2 & 0xff) * TABW;
+      const T* tb1 = tab + (ph2 >> 8) * TABW;
+      L0 = Loc<T>{tb0, tb0[2 * C * C], T(0), T(0)};
+      L1 = Loc<T>{tb1, tb1[2 * C * C], T(0), T(0)};
+    }
+    T p0[C], p1[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      p0[j] = v[j][i].x;
+      p1[j] = v[j][i].y;
+    }
+    part += (double)(L0.in * loc_quad<T, C>(L0, vm, iso, p0)) + (double)(L1.in * loc_quad<T, C>(L1, vm, iso, p1));
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (!valid) part = 0.0;
+  // R2C of every component: half-length transforms, then the unpacking
+  cpx<T>* lrow = lds + slot * MX;
+  fft_pencil_multi<MX, P, -1, T, C>(v, t, lrow, 1, twl, 2);
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < P; ++i) lrow[t + TR * i] = v[j][i];
+    __syncthreads();
+    const long long row = (long long)j * vrows + vrc;
+    const long long so = (long long)l * main_cpx(g) + row * MX;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int k = t + TR * i;
+      const cpx<T> z = v[j][i];
+      if (k == 0) {
+        if (valid) {
+          a.smain[so] = cpx<T>{z.x + z.y, T(0)};
+          a.snyq[(long long)l * nyq_cpx(g) + row] = cpx<T>{z.x - z.y, T(0)};
+        }
+      } else {
+        const cpx<T> zm = lrow[MX - k];
+        const cpx<T> s1 = cpx<T>{z.x + zm.x, z.y - zm.y};   // Z + conj(Zm)
+        const cpx<T> d1 = cpx<T>{z.x - zm.x, z.y + zm.y};   // Z - conj(Zm)
+        const cpx<T> wo = cmul(twl[k], mul_neg_i(d1));
+        if (valid) a.smain[so + k] = cpx<T>{T(0.5) * (s1.x + wo.x), T(0.5) * (s1.y + wo.y)};
+      }
+    }
+  }
+  const double sum = block_sum<256>(part, red);
+  if (tid == 0) a.partials[(long long)l * a.pstride + blockIdx.x] = sum;
+}
+
 // ----------------------------------------------------------------------------
 // y pass: strided pencils of the main spectrum, contiguous rows of the Nyquist plane
 // ----------------------------------------------------------------------------
@@ -233,14 +473,22 @@ __global__ __launch_bounds__(TX*(NY / P)) void k_y(const Geo g, cpx<T>* __restri
 // ----------------------------------------------------------------------------
 // z pass fused with the Green operator: forward z FFT, Gamma_hat, inverse z FFT
 // ----------------------------------------------------------------------------
+// With qpart, the pass also sums the spectral quadratic form
+// (1/V) sum_k w_k Re(conj(tau_hat_k) . Gamma_hat_k tau_hat_k) = tau . Gamma tau
+// (Parseval), w_k = 1 on the kx = 0 and kx = nx/2 planes and 2 elsewhere
+// (the half spectrum of a real field), one FP64 partial per workgroup at
+// qpart[load * pstride + blockIdx.x].
 template <typename T, int NZ, int P, int TX, int C>
 __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenParams gp, const GreenTabs<T> tb,
                                                    const int zmode, cpx<T>* __restrict__ smain,
                                                    cpx<T>* __restrict__ snyq, const cpx<T>* __restrict__ twz,
-                                                   const LoadState* __restrict__ st, const int main_tiles) {
+                                                   const LoadState* __restrict__ st, const int main_tiles,
+                                                   double* __restrict__ qpart, const int pstride) {
   constexpr int TZ = NZ / P;
+  constexpr int NT = TX * TZ;
   __shared__ cpx<T> lds[TX * NZ];
   __shared__ cpx<T> twl[NZ];
+  __shared__ double red[(NT + 63) / 64];
   const int l = blockIdx.y;
   if (st != nullptr && !st[l].active) return;
   const int tid = threadIdx.x;
@@ -279,6 +527,7 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
   __syncthreads();
   fft_pencil_multi<NZ, P, -1, T, C>(v, t, lp, TX, twl, 1);
   if (zmode == Z_GAMMA) {
+    double quad = 0.0;
     if (valid) {
 #pragma unroll
       for (int i = 0; i < P; ++i) {
@@ -290,9 +539,20 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
 #pragma unroll
         for (int j = 0; j < C; ++j) w[j] = v[j][i];
         green_apply<T, C>(gp, tb, k, tidx, w);
+        if (qpart != nullptr) {
+          double d = 0.0;
+#pragma unroll
+          for (int j = 0; j < C; ++j) d += (double)v[j][i].x * w[j].x + (double)v[j][i].y * w[j].y;
+          quad += d;
+        }
 #pragma unroll
         for (int j = 0; j < C; ++j) v[j][i] = w[j];
       }
+    }
+    if (qpart != nullptr) {
+      const double wk = (kx == 0 || kx == g.mx) ? 1.0 : 2.0;
+      const double s = block_sum<NT>(quad * wk / (double)g.nvox, red);
+      if (tid == 0) qpart[(long long)l * pstride + blockIdx.x] = s;
     }
     fft_pencil_multi<NZ, P, 1, T, C>(v, t, lp, TX, twl, 1);
   }
@@ -403,7 +663,8 @@ struct XinvArgs {
   const cpx<T>* snyq;
   const cpx<T>* twx;
   const T* tau;           // field the spectrum was taken of (p, tau, x)
-  T* out;                 // real output (q, new tau, strain); may alias smain
+  T* out;                 // real output (q, new tau, strain, updated r); may alias smain or rin
+  const T* rin;           // residual updated in place by XI_CGR
   float* rout;            // FP32 residual (refinement)
   const T* ptab;          // [nphase][2 c c + 5], see phase_row
   const uint8_t* phase;
@@ -415,73 +676,6 @@ struct XinvArgs {
   T scale;                // 1/N^d times the factor of the half-length route
   T em2[9];               // 2 A0: c x c (scalar), or (4 mu0, 2 lambda0) of the isotropic elastic A0
 };
-
-// Row j of a per-phase c x c matrix applied to v.  Table row layout:
-// [(A-A0)^{-1} (c*c) | (A-A0) (c*c) | in-I0 flag | a_inv b_inv a_dir b_dir]
-// where, when every phase is "isotropic", each matrix is a Id + b m m^T with
-// m the indicator of the three normal Mandel components (b = 0 for scalar
-// problems), and the short form is used.
-template <typename T, int C>
-__device__ __forceinline__ T phase_row(const T* tb, int which, bool iso, int j, const T (&v)[C]) {
-  if (iso) {
-    const T a = tb[2 * C * C + 1 + 2 * which], b = tb[2 * C * C + 2 + 2 * which];
-    T r = a * v[j];
-    if (C == 6 && j < 3) r += b * (v[0] + v[1] + v[2]);
-    return r;
-  }
-  const T* M = tb + which * C * C + j * C;
-  T r = 0;
-#pragma unroll
-  for (int m = 0; m < C; ++m) r += M[m] * v[m];
-  return r;
-}
-
-// Local operator of one voxel: a row of the phase table, or (per-voxel mode)
-// the short form a_inv Id + b_inv m m^T of (A_beta - A0)^{-1} with its
-// inverse a_dir = 1/a_inv, b_dir = -b_inv / (a_inv (a_inv + 3 b_inv)).
-// a_inv = 0 marks a voxel outside I0.
-template <typename T>
-struct Loc {
-  const T* tb;
-  T in, ai, bi;
-};
-
-// which = 0: (A - A0)^{-1}; 1: the table's second matrix, i.e. (A - A0) for
-// the basic scheme or (A - A0)(A + A0)^{-1} for Eyre--Milton; per-voxel mode
-// forms the first (which 1) or the second (which 2, from 2 A0 = (ea, eb)) in place.
-// (A - A0)(A + A0)^{-1} = (Id + 2 A0 (A - A0)^{-1})^{-1}, with
-// 2 A0 (a_inv Id + b_inv m m^T) = 4 mu0 a_inv Id + (4 mu0 b_inv + 2 lambda0 (a_inv + 3 b_inv)) m m^T.
-template <typename T>
-__device__ __forceinline__ void iso_inverse(T& a, T& b, bool six) {
-  const bool z = a == T(0);
-  const T ad = z ? T(0) : T(1) / a;
-  b = (six && !z) ? -b / (a * (a + T(3) * b)) : T(0);
-  a = ad;
-}
-
-template <typename T, int C>
-__device__ __forceinline__ T loc_row(const Loc<T>& L, bool vm, int which, bool iso, int j, const T (&v)[C],
-                                     T ea = T(0), T eb = T(0)) {
-  if (!vm) return phase_row<T, C>(L.tb, which, iso, j, v);
-  T a = L.ai, b = L.bi;
-  if (which == 1) {
-    iso_inverse(a, b, C == 6);
-  } else if (which == 2) {
-    if (C == 6) {
-      T al = T(1) + ea * a;
-      T be = ea * b + eb * (a + T(3) * b);
-      iso_inverse(al, be, true);
-      a = al;
-      b = be;
-    } else {
-      a = T(1) / (T(1) + ea * a);
-      b = T(0);
-    }
-  }
-  T r = a * v[j];
-  if (C == 6 && j < 3) r += b * (v[0] + v[1] + v[2]);
-  return r;
-}
 
 template <typename T, int MX, int P, int C>
 __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
@@ -589,6 +783,17 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
                         in1 * (loc_row<T, C>(L1, vm, 0, iso, j, t1) + g1[j])};
 #pragma unroll
       for (int j = 0; j < C; ++j) part += (double)t0[j] * res[j].x + (double)t1[j] * res[j].y;
+    } else if (a.mode == XI_CGR) {
+      // r -= alpha L p in place (alpha known from the quadratic forms), and ||r||^2
+      const T al = static_cast<T>(a.st[l].alpha);
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const cpx<T> rv = *reinterpret_cast<const cpx<T>*>(a.rin + fo + (long long)j * g.nvox + vox);
+        const T q0 = in0 * (loc_row<T, C>(L0, vm, 0, iso, j, t0) + g0[j]);
+        const T q1 = in1 * (loc_row<T, C>(L1, vm, 0, iso, j, t1) + g1[j]);
+        res[j] = cpx<T>{rv.x - al * q0, rv.y - al * q1};
+        part += (double)res[j].x * res[j].x + (double)res[j].y * res[j].y;
+      }
     } else if (a.mode == XI_BASIC) {
       // new tau = (A - A0)(p - Gamma tau); residual (p - Gamma tau) - (A - A0)^{-1} tau
       T u0[C], u1[C];

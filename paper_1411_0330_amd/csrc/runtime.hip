@@ -150,6 +150,7 @@ struct lsh_ctx {
   int series = 8;
   int iso = 0;  // every phase matrix has the short form (see phase_row)
   bool mat_voxel = false;  // material given per voxel (lsh_set_voxel_moduli) instead of per phase
+  bool cg_fused = true;    // CG with p.Lp from the x and z passes and r updated in the x-inverse pass
   bool tab_em = false;     // second table matrix: (A-A0)(A+A0)^{-1} (Eyre--Milton) instead of A-A0
   char* sbuf = nullptr;    // bound solver buffer (MINRES fields)
   size_t sbuf_size = 0;
@@ -324,7 +325,8 @@ void compute_layout(lsh_ctx* ctx) {
   ctx->off.st_in = take(sizeof(LoadState) * L);
   ctx->off.mstate = take(sizeof(MinresState) * L);
   // partial sums: the largest grid of any reducing kernel, per group
-  long long pmax = xinv_blocks(ctx->geo, 2);
+  // (the fused CG step writes the x pass's and the z pass's partials side by side)
+  long long pmax = xinv_blocks(ctx->geo, 2) + zg_blocks_max<float>(ctx->geo);
   pmax = std::max(pmax, (F + 1023) / 1024 + 1);
   ctx->pstride = pmax;
   ctx->off.partials = take(sizeof(double) * L * c * pmax);
@@ -598,6 +600,8 @@ template <typename T> int tv(const lsh_ctx* ctx, int pass) { return ctx->tune[si
 
 // Variants from LSH_TUNE, e.g. "zg32=3,y32=1,xinv64=2" (pass name + 32/64 = variant).
 void tune_from_env(lsh_ctx* ctx) {
+  const char* f = std::getenv("LSH_CG_FUSED");
+  if (f && f[0] == '0') ctx->cg_fused = false;
   const char* e = std::getenv("LSH_TUNE");
   if (!e) return;
   const char* names[NPASS] = {"xfwd", "y", "zg", "xinv"};
@@ -663,7 +667,7 @@ lsh_status forward_part(lsh_ctx* ctx, int l0, int nload, int xmode, const T* src
 
 template <typename T>
 lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T* out, float* rout,
-                     const LoadState* st, double* partials, int* nparts) {
+                     const LoadState* st, double* partials, int* nparts, const T* rin = nullptr) {
   const Geo& g = ctx->geo;
   XinvArgs<T> a{};
   a.g = g;
@@ -675,6 +679,7 @@ lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T*
   a.twx = Sel<T>::tw(ctx, 0);
   a.tau = tau;
   a.out = out;
+  a.rin = rin;
   a.rout = rout;
   a.ptab = Sel<T>::ptab(ctx);
   a.phase = ctx->ptr<uint8_t>(ctx->off.phase);
@@ -696,6 +701,7 @@ lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T*
   // spectrum + material (phase ids, or two coefficients per voxel)
   double bytes = cvs + 2.0 * sizeof(T) * (double)nyq_cpx(g) + (ctx->mat_voxel ? 2.0 * sizeof(T) : 1.0) * g.nvox;
   if (mode != XI_STRAIN) bytes += cvs;                                          // the field transformed
+  if (mode == XI_CGR) bytes += cvs;                                             // residual read
   if (mode == XI_IRRES) bytes += 4.0 * ctx->F;                                  // FP32 residual out
   else if (mode != XI_RESNORM) bytes += cvs;                                    // real output
   Scope sc(ctx, kcls<T>(K_XINV), nl * bytes);
@@ -703,6 +709,53 @@ lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T*
   STCHK(check_launch(ctx, nb, "x inverse"));
   if (nparts) *nparts = nb;
   return LSH_OK;
+}
+
+lsh_status scal(lsh_ctx* ctx, int mode, int ngroups, int nparts, LoadState* st, double tol);
+
+// One CG step with p.Lp known before the inverse passes: the x pass forms p
+// and sums p.(A - A0)^{-1} p, the z pass sums p.Gamma p over the spectrum
+// (Parseval), alpha follows, and the x-inverse pass updates r in place with
+// ||r||^2; q = Lp is never stored.
+template <typename T>
+lsh_status cg_fused_step(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, bool scalars = true) {
+  const Geo& g = ctx->geo;
+  cpx<T>* sm = Sel<T>::sm(ctx);
+  cpx<T>* sn = Sel<T>::sn(ctx);
+  double* parts = ctx->ptr<double>(ctx->off.partials);
+  const double nl = std::min(ctx->nact, nload);
+  const double cvs = (double)ctx->F * sizeof(T);
+  const double spec = cvs + 2.0 * sizeof(T) * (double)nyq_cpx(g);
+  const double mat = (ctx->mat_voxel ? 2.0 * sizeof(T) : 1.0) * g.nvox;
+  XfwdcArgs<T> xa{g, r, p, x, sm, sn, Sel<T>::tw(ctx, 0), st, ctx->nphase, ctx->iso, Sel<T>::ptab(ctx),
+                  ctx->ptr<uint8_t>(ctx->off.phase), Sel<T>::vc(ctx), parts, (int)ctx->pstride};
+  int nbx = 0, nbz = 0, nbi = 0;
+  {
+    Scope sc(ctx, kcls<T>(K_XFWD), nl * ((ctx->xf_first ? 2.0 : 5.0) * cvs + spec + mat));
+    nbx = launch_xfwdc<T>(ctx->stream, xa, nload);
+    STCHK(check_launch(ctx, nbx, "x forward (CG)"));
+  }
+  {
+    Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
+    STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, -1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y)),
+                       "y forward"));
+  }
+  {
+    Scope sc(ctx, kcls<T>(K_ZG), nl * 2.0 * spec);
+    GreenTabs<T> tb{Sel<T>::wt(ctx), ctx->wstride, {Sel<T>::tw(ctx, 0), Sel<T>::tw(ctx, 1), Sel<T>::tw(ctx, 2)},
+                    Sel<T>::gtab(ctx)};
+    nbz = launch_zg<T>(ctx->stream, g, ctx->gp, tb, Z_GAMMA, sm, sn, Sel<T>::tw(ctx, 2), st, nload,
+                       tv<T>(ctx, PASS_ZG), parts + nbx, (int)ctx->pstride);
+    STCHK(check_launch(ctx, nbz, "z/Green"));
+  }
+  if (scalars) STCHK(scal(ctx, SC_ALPHA, nload, nbx + nbz, st, 0.0));
+  {
+    Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
+    STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, 1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y)),
+                       "y inverse"));
+  }
+  STCHK(inverse_x<T>(ctx, 0, nload, XI_CGR, p, r, nullptr, st, parts, &nbi, r));
+  return scalars ? scal(ctx, SC_BETA, nload, nbi, st, 0.0) : LSH_OK;
 }
 
 lsh_status scal(lsh_ctx* ctx, int mode, int ngroups, int nparts, LoadState* st, double tol) {
@@ -813,13 +866,14 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
   for (auto& s : hst) any |= s.active != 0, ctx->nact += s.active != 0;
   if (!any) return LSH_OK;
   auto iteration = [&]() -> lsh_status {
+    if (ctx->cg_fused) return cg_fused_step<T>(ctx, nload, x, r, p, st);
     STCHK(forward_part<T>(ctx, 0, nload, XF_CG, r, p, x, nullptr, st, true));
     int np = 0;
     STCHK(inverse_x<T>(ctx, 0, nload, XI_CG, p, q, nullptr, st, ctx->ptr<double>(ctx->off.partials), &np));
     STCHK(scal(ctx, SC_ALPHA, nload, np, st, 0.0));
     return cg_update<T>(ctx, nload, r, q, st);
   };
-  const long long key = (long long)nload * 4 + (st_off == ctx->off.st_in ? 1 : 0);
+  const long long key = (long long)nload * 4 + (st_off == ctx->off.st_in ? 1 : 0) + (ctx->cg_fused ? 2 : 0);
   for (int it = 0; it < maxit; ++it) {
     ctx->xf_first = it == 0;
     STCHK(run_iteration(ctx, sizeof(T) == 8 ? 0 : 1, key, iteration));
@@ -1001,6 +1055,12 @@ int pass_class(int pass, bool fp64) {
 // FP64 residual to FP32) for the FP64 passes of a mixed context.
 lsh_status timing_iteration(lsh_ctx* ctx, int nload, bool fp64) {
   double* parts = ctx->ptr<double>(ctx->off.partials);
+  if (!fp64 && ctx->cg_fused)
+    return cg_fused_step<float>(ctx, nload, ctx->ptr<float>(ctx->off.d32), ctx->ptr<float>(ctx->off.r32),
+                                ctx->ptr<float>(ctx->off.p32), ctx->ptr<LoadState>(ctx->off.st_in), false);
+  if (fp64 && ctx->cg_fused && ctx->precision != LSH_MIXED)
+    return cg_fused_step<double>(ctx, nload, ctx->ptr<double>(ctx->off.x64), ctx->ptr<double>(ctx->off.r64),
+                                 ctx->ptr<double>(ctx->off.p64), ctx->ptr<LoadState>(ctx->off.st_out), false);
   if (!fp64) {
     LoadState* st = ctx->ptr<LoadState>(ctx->off.st_in);
     float* q = reinterpret_cast<float*>(Sel<float>::sm(ctx));
@@ -1801,6 +1861,8 @@ lsh_status lsh_autotune(lsh_ctx* ctx, int nload, const char* cache_path, int32_t
     const bool fp64 = prec == 1;
     for (int pass = 0; pass < NPASS; ++pass) {
       if (!pass_has_variants(ctx, pass)) continue;
+      // the fused CG x pass has one shape (CG fields: FP32 of a mixed context, FP64 of an FP64 one)
+      if (pass == PASS_XFWD && ctx->cg_fused && (!fp64 || ctx->precision != LSH_MIXED)) continue;
       const int cls = pass_class(pass, fp64);
       double best_t = 1e300;
       int best_v = ctx->tune[prec][pass];
