@@ -66,7 +66,8 @@ struct XfwdArgs {
 // Kernel-shape variants of each pass (0 = the default shape).  For the axis
 // lengths 128 and 256 every pass is compiled in kVariants shapes:
 //   strided passes (y, zg): 1 = half the pencils per workgroup,
-//                           2 = half the points per thread, 3 = both;
+//                           2 = half the points per thread,
+//                           3 = twice the pencils per workgroup;
 //   row passes (xfwd, xinv): 1 = half the points per thread, 2 = twice,
 //                            3 = a quarter.
 // Shapes that break a limit (threads, LDS, points) fall back to the default.
@@ -105,11 +106,15 @@ template <typename T> int launch_xinv(hipStream_t s, const XinvArgs<T>& a, int n
 // strided-pass shape of a variant: (pencils per workgroup, points per thread)
 template <typename T> constexpr int sv_tx(int n, int p0, int v) {
   const int tx0 = tx_strided<T>(n, p0);
-  return (v == 1 || v == 3) ? (tx0 / 2 >= 2 ? tx0 / 2 : tx0) : tx0;
+  return v == 1 ? (tx0 / 2 >= 2 ? tx0 / 2 : tx0) : (v == 3 ? 2 * tx0 : tx0);
 }
-constexpr int sv_p(int p0, int v) { return (v == 2 || v == 3) ? (p0 / 2 >= 2 ? p0 / 2 : p0) : p0; }
+constexpr int sv_p(int p0, int v) { return v == 2 ? (p0 / 2 >= 2 ? p0 / 2 : p0) : p0; }
+// a shape is compiled when it fits 1024 threads and the 160 KiB of LDS a gfx950
+// workgroup may hold (exchange buffer, twiddles and the reduction slots)
+constexpr long kLdsPerWorkgroup = 160 * 1024;
 template <typename T> constexpr bool sv_ok(int n, int tx, int p) {
-  return p >= 1 && p <= n && tx >= 1 && tx * (n / p) <= 1024 && (long)tx * n * 2 * (int)sizeof(T) <= 65536;
+  return p >= 1 && p <= n && tx >= 1 && tx * (n / p) <= 1024 &&
+         (long)(tx + 1) * n * 2 * (int)sizeof(T) + 128 <= kLdsPerWorkgroup;
 }
 // row-pass points per thread of a variant
 constexpr int rv_p(int mx, int p0, int v) {

@@ -547,6 +547,8 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
         }
 #pragma unroll
         for (int j = 0; j < C; ++j) v[j][i] = w[j];
+        // one wave-vector's operator at a time: bounds the registers of the alias sums
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     if (qpart != nullptr) {
