@@ -387,15 +387,16 @@ def main():
         torch.cuda.empty_cache()
     out["C_star_mandel"] = [[round(x, 8) for x in row] for row in C_mixed.tolist()]
 
-    # ---------------- a launch-bound grid: 2D disk 64^2, graphs vs eager ----------------
+    # ---------------- a launch-bound grid: 2D disk 64^2, multi-kernel (eager, graphs) vs persistent ----------------
     wd = I.disk_workload(64, "truncated")
     small = {}
-    for graphs in (() if args.no_small else (False, True)):
+    for mode in (() if args.no_small else ("eager", "graphs", "persistent")):
         ctxs = lsh.Context(wd.phase.shape, "scalar", "fp64", max_loads=2, device=dev)
         ctxs.set_reference(wd.A0)
         ctxs.set_phases(wd.phase, wd.moduli)
         ctxs.set_green("truncated")
-        ctxs.set_graphs(graphs)
+        ctxs.set_graphs(mode == "graphs")
+        ctxs.set_persistent(mode == "persistent")
         ctxs.solve(wd.loads, "cg", tol=1e-10)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -405,7 +406,7 @@ def main():
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         its = max(r["iterations"])
-        small["graphs" if graphs else "eager"] = {"ms_per_solve": round(dt * 1e3, 3),
+        small[mode] = {"ms_per_solve": round(dt * 1e3, 3),
                                                    "us_per_iteration": round(dt * 1e6 / its, 2),
                                                    "iterations": its}
         del ctxs

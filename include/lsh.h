@@ -299,6 +299,16 @@ lsh_status lsh_solve_many(int n, lsh_ctx* const* ctxs, int solver, const int32_t
                           int32_t* statuses, int nthreads);
 
 /*
+ * Persistent launch (default on): for small grids (squares of 8..64 voxels in
+ * 2D, cubes of 8..32 in 3D) conjugate gradients run as one kernel launch per
+ * solve, one workgroup per load performing every iteration (the same fused
+ * step, its passes separated by workgroup barriers), which removes the
+ * per-kernel latency that dominates such grids.  0 keeps the multi-kernel
+ * loop.  The environment variable LSH_PERSISTENT=0 sets 0 at creation.
+ */
+lsh_status lsh_set_persistent(lsh_ctx* ctx, int enable);
+
+/*
  * Iteration graphs (default on): the kernels of one solver iteration are
  * captured once into a HIP graph (on a private stream of default priority)
  * and the graph is replayed on the context's stream for every iteration.

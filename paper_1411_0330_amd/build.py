@@ -34,6 +34,8 @@ UNITS = [
     ("k_y.hip", "k_y_f64.o", ["-DLSH_Y_TYPE=double"]),
     ("k_z.hip", "k_z_f32.o", ["-DLSH_Z_TYPE=float"]),
     ("k_z.hip", "k_z_f64.o", ["-DLSH_Z_TYPE=double"]),
+    ("k_tiny.hip", "k_tiny_f32.o", ["-DLSH_TINY_TYPE=float"]),
+    ("k_tiny.hip", "k_tiny_f64.o", ["-DLSH_TINY_TYPE=double"]),
     ("runtime.hip", "runtime.o", []),
 ]
 

@@ -101,6 +101,13 @@ template <typename T> int launch_zg(hipStream_t s, const Geo& g, const GreenPara
 // x forward of conjugate gradients over all components of a voxel row (returns
 // the workgroups per load, i.e. the partials written per load)
 template <typename T> int launch_xfwdc(hipStream_t s, const XfwdcArgs<T>& a, int nload);
+// persistent CG for small grids (returns -1 for grids without an instance)
+template <typename T> struct TinyArgs;
+template <typename T> int launch_tiny_cg(hipStream_t s, const TinyArgs<T>& a, int nload);
+inline bool tiny_grid(const Geo& g) {
+  if (g.nz == 1) return g.c == 2 && g.nx == g.ny && (g.nx == 8 || g.nx == 16 || g.nx == 32 || g.nx == 64);
+  return (g.c == 3 || g.c == 6) && g.nx == g.ny && g.ny == g.nz && (g.nx == 8 || g.nx == 16 || g.nx == 32);
+}
 template <typename T> int launch_xinv(hipStream_t s, const XinvArgs<T>& a, int nload, int variant = 0);
 
 // strided-pass shape of a variant: (pencils per workgroup, points per thread)

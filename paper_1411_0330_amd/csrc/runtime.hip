@@ -19,6 +19,7 @@
 
 #include "dispatch.hpp"
 #include "solver_kernels.hpp"
+#include "tiny.hpp"
 #include "lsh.h"
 
 using namespace lsh;
@@ -116,10 +117,11 @@ struct KTimer {
 // are split by element type (FP32 / FP64).
 const char* kClassNames[] = {"xfwd_f32",   "xfwd_f64",   "y_f32",   "y_f64",   "zgamma_f32",
                              "zgamma_f64", "xinv_f32",   "xinv_f64", "cg_update_f32", "cg_update_f64",
-                             "scalars",    "init",       "mean",     "copy",          "gradient"};
+                             "scalars",    "init",       "mean",     "copy",          "gradient",
+                             "persistent_cg"};
 enum KClass {
   K_XFWD = 0, K_Y = 2, K_ZG = 4, K_XINV = 6, K_CGUPD = 8,  // + 1 for FP64
-  K_SCAL = 10, K_INIT, K_MEAN, K_COPY, K_GRAD, K_NCLASS
+  K_SCAL = 10, K_INIT, K_MEAN, K_COPY, K_GRAD, K_TINY, K_NCLASS
 };
 template <typename T> constexpr int kcls(int base) { return base + (sizeof(T) == 8 ? 1 : 0); }
 
@@ -151,6 +153,7 @@ struct lsh_ctx {
   int iso = 0;  // every phase matrix has the short form (see phase_row)
   bool mat_voxel = false;  // material given per voxel (lsh_set_voxel_moduli) instead of per phase
   bool cg_fused = true;    // CG with p.Lp from the x and z passes and r updated in the x-inverse pass
+  bool persistent = true;  // small grids: the whole CG loop of a load in one workgroup
   bool tab_em = false;     // second table matrix: (A-A0)(A+A0)^{-1} (Eyre--Milton) instead of A-A0
   char* sbuf = nullptr;    // bound solver buffer (MINRES fields)
   size_t sbuf_size = 0;
@@ -602,6 +605,8 @@ template <typename T> int tv(const lsh_ctx* ctx, int pass) { return ctx->tune[si
 void tune_from_env(lsh_ctx* ctx) {
   const char* f = std::getenv("LSH_CG_FUSED");
   if (f && f[0] == '0') ctx->cg_fused = false;
+  const char* pe = std::getenv("LSH_PERSISTENT");
+  if (pe && pe[0] == '0') ctx->persistent = false;
   const char* e = std::getenv("LSH_TUNE");
   if (!e) return;
   const char* names[NPASS] = {"xfwd", "y", "zg", "xinv"};
@@ -865,6 +870,32 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
   ctx->nact = 0;
   for (auto& s : hst) any |= s.active != 0, ctx->nact += s.active != 0;
   if (!any) return LSH_OK;
+  if (ctx->persistent && ctx->cg_fused && tiny_grid(ctx->geo)) {
+    // the whole loop in one launch: one workgroup per load
+    TinyArgs<T> ta{};
+    ta.g = ctx->geo;
+    ta.gp = ctx->gp;
+    ta.tb = GreenTabs<T>{Sel<T>::wt(ctx), ctx->wstride, {Sel<T>::tw(ctx, 0), Sel<T>::tw(ctx, 1), Sel<T>::tw(ctx, 2)},
+                         Sel<T>::gtab(ctx)};
+    ta.x = x;
+    ta.r = r;
+    ta.p = p;
+    ta.sm = Sel<T>::sm(ctx);
+    ta.sn = Sel<T>::sn(ctx);
+    for (int a = 0; a < 3; ++a) ta.tw[a] = Sel<T>::tw(ctx, a);
+    ta.nphase = ctx->nphase;
+    ta.iso = ctx->iso;
+    ta.ptab = Sel<T>::ptab(ctx);
+    ta.phase = ctx->ptr<uint8_t>(ctx->off.phase);
+    ta.vcoef = Sel<T>::vc(ctx);
+    ta.st = st;
+    ta.maxit = maxit;
+    {
+      Scope sc(ctx, K_TINY);
+      STCHK(check_launch(ctx, launch_tiny_cg<T>(ctx->stream, ta, nload), "persistent CG"));
+    }
+    return LSH_OK;
+  }
   auto iteration = [&]() -> lsh_status {
     if (ctx->cg_fused) return cg_fused_step<T>(ctx, nload, x, r, p, st);
     STCHK(forward_part<T>(ctx, 0, nload, XF_CG, r, p, x, nullptr, st, true));
@@ -1944,6 +1975,12 @@ lsh_status lsh_solve_many(int n, lsh_ctx* const* ctxs, int solver, const int32_t
     if (st[i] == LSH_MAXIT && overall == LSH_OK) overall = LSH_MAXIT;
   }
   return overall;
+}
+
+lsh_status lsh_set_persistent(lsh_ctx* ctx, int enable) {
+  if (!ctx) return LSH_EINVAL;
+  ctx->persistent = enable != 0;
+  return LSH_OK;
 }
 
 lsh_status lsh_set_graphs(lsh_ctx* ctx, int enable) {

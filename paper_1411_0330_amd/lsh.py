@@ -77,6 +77,7 @@ _SIGS = {
                                  C.c_int]),
     "lsh_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "lsh_set_graphs": (C.c_int, [C.c_void_p, C.c_int]),
+    "lsh_set_persistent": (C.c_int, [C.c_void_p, C.c_int]),
     "lsh_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
                                    C.POINTER(C.c_int64), C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_int)]),
     "lsh_last_error": (C.c_char_p, [C.c_void_p]),
@@ -357,6 +358,9 @@ class Context:
         path = None if cache is None else os.fspath(cache).encode()
         self._check(self.lib.lsh_autotune(self.h, int(nload or self.max_loads), path, v, C.byref(hit)))
         return {"fp32": list(v[:4]), "fp64": list(v[4:])}, bool(hit.value)
+
+    def set_persistent(self, enable=True):
+        return self._check(self.lib.lsh_set_persistent(self.h, int(bool(enable))))
 
     def set_graphs(self, enable=True):
         self._check(self.lib.lsh_set_graphs(self.h, 1 if enable else 0))

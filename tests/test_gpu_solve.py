@@ -182,6 +182,7 @@ def test_graph_replay_matches_eager(lsh, precision):
     w = I.boolean_workload(32, seed=3)
     def run(graphs):
         ctx = context(lsh, w.phase, w.moduli, w.A0, "scalar", "filtered", precision=precision, max_loads=3)
+        ctx.set_persistent(False)      # the multi-kernel loop is what graphs capture
         ctx.set_graphs(graphs)
         outs = []
         for rep in range(3):
@@ -198,6 +199,7 @@ def test_graph_replay_matches_eager(lsh, precision):
     res = []
     for graphs in (False, True):
         ctx = context(lsh, w2.phase, w2.moduli, w2.A0, "scalar", "truncated", precision=precision, max_loads=2)
+        ctx.set_persistent(False)
         ctx.set_graphs(graphs)
         ctx.solve(w2.loads, "basic", tol=1e-10, maxit=3000)
         res.append(ctx.effective())
