@@ -223,3 +223,34 @@ def test_fd_and_consistent_solves_match_oracle(lsh):
             vals.append(A[0, 0])
         if variant == "fd":   # Table 1: independent of A0
             assert abs(vals[0] - vals[1]) < 1e-10
+
+
+def test_full_size_elastic_rsa_256_mixed_against_fp64_and_bounds(lsh):
+    # the benchmark's workload and launch configuration: 256^3, six loads, filtered, mixed CG to 1e-6
+    w = I.elastic_rsa_workload(256, tol=1e-6)
+    import torch
+    phase_dev = torch.from_numpy(w.phase).to("cuda:0")
+    res = {}
+    for precision, tol in (("mixed", 1e-6), ("fp64", 1e-9)):
+        ctx = lsh.Context(w.phase.shape, "elastic", precision, max_loads=6)
+        ctx.set_reference(w.A0)
+        ctx.set_phases(phase_dev, w.moduli)
+        ctx.set_green("filtered")
+        rep = ctx.solve(w.loads, "cg", tol=tol, maxit=3000)
+        assert rep["status"] == lsh.OK and max(rep["rel_residual"]) <= tol
+        res[precision] = ctx.effective().T.copy()
+        del ctx
+        torch.cuda.empty_cache()
+    C, C64 = res["mixed"], res["fp64"]
+    assert rel_max_err(C, C64) <= 1e-5
+    assert np.abs(C64 - C64.T).max() <= 1e-7 * np.abs(C64).max()
+    # Voigt and Reuss bounds of the discrete problem (A0 softer than both phases)
+    f = float(w.phase.mean())
+    Cv = (1 - f) * w.moduli[0] + f * w.moduli[1]
+    Cr = np.linalg.inv((1 - f) * np.linalg.inv(w.moduli[0]) + f * np.linalg.inv(w.moduli[1]))
+    for i in range(6):
+        assert Cr[i, i] * (1 - 1e-9) <= C64[i, i] <= Cv[i, i] * (1 + 1e-9)
+    # Hashin-Shtrikman band for the bulk and shear estimates of the isotropic part
+    K = (C64[:3, :3].sum()) / 9.0
+    mu = (np.trace(C64) - C64[:3, :3].sum() / 3.0) / 10.0
+    assert 1.243 <= K <= 1.767 and 0.650 <= mu <= 1.102, (K, mu)
