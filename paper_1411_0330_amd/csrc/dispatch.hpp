@@ -66,7 +66,7 @@ struct XfwdArgs {
 // Kernel-shape variants of each pass (0 = the default shape).  For the axis
 // lengths 128 and 256 every pass is compiled in kVariants shapes:
 //   strided passes (y, zg): 1 = half the pencils per workgroup,
-//                           2 = half the points per thread,
+//                           2 = half the points per thread (at most 256 threads),
 //                           3 = twice the pencils per workgroup;
 //   row passes (xfwd, xinv): 1 = half the points per thread, 2 = twice,
 //                            3 = a quarter.
@@ -113,6 +113,12 @@ template <typename T> int launch_xinv(hipStream_t s, const XinvArgs<T>& a, int n
 // strided-pass shape of a variant: (pencils per workgroup, points per thread)
 template <typename T> constexpr int sv_tx(int n, int p0, int v) {
   const int tx0 = tx_strided<T>(n, p0);
+  if (v == 2) {
+    // half the points per thread, at most 256 threads per workgroup
+    const int tpp = n / (p0 / 2 >= 2 ? p0 / 2 : p0);
+    const int tx = 256 / tpp;
+    return tx < 1 ? 1 : (tx < tx0 ? tx : tx0);
+  }
   return v == 1 ? (tx0 / 2 >= 2 ? tx0 / 2 : tx0) : (v == 3 ? 2 * tx0 : tx0);
 }
 constexpr int sv_p(int p0, int v) { return v == 2 ? (p0 / 2 >= 2 ? p0 / 2 : p0) : p0; }
