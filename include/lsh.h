@@ -300,7 +300,9 @@ lsh_status lsh_solve_many(int n, lsh_ctx* const* ctxs, int solver, const int32_t
 
 /*
  * Persistent launch (default on): for small grids (squares of 8..64 voxels in
- * 2D, cubes of 8..32 in 3D) conjugate gradients run as one kernel launch per
+ * 2D, cubes of 8 voxels, and cubes of 16 for scalar problems: at most 12288
+ * unknowns per load, where it beats the multi-kernel loop on MI355X)
+ * conjugate gradients run as one kernel launch per
  * solve, one workgroup per load performing every iteration (the same fused
  * step, its passes separated by workgroup barriers), which removes the
  * per-kernel latency that dominates such grids.  0 keeps the multi-kernel

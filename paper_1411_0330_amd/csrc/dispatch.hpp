@@ -104,9 +104,14 @@ template <typename T> int launch_xfwdc(hipStream_t s, const XfwdcArgs<T>& a, int
 // persistent CG for small grids (returns -1 for grids without an instance)
 template <typename T> struct TinyArgs;
 template <typename T> int launch_tiny_cg(hipStream_t s, const TinyArgs<T>& a, int nload);
+// Grids where one workgroup per load beats the multi-kernel loop on MI355X
+// (measured): at most 12288 unknowns per load -- squares 8..64 (2D), cubes of
+// 8 (scalar and elastic) and 16 (scalar).  Larger grids keep every CU busy
+// with the multi-kernel loop instead.
 inline bool tiny_grid(const Geo& g) {
   if (g.nz == 1) return g.c == 2 && g.nx == g.ny && (g.nx == 8 || g.nx == 16 || g.nx == 32 || g.nx == 64);
-  return (g.c == 3 || g.c == 6) && g.nx == g.ny && g.ny == g.nz && (g.nx == 8 || g.nx == 16 || g.nx == 32);
+  if (g.nx != g.ny || g.ny != g.nz) return false;
+  return (g.nx == 8 && (g.c == 3 || g.c == 6)) || (g.nx == 16 && g.c == 3);
 }
 template <typename T> int launch_xinv(hipStream_t s, const XinvArgs<T>& a, int nload, int variant = 0);
 

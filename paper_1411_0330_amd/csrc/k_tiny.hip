@@ -13,7 +13,7 @@ static int tiny_inst(hipStream_t s, const TinyArgs<T>& a, int nload) {
   return nload;
 }
 
-// supported grids: squares 8..64 (2D), cubes 8..32 (3D)
+// grids of tiny_grid(): squares 8..64 (2D), cubes of 8 and (scalar) 16
 template <typename T>
 int launch_tiny_cg(hipStream_t s, const TinyArgs<T>& a, int nload) {
   const Geo& g = a.g;
@@ -26,13 +26,10 @@ int launch_tiny_cg(hipStream_t s, const TinyArgs<T>& a, int nload) {
       default: return -1;
     }
   }
-  if (g.nz > 1 && g.nx == g.ny && g.ny == g.nz && (g.c == 3 || g.c == 6)) {
-    switch (g.nx) {
-      case 8: return g.c == 3 ? tiny_inst<T, 8, 8, 8, 3>(s, a, nload) : tiny_inst<T, 8, 8, 8, 6>(s, a, nload);
-      case 16: return g.c == 3 ? tiny_inst<T, 16, 16, 16, 3>(s, a, nload) : tiny_inst<T, 16, 16, 16, 6>(s, a, nload);
-      case 32: return g.c == 3 ? tiny_inst<T, 32, 32, 32, 3>(s, a, nload) : tiny_inst<T, 32, 32, 32, 6>(s, a, nload);
-      default: return -1;
-    }
+  if (g.nz > 1 && g.nx == g.ny && g.ny == g.nz) {
+    if (g.nx == 8 && g.c == 3) return tiny_inst<T, 8, 8, 8, 3>(s, a, nload);
+    if (g.nx == 8 && g.c == 6) return tiny_inst<T, 8, 8, 8, 6>(s, a, nload);
+    if (g.nx == 16 && g.c == 3) return tiny_inst<T, 16, 16, 16, 3>(s, a, nload);
   }
   return -1;
 }

@@ -2,10 +2,10 @@
 whole loop) for small grids.
 
 * Against the multi-kernel loop on the same context: A* within rounding and
-  iteration counts within one, for every supported grid (squares 8..64,
-  cubes 8..32), scalar and elastic, FP64 and mixed, phase maps and
-  per-voxel moduli, truncated/filtered/consistent operators.
-* Against the oracle (64^2 disk, 16^3 elastic) and the stored disk A*.
+  iteration counts within one, for every persistent grid (squares 8..64,
+  cubes of 8, scalar cubes of 16), scalar and elastic, FP64 and mixed, phase
+  maps and per-voxel moduli, truncated/filtered/consistent operators.
+* Against the oracle (64^2 disk) and the stored disk A*.
 * Loads that converge at different steps, a zero load, maxit, and an
   indefinite system (A0 between the phases).
 """
@@ -39,8 +39,9 @@ def _pair(lsh, ph, moduli, A0, physics, green, precision, loads, tol, maxit=3000
 
 @pytest.mark.parametrize("physics,shape", [("scalar", (8, 8)), ("scalar", (16, 16)), ("scalar", (32, 32)),
                                            ("scalar", (64, 64)), ("scalar", (8, 8, 8)), ("scalar", (16, 16, 16)),
-                                           ("scalar", (32, 32, 32)), ("elastic", (8, 8, 8)),
-                                           ("elastic", (16, 16, 16)), ("elastic", (32, 32, 32))])
+                                           ("elastic", (8, 8, 8)),
+                                           # beyond the persistent grids: the multi-kernel loop runs either way
+                                           ("scalar", (32, 32, 32)), ("elastic", (16, 16, 16))])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_persistent_matches_multi_kernel_loop(lsh, physics, shape, precision):
     ph, moduli, A0 = _op_setup(physics, shape, "filtered", "masked")
@@ -56,7 +57,7 @@ def test_persistent_matches_multi_kernel_loop(lsh, physics, shape, precision):
 
 @pytest.mark.parametrize("green,series", [("truncated", None), ("consistent", 2)])
 def test_persistent_other_operators_and_voxel_moduli(lsh, green, series):
-    ph, moduli, A0 = _op_setup("elastic", (16, 16, 16), green, "")
+    ph, moduli, A0 = _op_setup("elastic", (8, 8, 8), green, "")
     loads = np.eye(6)[[0, 5]]
     (Ap, rp), (Am, rm) = _pair(lsh, ph, moduli, A0, "elastic", green, "fp64", loads, 1e-11, series=series)
     assert rel_max_err(Ap, Am) <= 1e-10
@@ -84,8 +85,8 @@ def test_persistent_disk_against_golden_and_oracle(lsh):
     assert rel_max_err(ctx.effective().T, gold["A_star"]) <= 1e-10
     rep10 = ctx.solve(w.loads, "cg", tol=1e-10)
     assert abs(rep10["iterations"][0] - gold["cg_iterations_tol1e-10"]) <= 1
-    # elastic 16^3 against the oracle
-    ph, _ = I.rsa_spheres(16, 3.0, 6.0, 0.2, 1)
+    # elastic 8^3 against the oracle
+    ph = I.random_phases((8, 8, 8), 2, seed=6)
     mods = np.stack([I.elastic_from_young(1.0, 0.3), I.elastic_from_young(10.0, 0.2)])
     pb = problem(ph, mods, C0, "elastic", "filtered")
     loads = np.eye(6)[[0, 3]]
