@@ -21,7 +21,9 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // the exchange buffer of the row passes stays within 48 KiB, else 2.
 template <typename T> constexpr int p_odd(int n, int q) {
   const int f = odd_part(n);
-  while (q > 2 && 256 * f * q * 2 * (int)sizeof(T) > 48 * 1024) q /= 2;
+  // at most 12 points per thread (radix 5: 10); 20 needs more registers than
+  // the pencil buffers leave and drops occupancy to one or two waves
+  while (q > 2 && (256 * f * q * 2 * (int)sizeof(T) > 48 * 1024 || f * q > 12)) q /= 2;
   return f * cmin(q, pow2_part(n));
 }
 template <typename T> constexpr int p_xfwd(int mx) { return odd_part(mx) > 1 ? p_odd<T>(mx, 4) : cmin(8, mx); }

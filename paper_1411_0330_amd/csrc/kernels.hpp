@@ -744,8 +744,10 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
   T pl[C];
 #pragma unroll
   for (int j = 0; j < C; ++j) pl[j] = static_cast<T>(a.loads[l * C + j]);
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
+  // unrolled by template recursion: the body is too large for the unroll
+  // pragma at P >= 8, and a run-time i would index gam and force it to scratch
+  static_for<0, P>([&](auto i_) {
+    constexpr int i = decltype(i_)::value;
     const int n = t + TR * i;
     const long long vox = vrc * (2 * MX) + 2 * n;   // first voxel of the pair
     T t0[C], t1[C], g0[C], g1[C];
@@ -871,7 +873,7 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
         for (int j = 0; j < C; ++j) *reinterpret_cast<cpx<T>*>(a.out + fo + (long long)j * g.nvox + vox) = res[j];
       }
     }
-  }
+  });
   if (!valid) part = 0.0;
   if (a.partials != nullptr) {
     const double s = block_sum<256>(part, red);
