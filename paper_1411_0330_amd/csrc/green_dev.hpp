@@ -239,8 +239,8 @@ template <typename T>
 __device__ __forceinline__ void bd_add(BD<T>& s, T w, T a, T b, T c) {
   const T aa = a * a, bb = b * b, cc = c * c;
   const T n2 = aa + bb + cc;
-  if (!(n2 > T(0)) || w == T(0)) return;
-  const T inv = recip(n2);
+  // no branch: a zero wave-vector (or weight) adds zeros
+  const T inv = (n2 > T(0)) ? recip(n2) : T(0);
   const T q = w * inv;      // w / |xi|^2
   const T u = q * inv;      // w / |xi|^4
   const T ab = a * b, ac = a * c, bc = b * c;

@@ -18,7 +18,7 @@ static int z_inst(hipStream_t s, const Geo& g, const GreenParams& gp, const Gree
 
 template <typename T, int NZ, int C>
 static int zm_inst(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, cpx<T>* sm,
-                   cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload) {
+                   cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload, double* qp, int ps) {
   constexpr int P = p_zm<T, C>(NZ);
   constexpr int TX = tx_zm<T>(NZ, P);
   constexpr int NT = TX * (NZ / P);
@@ -26,7 +26,7 @@ static int zm_inst(hipStream_t s, const Geo& g, const GreenParams& gp, const Gre
   const int main_tiles = g.ny * xtiles;
   const int nyq_tiles = (g.ny + TX - 1) / TX;
   hipLaunchKernelGGL((k_zgm<T, NZ, P, TX, C>), dim3(main_tiles + nyq_tiles, 1), dim3(NT), 0, s, g, gp, tb, sm, sn,
-                     tw, st, main_tiles, nload);
+                     tw, st, main_tiles, nload, qp, ps);
   return main_tiles + nyq_tiles;
 }
 
@@ -46,8 +46,8 @@ template <typename T, int NZ, int C>
 static int z_one(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, int zmode, cpx<T>* sm,
                  cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload, double* qp, int ps, int variant = 0) {
   if constexpr (sizeof(T) == 4 && (NZ == 128 || NZ == 256) && C != 2) {
-    if (variant == 4 && zmode == Z_GAMMA && gp.variant != kGreenFD && qp == nullptr)
-      return zm_inst<T, NZ, C>(s, g, gp, tb, sm, sn, tw, st, nload);
+    if (variant == 4 && zmode == Z_GAMMA && gp.variant != kGreenFD)
+      return zm_inst<T, NZ, C>(s, g, gp, tb, sm, sn, tw, st, nload, qp, ps);
   }
   if constexpr (NZ == 128 || NZ == 256) {
     switch (variant) {

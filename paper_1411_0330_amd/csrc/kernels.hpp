@@ -78,6 +78,33 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // ----------------------------------------------------------------------------
+// XCD-aware tile order for strided passes.  Workgroups are dealt round-robin
+// to the 8 XCDs, each with its own L2, so consecutive ids land on different
+// XCDs.  Where a tile of TX pencils spans less than a 128-byte line, S = 128 /
+// (TX * element) adjacent x tiles share every line; within each run of 8 S
+// ids, ids r, r + 8, ..., r + 8 (S - 1) (one XCD, dispatched one after
+// another) take x tiles r S, ..., r S + S - 1.  Ids past the last whole run
+// keep their order.
+// ----------------------------------------------------------------------------
+template <int S>
+__device__ __forceinline__ int xcd_tile(const int b, const int n) {
+  if constexpr (S <= 1) {
+    return b;
+  } else {
+    constexpr int RUN = 8 * S;
+    const int b0 = b - b % RUN;
+    if (b0 + RUN > n) return b;
+    const int r = b % RUN;
+    return b0 + (r % 8) * S + r / 8;
+  }
+}
+
+template <typename T, int TX>
+constexpr int line_share() {
+  return (TX * 2 * (int)sizeof(T) < 128) ? 128 / (TX * 2 * (int)sizeof(T)) : 1;
+}
+
+// ----------------------------------------------------------------------------
 // x forward: R2C along rows
 // ----------------------------------------------------------------------------
 template <typename T, int MX, int P>
@@ -439,8 +466,9 @@ __global__ __launch_bounds__(TX*(NY / P)) void k_y(const Geo g, cpx<T>* __restri
   bool valid;
   if ((int)blockIdx.x < main_tiles) {
     const int xtiles = (g.mx + TX - 1) / TX;
-    const int xc = blockIdx.x % xtiles;
-    const long long jz = blockIdx.x / xtiles;
+    const int tile = xcd_tile<line_share<T, TX>()>(blockIdx.x, main_tiles);
+    const int xc = tile % xtiles;
+    const long long jz = tile / xtiles;
     const int xl = tid % TX;
     t = tid / TX;
     const int kx = xc * TX + xl;
@@ -500,8 +528,9 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
   bool valid;
   if ((int)blockIdx.x < main_tiles) {
     const int xtiles = (g.mx + TX - 1) / TX;
-    const int xc = blockIdx.x % xtiles;
-    ky = blockIdx.x / xtiles;
+    const int tile = xcd_tile<line_share<T, TX>()>(blockIdx.x, main_tiles);
+    const int xc = tile % xtiles;
+    ky = tile / xtiles;
     kx = xc * TX + xl;
     valid = kx < g.mx;
     base = smain + (long long)l * main_cpx(g) + (long long)ky * g.mx + (valid ? kx : 0);
@@ -517,7 +546,8 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
   }
   cpx<T>* lp = lds + xl;
 
-  // all components' loads are issued before the first transform
+  // all components' loads are issued before the first transform (guarded
+  // reads: unguarded ones let the scheduler raise this kernel past 256 VGPRs)
   cpx<T> v[C][P];
 #pragma unroll
   for (int j = 0; j < C; ++j)
@@ -540,10 +570,12 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
         for (int j = 0; j < C; ++j) w[j] = v[j][i];
         green_apply<T, C>(gp, tb, k, tidx, w);
         if (qpart != nullptr) {
-          double d = 0.0;
+          // one wave-vector's terms in the field type (tau_hat . Gamma_hat tau_hat >= 0:
+          // no cancellation), the sum over wave-vectors in FP64
+          T d = T(0);
 #pragma unroll
-          for (int j = 0; j < C; ++j) d += (double)v[j][i].x * w[j].x + (double)v[j][i].y * w[j].y;
-          quad += d;
+          for (int j = 0; j < C; ++j) d += v[j][i].x * w[j].x + v[j][i].y * w[j].y;
+          quad += (double)d;
         }
 #pragma unroll
         for (int j = 0; j < C; ++j) v[j][i] = w[j];
@@ -570,19 +602,26 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
 // The same z pass for every load of a tile in one workgroup (truncated,
 // filtered and consistent operators): the operator matrices of the thread's
 // wave-vectors are formed once and applied to each load in turn, so the alias
-// sums (or the stored-table reads) are shared by all loads.
+// sums (or the stored-table reads) are shared by all loads.  The pencils of
+// the next active load are read into a second register set before the
+// current one is transformed: workgroup barriers wait on LDS traffic only, so
+// those HBM reads overlap the transforms.  With qpart, the per-load Parseval
+// partials of k_zg (one per workgroup and load).
 // ----------------------------------------------------------------------------
 template <typename T, int NZ, int P, int TX, int C>
 __global__ __launch_bounds__(TX*(NZ / P)) void k_zgm(const Geo g, const GreenParams gp, const GreenTabs<T> tb,
                                                     cpx<T>* __restrict__ smain, cpx<T>* __restrict__ snyq,
                                                     const cpx<T>* __restrict__ twz, const LoadState* __restrict__ st,
-                                                    const int main_tiles, const int nload) {
+                                                    const int main_tiles, const int nload,
+                                                    double* __restrict__ qpart, const int pstride) {
   constexpr int TZ = NZ / P;
+  constexpr int NT = TX * TZ;
   constexpr int NE = C * (C + 1) / 2;
   __shared__ cpx<T> lds[TX * NZ];
   __shared__ cpx<T> twl[NZ];
+  __shared__ double red[(NT + 63) / 64];
   const int tid = threadIdx.x;
-  for (int i = tid; i < NZ; i += TX * TZ) twl[i] = twz[i];
+  for (int i = tid; i < NZ; i += NT) twl[i] = twz[i];
   const int xl = tid % TX, t = tid / TX;
   cpx<T>* base;
   long long es_g, cstride, lstride;
@@ -590,8 +629,9 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zgm(const Geo g, const GreenPar
   bool valid;
   if ((int)blockIdx.x < main_tiles) {
     const int xtiles = (g.mx + TX - 1) / TX;
-    const int xc = blockIdx.x % xtiles;
-    ky = blockIdx.x / xtiles;
+    const int tile = xcd_tile<line_share<T, TX>()>(blockIdx.x, main_tiles);
+    const int xc = tile % xtiles;
+    ky = tile / xtiles;
     kx = xc * TX + xl;
     valid = kx < g.mx;
     base = smain + (long long)ky * g.mx + (valid ? kx : 0);
@@ -621,34 +661,64 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zgm(const Geo g, const GreenPar
       for (int q = 0; q < NE; ++q) G[i][q] = T(0);
     }
   }
+  // the same for every thread of the workgroup
+  auto next_active = [&](int l) {
+    while (l < nload && st != nullptr && !st[l].active) ++l;
+    return l;
+  };
+  // base is clamped to an existing pencil, so every lane reads in bounds and
+  // the reads need no branch; lanes past the edge never store
+  auto read = [&](cpx<T> (&dst)[C][P], int l) {
+    const cpx<T>* b = base + (long long)l * lstride;
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+#pragma unroll
+      for (int i = 0; i < P; ++i) dst[j][i] = b[j * cstride + (long long)(t + TZ * i) * es_g];
+  };
+  const double wk = (kx == 0 || kx == g.mx) ? 1.0 : 2.0;
   cpx<T>* lp = lds + xl;
+  int l = next_active(0);
+  cpx<T> nx[C][P];
+  if (l < nload) read(nx, l);
   __syncthreads();
-  for (int l = 0; l < nload; ++l) {
-    if (st != nullptr && !st[l].active) continue;   // the same for every thread of the workgroup
-    cpx<T>* b = base + (long long)l * lstride;
+  while (l < nload) {
     cpx<T> v[C][P];
 #pragma unroll
     for (int j = 0; j < C; ++j)
 #pragma unroll
-      for (int i = 0; i < P; ++i)
-        v[j][i] = valid ? b[j * cstride + (long long)(t + TZ * i) * es_g] : cpx<T>{0, 0};
+      for (int i = 0; i < P; ++i) v[j][i] = nx[j][i];
+    const int ln = next_active(l + 1);
+    if (ln < nload) read(nx, ln);
     fft_pencil_multi<NZ, P, -1, T, C>(v, t, lp, TX, twl, 1);
+    double quad = 0.0;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       cpx<T> w[C];
 #pragma unroll
       for (int j = 0; j < C; ++j) w[j] = v[j][i];
       sym_apply<T, C>(G[i], w);
+      if (qpart != nullptr) {
+        T d = T(0);
+#pragma unroll
+        for (int j = 0; j < C; ++j) d += v[j][i].x * w[j].x + v[j][i].y * w[j].y;
+        quad += (double)d;
+      }
 #pragma unroll
       for (int j = 0; j < C; ++j) v[j][i] = w[j];
     }
+    if (qpart != nullptr) {
+      const double s = block_sum<NT>(valid ? quad * wk / (double)g.nvox : 0.0, red);
+      if (tid == 0) qpart[(long long)l * pstride + blockIdx.x] = s;
+    }
     fft_pencil_multi<NZ, P, 1, T, C>(v, t, lp, TX, twl, 1);
     if (valid) {
+      cpx<T>* b = base + (long long)l * lstride;
 #pragma unroll
       for (int j = 0; j < C; ++j)
 #pragma unroll
         for (int i = 0; i < P; ++i) b[j * cstride + (long long)(t + TZ * i) * es_g] = v[j][i];
     }
+    l = ln;
   }
 }
 

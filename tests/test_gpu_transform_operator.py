@@ -246,15 +246,20 @@ def test_multi_load_z_pass_matches_oracle(lsh, monkeypatch, physics, shape, nloa
     assert rel_max_err(out, ref) <= 1e-5
 
 
-def test_multi_load_z_pass_in_a_batched_solve(lsh, monkeypatch):
-    # loads converging at different steps: frozen loads are skipped inside the workgroup loop
+@pytest.mark.parametrize("physics", ["elastic", "scalar"])
+def test_multi_load_z_pass_in_a_batched_solve(lsh, monkeypatch, physics):
+    # loads converging at different steps: frozen loads are skipped inside the
+    # workgroup loop, and the fused CG step takes its p.Gamma p partials from it
     ph = I.random_phases((128, 16, 16), 2, seed=5)
-    moduli = np.stack([ELAS[0], ELAS[1]])
-    loads = np.eye(6)[[0, 3, 5]] * np.array([[1.0], [1e-3], [5.0]])
+    if physics == "elastic":
+        moduli, A0, c = np.stack([ELAS[0], ELAS[1]]), C0, 6
+    else:
+        moduli, A0, c = np.stack([np.eye(3), 10.0 * np.eye(3)]), 0.5 * np.eye(3), 3
+    loads = np.eye(c)[[0, c // 2, c - 1]] * np.array([[1.0], [1e-3], [5.0]])
     res = {}
     for tune in ("", "zg32=4"):
         monkeypatch.setenv("LSH_TUNE", tune)
-        ctx = context(lsh, ph, moduli, C0, "elastic", "filtered", precision="mixed", max_loads=3)
+        ctx = context(lsh, ph, moduli, A0, physics, "filtered", precision="mixed", max_loads=3)
         rep = ctx.solve(loads, "cg", tol=1e-8, maxit=2000)
         assert rep["status"] == lsh.OK
         res[tune] = (ctx.effective().copy(), rep["iterations"])
