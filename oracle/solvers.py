@@ -183,3 +183,93 @@ def eyre_milton(pb: op.Problem, p, tol: float = 1e-10, maxit: int = 10000, histo
         if rel <= tol:
             break
     return {"tau": tau, "iters": it, "rel_res": rel}
+
+
+def symmlq(pb: op.Problem, p, tol: float = 1e-10, maxit: int = 1000, history=None, iterates=None):
+    """SYMMLQ of Paige and Saunders (1975) on L tau = b, tau_0 = 0, the Krylov
+    solver the paper names for the symmetric indefinite system that eq. (13)
+    becomes when A0 lies between the phases.
+
+    The Lanczos process is that of MINRES.  An LQ factorisation T_k = Lbar_k Q_k
+    of the tridiagonal matrix, by reflectors [c s; s -c] acting on columns
+    (k, k+1), has the recurrences of MINRES's QR (T_k is symmetric):
+        delta_k   = c_{k-1} dbar_k + s_{k-1} alpha_k
+        gbar_k    = s_{k-1} dbar_k - c_{k-1} alpha_k
+        eps_{k+1} = s_{k-1} beta_{k+1},  dbar_{k+1} = -c_{k-1} beta_{k+1}
+        gamma_k   = hypot(gbar_k, beta_{k+1}),  c_k = gbar_k / gamma_k,
+        s_k       = beta_{k+1} / gamma_k,
+    from c_0 = -1, s_0 = 0, dbar_1 = 0.  Forward substitution in
+    L z = ||b|| e_1 with num_k = [k = 1] ||b|| - delta_k z_{k-1} - eps_k z_{k-2}
+    gives z_k = num_k / gamma_k and, with the last diagonal unrotated,
+    zbar_k = num_k / gbar_k.  The rotated Lanczos vectors are
+        w_k = c_k wbar_k + s_k v_{k+1},  wbar_{k+1} = s_k wbar_k - c_k v_{k+1},
+    wbar_1 = v_1.  The SYMMLQ iterate x^L_k = x^L_{k-1} + z_k w_k has the
+    least error ||tau* - x|| over x in L K_k(L, b); the CG point
+    x^C_k = x^L_{k-1} + zbar_k wbar_k (Galerkin over K_k, defined when
+    gbar_k != 0) has the residual |beta_{k+1}| |s_{k-1} z_{k-1} - c_{k-1} zbar_k|.
+
+    The loop stops once that residual is at most tol ||b|| and returns the CG
+    point; after maxit steps it returns the CG point of the last step (x^L_k if
+    gbar_k = 0).  ``history`` receives the CG-point residual / ||b|| after each
+    step; ``iterates`` (a list) receives (x^L_k, x^C_k or None) after each step
+    that was not the last."""
+    b = op.rhs(pb, p)
+    bnorm = math.sqrt(op.dot(b, b))
+    x = np.zeros_like(b)
+    if bnorm == 0.0:
+        return {"tau": x, "iters": 0, "rel_res": 0.0}
+    v_prev = np.zeros_like(b)
+    v = b / bnorm
+    wbar = v.copy()
+    beta = 0.0
+    c_prev, s_prev = -1.0, 0.0
+    dbar, eps = 0.0, 0.0
+    z1 = z2 = 0.0                      # z_{k-1}, z_{k-2}
+    first = bnorm                      # right-hand side entry of this row
+    out = None
+    it = 0
+    while it < maxit:
+        q = op.apply(pb, v)
+        it += 1
+        alpha = op.dot(v, q)
+        q = q - alpha * v - beta * v_prev
+        bn = math.sqrt(op.dot(q, q))
+        delta = c_prev * dbar + s_prev * alpha
+        gbar = s_prev * dbar - c_prev * alpha
+        eps_next, dbar_next = s_prev * bn, -c_prev * bn
+        num = first - delta * z1 - eps * z2
+        if gbar != 0.0:
+            zbar = num / gbar
+            xc = x + zbar * wbar
+            rc = bn * abs(s_prev * z1 - c_prev * zbar)
+        else:
+            xc, rc = None, math.inf
+        if history is not None:
+            history.append(rc / bnorm)
+        if rc <= tol * bnorm:
+            out = xc
+            break
+        gamma = math.hypot(gbar, bn)
+        if gamma == 0.0:               # beta_{k+1} = gbar_k = 0: singular on the Krylov space
+            out = x
+            break
+        c, s = gbar / gamma, bn / gamma
+        z = num / gamma
+        vn = q / bn
+        w = c * wbar + s * vn
+        wbar = s * wbar - c * vn
+        x = x + z * w
+        if it == maxit:
+            out = xc if xc is not None else x
+            break
+        if iterates is not None:
+            iterates.append((x.copy(), None if xc is None else xc.copy()))
+        v_prev, v = v, vn
+        beta, dbar, eps = bn, dbar_next, eps_next
+        c_prev, s_prev = c, s
+        z2, z1 = z1, z
+        first = 0.0
+    if out is None:
+        out = x
+    true_r = b - op.apply(pb, out)
+    return {"tau": out, "iters": it, "rel_res": math.sqrt(op.dot(true_r, true_r)) / bnorm}

@@ -1,4 +1,4 @@
-"""Pins of the oracle's MINRES and Eyre--Milton solvers.
+"""Pins of the oracle's MINRES, SYMMLQ and Eyre--Milton solvers.
 
 * Both reach the exact solution of eq. (12) (dense LAPACK solve) on small
   grids: scalar 2D with A0 between the phases (symmetric indefinite system)
@@ -10,7 +10,13 @@
   rho = max |(a - a0)/(a + a0)| (Euclidean norm), the bound that follows from
   0 <= a0 Gamma <= Id; at a0 = sqrt(a_min a_max) it needs fewer iterations than
   the basic scheme at its own best a0.
-* Planted mistakes in either solver break one of these pins.
+* SYMMLQ: reaches the dense solution; each iterate x^L_k is the orthogonal
+  projection of the exact solution onto L K_k(L, b) (least error), and each
+  CG point x^C_k is the Galerkin solution over K_k(L, b) -- both computed by
+  brute force from explicitly orthonormalised Krylov bases -- with the
+  residual the recurrence reports; on a definite system the CG points are
+  the CG iterates.
+* Planted mistakes in any of the solvers break one of these pins.
 """
 import math
 
@@ -164,3 +170,109 @@ def test_planted_minres_mistake_is_caught(variant):
     name, pb, p = CASES[0]
     assert _rel(_minres_variant(pb, p), dense.solve(pb, p)) <= 1e-9       # the unplanted copy agrees
     assert _rel(_minres_variant(pb, p, **variant), dense.solve(pb, p)) > 1e-6
+
+
+# SYMMLQ ------------------------------------------------------------------
+@pytest.mark.parametrize("name,pb,p", CASES, ids=[c[0] for c in CASES])
+def test_symmlq_reaches_the_dense_solution(name, pb, p):
+    exact = dense.solve(pb, p)
+    hist = []
+    r = solvers.symmlq(pb, p, tol=1e-13, maxit=2000, history=hist)
+    assert _rel(r["tau"], exact) <= 1e-9
+    assert r["rel_res"] <= 1e-11 and abs(r["rel_res"] - hist[-1]) <= 1e-10
+
+
+def _krylov_basis(pb, b, k):
+    """Orthonormal basis of K_k(L, b) by Arnoldi with full re-orthogonalisation
+    (columns flattened), and L applied to each basis vector."""
+    shape = b.shape
+    Q = [b.ravel() / np.linalg.norm(b)]
+    LQ = []
+    for j in range(k):
+        y = op.apply(pb, Q[j].reshape(shape)).ravel()
+        LQ.append(y)
+        if j + 1 < k:
+            for _ in range(2):
+                for q in Q:
+                    y = y - (q @ y) * q
+            Q.append(y / np.linalg.norm(y))
+    return np.stack(Q, axis=1), np.stack(LQ, axis=1)
+
+
+SMALL = [
+    ("disk8-indefinite", op.Problem(I.disk_2d(8), MODS2, 5.5 * np.eye(2), "scalar", "filtered"), [1.0, 0.3]),
+    ("aniso-indefinite", op.Problem(I.random_phases((4, 6), 2, seed=1), _aniso(), np.array([[4.0, 0.4], [0.4, 3.5]]),
+                                    "scalar", "truncated"), [0.2, 1.0]),
+    ("elastic-indefinite", _elastic_indefinite(), np.eye(6)[0] + 0.5 * np.eye(6)[5]),
+]
+
+
+@pytest.mark.parametrize("name,pb,p", SMALL, ids=[c[0] for c in SMALL])
+def test_symmlq_iterates_by_brute_force(name, pb, p):
+    K = 7
+    exact = dense.solve(pb, p).ravel()
+    b = op.rhs(pb, p)
+    its, hist = [], []
+    solvers.symmlq(pb, p, tol=0.0, maxit=K + 1, history=hist, iterates=its)
+    assert len(its) == K
+    for k in range(1, K + 1):
+        Q, LQ = _krylov_basis(pb, b, k)
+        U, _ = np.linalg.qr(LQ)
+        xl_ref = U @ (U.T @ exact)                                   # least error over L K_k
+        xc_ref = Q @ np.linalg.solve(Q.T @ LQ, Q.T @ b.ravel())      # Galerkin over K_k
+        xl, xc = its[k - 1]
+        assert np.linalg.norm(xl.ravel() - xl_ref) <= 1e-8 * np.linalg.norm(xl_ref)
+        assert xc is not None
+        assert np.linalg.norm(xc.ravel() - xc_ref) <= 1e-8 * np.linalg.norm(xc_ref)
+        rc = np.linalg.norm(b - op.apply(pb, xc)) / np.linalg.norm(b)
+        assert abs(rc - hist[k - 1]) <= 1e-9 * max(1.0, rc)
+
+
+def test_symmlq_cg_points_are_the_cg_iterates_on_a_definite_system():
+    pb = op.Problem(I.disk_2d(10), MODS2, 0.5 * np.eye(2), "scalar", "filtered")
+    p = [1.0, 0.0]
+    its = []
+    solvers.symmlq(pb, p, tol=0.0, maxit=12, iterates=its)
+    for k in (1, 4, 11):
+        x_cg = solvers.cg(pb, p, tol=0.0, maxit=k)["tau"]
+        assert _rel(its[k - 1][1], x_cg) <= 1e-10
+
+
+def _symmlq_variant(pb, p, wbar_sign=1.0, drop_eps=False, tol=1e-13, maxit=2000):
+    """The oracle's SYMMLQ loop with one planted change."""
+    b = op.rhs(pb, p)
+    bnorm = math.sqrt(op.dot(b, b))
+    x = np.zeros_like(b)
+    v_prev, v = np.zeros_like(b), b / bnorm
+    wbar = v.copy()
+    beta, c_prev, s_prev, dbar, eps, z1, z2, first = 0.0, -1.0, 0.0, 0.0, 0.0, 0.0, 0.0, bnorm
+    xc = x
+    for _ in range(maxit):
+        q = op.apply(pb, v)
+        alpha = op.dot(v, q)
+        q = q - alpha * v - beta * v_prev
+        bn = math.sqrt(op.dot(q, q))
+        delta = c_prev * dbar + s_prev * alpha
+        gbar = s_prev * dbar - c_prev * alpha
+        num = first - delta * z1 - (0.0 if drop_eps else eps) * z2
+        zbar = num / gbar
+        xc = x + zbar * wbar
+        if bn * abs(s_prev * z1 - c_prev * zbar) <= tol * bnorm:
+            break
+        gamma = math.hypot(gbar, bn)
+        c, s = gbar / gamma, bn / gamma
+        vn = q / bn
+        w = c * wbar + s * vn
+        wbar = wbar_sign * s * wbar - c * vn
+        x = x + (num / gamma) * w
+        eps, dbar = s_prev * bn, -c_prev * bn
+        v_prev, v, beta, c_prev, s_prev, z2, z1, first = v, vn, bn, c, s, z1, num / gamma, 0.0
+    return xc
+
+
+@pytest.mark.parametrize("variant", [dict(wbar_sign=-1.0), dict(drop_eps=True)])
+def test_planted_symmlq_mistake_is_caught(variant):
+    name, pb, p = SMALL[0]
+    exact = dense.solve(pb, p)
+    assert _rel(_symmlq_variant(pb, p), exact) <= 1e-9       # the unplanted copy agrees
+    assert _rel(_symmlq_variant(pb, p, maxit=400, **variant), exact) > 1e-6
