@@ -55,7 +55,13 @@ typedef enum {
 enum { LSH_SCALAR = 0, LSH_ELASTIC = 1 };            /* physics */
 enum { LSH_FP64 = 0, LSH_MIXED = 1 };                /* precision */
 enum { LSH_GREEN_TRUNCATED = 0, LSH_GREEN_FILTERED = 1, LSH_GREEN_CONSISTENT = 2, LSH_GREEN_FD = 3 };
-enum { LSH_SOLVER_BASIC = 0, LSH_SOLVER_CG = 1, LSH_SOLVER_MINRES = 2, LSH_SOLVER_EYRE_MILTON = 3 };
+enum {
+  LSH_SOLVER_BASIC = 0,
+  LSH_SOLVER_CG = 1,
+  LSH_SOLVER_MINRES = 2,
+  LSH_SOLVER_EYRE_MILTON = 3,
+  LSH_SOLVER_SYMMLQ = 4
+};
 enum { LSH_HOST = 0, LSH_DEVICE = 1 };               /* memory space of a pointer */
 enum { LSH_F64 = 0, LSH_F32 = 1 };                   /* element type of a field buffer */
 enum { LSH_FIELD_TAU = 0, LSH_FIELD_STRAIN = 1 };
@@ -163,10 +169,12 @@ lsh_status lsh_bind_green_table(lsh_ctx* ctx, void* dev_ptr, size_t bytes);
 lsh_status lsh_set_green_series(lsh_ctx* ctx, int nmax);
 
 /*
- * MINRES keeps four FP64 fields per load (two Lanczos vectors, two search
- * directions) in caller-owned device memory of lsh_solver_buffer_bytes bytes
- * bound with lsh_bind_solver_buffer (256-byte aligned); the other solvers
- * need none (0 bytes).
+ * MINRES and SYMMLQ keep four FP64 fields per load (MINRES: two Lanczos
+ * vectors, two search directions; SYMMLQ uses three: two Lanczos vectors and
+ * the partially rotated direction wbar) in caller-owned device memory of
+ * lsh_solver_buffer_bytes bytes (the same for both) bound with
+ * lsh_bind_solver_buffer (256-byte aligned); the other solvers need none
+ * (0 bytes).
  */
 lsh_status lsh_solver_buffer_bytes(const lsh_ctx* ctx, int solver, size_t* bytes);
 lsh_status lsh_bind_solver_buffer(lsh_ctx* ctx, void* dev_ptr, size_t bytes);
@@ -185,8 +193,16 @@ lsh_status lsh_bind_solver_buffer(lsh_ctx* ctx, void* dev_ptr, size_t bytes);
  *   LSH_SOLVER_EYRE_MILTON  the fixed point tau = (A - A0)(A + A0)^{-1}
  *                           (tau + 2 A0 (p - Gamma tau)) of the Eyre--Milton
  *                           scheme, contracting for any SPD A0 (factor
- *                           max |(a - a0)/(a + a0)| for scalar A0 = a0 Id).
- * The basic, MINRES and Eyre--Milton iterations run in FP64 in either
+ *                           max |(a - a0)/(a + a0)| for scalar A0 = a0 Id);
+ *   LSH_SOLVER_SYMMLQ       SYMMLQ (Paige and Saunders), named beside CG as
+ *                           a solver of the discretised equation (Section 1),
+ *                           for the symmetric indefinite system of an A0
+ *                           between the phases: LQ iterates of
+ *                           least error over L K_k(L, b); it stops on the
+ *                           residual of the CG point and returns that point
+ *                           (also after maxit steps, when it exists); needs
+ *                           the solver buffer.
+ * The basic, MINRES, SYMMLQ and Eyre--Milton iterations run in FP64 in either
  * precision; CG in a mixed context uses FP32 fields with FP64 refinement.
  *   reports   host array of nload lsh_load_report (may be NULL).
  *   summary   host lsh_solve_report (may be NULL).

@@ -1,9 +1,11 @@
 """Iterative solvers of the discrete system eq. (13) (oracle).
 
-Both follow textbook definitions.  The paper cites conjugate gradients
+Each follows its textbook definition.  The paper cites conjugate gradients
 (its Section 5 choice, valid when A0 is softer than every phase so that the
-system is positive definite) and the fixed-point scheme of Moulinec and
-Suquet, which it does not write out.
+system is positive definite), SYMMLQ beside it (Section 1), and the
+fixed-point scheme of Moulinec and Suquet, which it does not write out.
+MINRES (the other Lanczos solver of symmetric indefinite systems) and the
+Eyre--Milton scheme complete the set.
 """
 from __future__ import annotations
 
@@ -186,9 +188,9 @@ def eyre_milton(pb: op.Problem, p, tol: float = 1e-10, maxit: int = 10000, histo
 
 
 def symmlq(pb: op.Problem, p, tol: float = 1e-10, maxit: int = 1000, history=None, iterates=None):
-    """SYMMLQ of Paige and Saunders (1975) on L tau = b, tau_0 = 0, the Krylov
-    solver the paper names for the symmetric indefinite system that eq. (13)
-    becomes when A0 lies between the phases.
+    """SYMMLQ of Paige and Saunders (1975) on L tau = b, tau_0 = 0: the Krylov
+    solver named beside CG in Section 1, for the symmetric indefinite system
+    that eq. (13) becomes when A0 lies between the phases.
 
     The Lanczos process is that of MINRES.  An LQ factorisation T_k = Lbar_k Q_k
     of the tridiagonal matrix, by reflectors [c s; s -c] acting on columns

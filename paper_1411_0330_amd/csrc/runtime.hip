@@ -1027,6 +1027,79 @@ lsh_status mr_loop(lsh_ctx* ctx, int nload, double tol, int maxit, std::vector<L
   return LSH_OK;
 }
 
+// SYMMLQ on x64: MINRES's Lanczos step, then the LQ step or the transfer to
+// the CG point (k_sy_scal, k_sy_update); fields v_{k-1}/v_{k+1}, v_k, wbar_k
+// in the bound solver buffer.
+lsh_status sy_loop(lsh_ctx* ctx, int nload, double tol, int maxit, std::vector<LoadState>& hst) {
+  const long long F = ctx->F;
+  const long long LF = (long long)ctx->max_loads * F;
+  double* vp = reinterpret_cast<double*>(ctx->sbuf);
+  double* v = vp + LF;
+  double* wbar = vp + 2 * LF;
+  double* x = ctx->ptr<double>(ctx->off.x64);
+  LoadState* st = ctx->ptr<LoadState>(ctx->off.st_out);
+  MinresState* ms = ctx->ptr<MinresState>(ctx->off.mstate);
+  double* parts = ctx->ptr<double>(ctx->off.partials);
+  STCHK(cg_init<double>(ctx, nload, x, v, st, tol));   // x = 0, v = b, ||b||^2
+  {
+    Scope sc(ctx, K_INIT);
+    hipLaunchKernelGGL(k_sy_start, dim3((unsigned)((F + 255) / 256), nload), dim3(256), 0, ctx->stream, F, v, vp,
+                       wbar, st);
+    STCHK(check_launch(ctx, 0, "symmlq start"));
+  }
+  {
+    Scope sc(ctx, K_SCAL);
+    hipLaunchKernelGGL(k_sy_scal, dim3(nload), dim3(256), 0, ctx->stream, (int)SY_INIT, parts, (int)ctx->pstride, 0,
+                       0, st, ms);
+    STCHK(check_launch(ctx, 0, "symmlq init"));
+  }
+  const int period = check_period(ctx, nload);
+  STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
+  ctx->nact = 0;
+  bool any = false;
+  for (auto& sv : hst) any |= sv.active != 0, ctx->nact += sv.active != 0;
+  if (!any) return LSH_OK;
+  double* q = reinterpret_cast<double*>(Sel<double>::sm(ctx));
+  const int nbe = (int)((F + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
+  for (int it = 0; it < maxit; ++it) {
+    STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, v, nullptr, nullptr, nullptr, st, true));
+    int np = 0;
+    STCHK(inverse_x<double>(ctx, 0, nload, XI_CG, v, q, nullptr, st, parts, &np));
+    {
+      Scope sc(ctx, K_SCAL);
+      hipLaunchKernelGGL(k_mr_scal, dim3(nload), dim3(256), 0, ctx->stream, (int)MR_ALPHA, parts, (int)ctx->pstride,
+                         np, st, ms);
+      STCHK(check_launch(ctx, 0, "symmlq alpha"));
+    }
+    {
+      Scope sc(ctx, kcls<double>(K_CGUPD), std::min(ctx->nact, nload) * 4.0 * (double)F * 8.0);
+      hipLaunchKernelGGL(k_mr_lanczos, dim3(nbe, nload), dim3(256), 0, ctx->stream, F, q, v, vp, st, ms, parts,
+                         (int)ctx->pstride);
+      STCHK(check_launch(ctx, 0, "symmlq lanczos"));
+    }
+    {
+      Scope sc(ctx, K_SCAL);
+      hipLaunchKernelGGL(k_sy_scal, dim3(nload), dim3(256), 0, ctx->stream, (int)SY_ROT, parts, (int)ctx->pstride,
+                         nbe, it + 1 == maxit ? 1 : 0, st, ms);
+      STCHK(check_launch(ctx, 0, "symmlq rotation"));
+    }
+    {
+      Scope sc(ctx, kcls<double>(K_CGUPD), std::min(ctx->nact, nload) * 6.0 * (double)F * 8.0);
+      hipLaunchKernelGGL(k_sy_update, dim3(nbe, nload), dim3(256), 0, ctx->stream, F, vp, wbar, x, ms);
+      STCHK(check_launch(ctx, 0, "symmlq update"));
+    }
+    std::swap(v, vp);    // v_{k+1} now in the old v_{k-1} slot
+    if ((it + 1) % period == 0 || it + 1 == maxit) {
+      STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
+      any = false;
+      ctx->nact = 0;
+      for (auto& sv : hst) any |= sv.active != 0, ctx->nact += sv.active != 0;
+      if (!any) break;
+    }
+  }
+  return LSH_OK;
+}
+
 // ||b - L x||^2 per load into sums[0..nload) (FP64 application on x64)
 lsh_status true_residual(lsh_ctx* ctx, int nload) {
   double* x = ctx->ptr<double>(ctx->off.x64);
@@ -1515,8 +1588,9 @@ lsh_status lsh_set_green_series(lsh_ctx* ctx, int nmax) {
 
 lsh_status lsh_solver_buffer_bytes(const lsh_ctx* ctx, int solver, size_t* bytes) {
   if (!ctx || !bytes) return LSH_EINVAL;
-  if (solver < LSH_SOLVER_BASIC || solver > LSH_SOLVER_EYRE_MILTON) return LSH_EINVAL;
-  *bytes = solver == LSH_SOLVER_MINRES ? align_up(4 * sizeof(double) * (size_t)ctx->max_loads * ctx->F) : 0;
+  if (solver < LSH_SOLVER_BASIC || solver > LSH_SOLVER_SYMMLQ) return LSH_EINVAL;
+  const bool krylov = solver == LSH_SOLVER_MINRES || solver == LSH_SOLVER_SYMMLQ;
+  *bytes = krylov ? align_up(4 * sizeof(double) * (size_t)ctx->max_loads * ctx->F) : 0;
   return LSH_OK;
 }
 
@@ -1537,7 +1611,7 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
                      lsh_load_report* reports, lsh_solve_report* summary) {
   if (!ctx) return LSH_EINVAL;
   if (solver != LSH_SOLVER_BASIC && solver != LSH_SOLVER_CG && solver != LSH_SOLVER_MINRES &&
-      solver != LSH_SOLVER_EYRE_MILTON)
+      solver != LSH_SOLVER_EYRE_MILTON && solver != LSH_SOLVER_SYMMLQ)
     return fail(ctx, LSH_EINVAL, "unknown solver");
   if (nload < 1 || nload > ctx->max_loads) return fail(ctx, LSH_EINVAL, "nload out of range");
   if (!loads) return fail(ctx, LSH_EINVAL, "null loads");
@@ -1546,8 +1620,8 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
   const int c = ctx->c;
   for (int i = 0; i < nload * c; ++i)
     if (!std::isfinite(loads[i])) return fail(ctx, LSH_EINVAL, "non-finite load");
-  if (solver == LSH_SOLVER_MINRES && !ctx->sbuf)
-    return fail(ctx, LSH_ESTATE, "MINRES needs a bound solver buffer (lsh_solver_buffer_bytes)");
+  if ((solver == LSH_SOLVER_MINRES || solver == LSH_SOLVER_SYMMLQ) && !ctx->sbuf)
+    return fail(ctx, LSH_ESTATE, "MINRES and SYMMLQ need a bound solver buffer (lsh_solver_buffer_bytes)");
   if (solver == LSH_SOLVER_BASIC || solver == LSH_SOLVER_EYRE_MILTON) {
     const bool em = solver == LSH_SOLVER_EYRE_MILTON;
     if (ctx->tab_em != em) {
@@ -1581,8 +1655,8 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
                      solver == LSH_SOLVER_BASIC ? XI_BASIC : XI_EM));
     STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
     for (int l = 0; l < nload; ++l) iters[l] = hst[l].iters, apps64 += hst[l].iters;
-  } else if (solver == LSH_SOLVER_MINRES) {
-    STCHK(mr_loop(ctx, nload, tol, maxit, hst));
+  } else if (solver == LSH_SOLVER_MINRES || solver == LSH_SOLVER_SYMMLQ) {
+    STCHK(solver == LSH_SOLVER_MINRES ? mr_loop(ctx, nload, tol, maxit, hst) : sy_loop(ctx, nload, tol, maxit, hst));
     STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
     for (int l = 0; l < nload; ++l) iters[l] = hst[l].iters, apps64 += hst[l].iters;
   } else if (ctx->precision == LSH_FP64) {

@@ -14,10 +14,14 @@ namespace lsh {
 struct MinresState {
   double alpha, beta, c, s, delta1, eps, phi;  // recurrences (beta = beta_k, eps = eps_k)
   double delta2, epsk, gamma2, t, inv_beta;    // coefficients of this step's vector update
+  double z1, z2, first, zbar, wc, ws;          // SYMMLQ: z_{k-1}, z_{k-2}, row k's right-hand side,
+                                               // CG-point coefficient, rotation of this step
   int apply, pad;
 };
 
 enum : int { MR_INIT = 0, MR_ALPHA = 1, MR_ROT = 2 };
+enum : int { SY_INIT = 0, SY_ROT = 1 };
+enum : int { SY_NONE = 0, SY_STEP = 1, SY_TRANSFER = 2 };
 
 // v = b / ||b||, v_prev = w_{k-1} = w_{k-2} = 0 on the loads that iterate
 static __global__ __launch_bounds__(256) void k_mr_start(const long long F, double* __restrict__ v,
@@ -159,6 +163,144 @@ static __global__ __launch_bounds__(256) void k_mr_scal(const int mode, const do
   M.s = s;
   L.res2 = M.phi * M.phi;
   if (L.res2 <= L.tol2 || bn == 0.0) L.active = 0;
+}
+
+// ----------------------------------------------------------------------------
+// SYMMLQ (Paige--Saunders) on the same fields: the Lanczos step is MINRES's
+// (k_mr_scal MR_ALPHA, k_mr_lanczos); the LQ factorisation of the tridiagonal
+// matrix by reflectors [c s; s -c] on columns (k, k+1) has MINRES's rotation
+// recurrences (dbar in delta1), then forward substitution gives
+// z_k = num_k / gamma_k and the CG-point coefficient zbar_k = num_k / gbar_k,
+// num_k = [k = 1] ||b|| - delta_k z_{k-1} - eps_k z_{k-2}.  The fields are
+// v_{k-1} (overwritten by v_{k+1}), v_k, wbar_k and the iterate x^L.
+// ----------------------------------------------------------------------------
+
+// v = b / ||b||, v_prev = 0, wbar_1 = v on the loads that iterate
+static __global__ __launch_bounds__(256) void k_sy_start(const long long F, double* __restrict__ v,
+                                                  double* __restrict__ vp, double* __restrict__ wbar,
+                                                  const LoadState* __restrict__ st) {
+  const int l = blockIdx.y;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= F) return;
+  const long long o = (long long)l * F + i;
+  const double sc = st[l].bb > 0.0 ? 1.0 / sqrt(st[l].bb) : 0.0;
+  const double vv = v[o] * sc;
+  v[o] = vv;
+  vp[o] = 0.0;
+  wbar[o] = vv;
+}
+
+// Scalar step of SYMMLQ after the Lanczos step (one workgroup per load).  The
+// CG point's residual |beta_{k+1}| |s_{k-1} z_{k-1} - c_{k-1} zbar_k| is the
+// stopping quantity: at tol ||b|| the load transfers to the CG point
+// (x = x^L_{k-1} + zbar_k wbar_k) and stops; on the last allowed step it
+// transfers without stopping (the host reports the iteration limit); with
+// gbar_k = 0 there is no CG point and the LQ step is taken; gamma_k = 0 (the
+// system singular on the Krylov space) is a breakdown.
+static __global__ __launch_bounds__(256) void k_sy_scal(const int mode, const double* __restrict__ partials,
+                                                        const int pstride, const int nparts, const int last,
+                                                        LoadState* __restrict__ st, MinresState* __restrict__ ms) {
+  __shared__ double red[256];
+  const int l = blockIdx.x;
+  const double S = mode == SY_INIT ? 0.0 : group_sum(partials, pstride, nparts, l, red);
+  if (threadIdx.x != 0) return;
+  LoadState& L = st[l];
+  MinresState& M = ms[l];
+  if (mode == SY_INIT) {
+    M.alpha = M.beta = M.delta1 = M.eps = 0.0;
+    M.c = -1.0;
+    M.s = 0.0;
+    M.z1 = M.z2 = M.zbar = M.wc = M.ws = M.t = M.inv_beta = 0.0;
+    M.first = sqrt(L.bb);
+    M.apply = SY_NONE;
+    return;
+  }
+  M.apply = SY_NONE;
+  if (!L.active) return;
+  if (!isfinite(S) || !isfinite(M.alpha)) {
+    L.status = kStatusNumeric;
+    L.active = 0;
+    return;
+  }
+  const double bn = sqrt(S);
+  const double delta = M.c * M.delta1 + M.s * M.alpha;
+  const double gbar = M.s * M.delta1 - M.c * M.alpha;
+  const double eps_next = M.s * bn;
+  const double dbar_next = -M.c * bn;
+  const double num = M.first - delta * M.z1 - M.eps * M.z2;
+  L.iters += 1;
+  double zbar = 0.0;
+  if (gbar != 0.0) {
+    zbar = num / gbar;
+    const double rc = bn * fabs(M.s * M.z1 - M.c * zbar);
+    L.res2 = rc * rc;
+    if (L.res2 <= L.tol2) {
+      M.zbar = zbar;
+      M.apply = SY_TRANSFER;
+      L.active = 0;
+      return;
+    }
+  }
+  const double gamma = hypot(gbar, bn);
+  if (gamma == 0.0) {
+    L.status = kStatusBreakdown;
+    L.active = 0;
+    return;
+  }
+  if (last && gbar != 0.0) {
+    M.zbar = zbar;
+    M.apply = SY_TRANSFER;
+    return;
+  }
+  const double c = gbar / gamma, s = bn / gamma;
+  const double z = num / gamma;
+  M.wc = c;
+  M.ws = s;
+  M.t = z;
+  M.inv_beta = 1.0 / bn;   // bn > 0: bn = 0 gives a zero CG residual or gamma = 0 above
+  M.apply = SY_STEP;
+  M.beta = bn;
+  M.delta1 = dbar_next;
+  M.eps = eps_next;
+  M.c = c;
+  M.s = s;
+  M.z2 = M.z1;
+  M.z1 = z;
+  M.first = 0.0;
+}
+
+// SY_STEP: v_{k+1} = vp / beta_{k+1} in place, w_k = c wbar_k + s v_{k+1},
+// wbar_{k+1} = s wbar_k - c v_{k+1}, x += z_k w_k.  SY_TRANSFER: x += zbar_k wbar_k.
+static __global__ __launch_bounds__(256) void k_sy_update(const long long F, double* __restrict__ vp,
+                                                   double* __restrict__ wbar, double* __restrict__ x,
+                                                   const MinresState* __restrict__ ms) {
+  const int l = blockIdx.y;
+  const MinresState& m = ms[l];
+  if (m.apply == SY_NONE) return;
+  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
+  if (m.apply == SY_TRANSFER) {
+#pragma unroll
+    for (int u = 0; u < kEwUnroll; ++u) {
+      const long long i = b0 + (long long)u * 256;
+      if (i < F) {
+        const long long o = (long long)l * F + i;
+        x[o] += m.zbar * wbar[o];
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int u = 0; u < kEwUnroll; ++u) {
+    const long long i = b0 + (long long)u * 256;
+    if (i < F) {
+      const long long o = (long long)l * F + i;
+      const double vn = vp[o] * m.inv_beta;
+      const double wb = wbar[o];
+      vp[o] = vn;
+      wbar[o] = m.ws * wb - m.wc * vn;
+      x[o] += m.t * (m.wc * wb + m.ws * vn);
+    }
+  }
 }
 
 // Deterministic final reduction of the partials of group blockIdx.x, then the

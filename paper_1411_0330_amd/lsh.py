@@ -23,13 +23,13 @@ STATUS_NAMES = {0: "OK", 1: "MAXIT", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4:
 SCALAR, ELASTIC = 0, 1
 FP64, MIXED = 0, 1
 TRUNCATED, FILTERED, CONSISTENT, FD = 0, 1, 2, 3
-BASIC, CG, MINRES, EYRE_MILTON = 0, 1, 2, 3
+BASIC, CG, MINRES, EYRE_MILTON, SYMMLQ = 0, 1, 2, 3, 4
 HOST, DEVICE = 0, 1
 F64, F32 = 0, 1
 TAU, STRAIN = 0, 1
 
 GREEN = {"truncated": TRUNCATED, "filtered": FILTERED, "consistent": CONSISTENT, "fd": FD}
-SOLVERS = {"basic": BASIC, "cg": CG, "minres": MINRES, "eyre_milton": EYRE_MILTON}
+SOLVERS = {"basic": BASIC, "cg": CG, "minres": MINRES, "eyre_milton": EYRE_MILTON, "symmlq": SYMMLQ}
 PHYSICS = {"scalar": SCALAR, "elastic": ELASTIC}
 PRECISION = {"fp64": FP64, "mixed": MIXED}
 

@@ -1,4 +1,4 @@
-"""GPU parity of the MINRES and Eyre--Milton solvers.
+"""GPU parity of the MINRES, SYMMLQ and Eyre--Milton solvers.
 
 * MINRES (FP64, either context precision) on the symmetric indefinite
   systems of an A0 between the phases: the centred disk at a0 = 5.5 against
@@ -6,6 +6,11 @@
   disk and an elastic indefinite medium against the oracle's MINRES, batched
   loads converging at different steps; and the 128^3 Boolean medium (SPD)
   against its stored oracle A*.
+* SYMMLQ (FP64, either context precision) on the same indefinite systems:
+  the disk against the stored A*, the filtered disk and the elastic medium
+  against the oracle's SYMMLQ (iteration counts, A*, and the solution field
+  after a fixed number of steps, where both return the CG point of the last
+  step), zero loads and the iteration limit.
 * Eyre--Milton at the geometric-mean reference: disk against the stored A*,
   anisotropic scalar phases and reference, elasticity, per-voxel moduli, and
   a context that switches between the basic scheme and Eyre--Milton.
@@ -94,6 +99,71 @@ def test_minres_maxit_and_zero_load(lsh):
     assert rep["load_status"] == [lsh.MAXIT, lsh.OK]
     assert rep["iterations"][0] == 5 and rep["iterations"][1] == 0
     assert np.all(ctx.effective()[1] == 0.0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_symmlq_indefinite_disk_against_golden(lsh, precision):
+    gold = json.load(open(os.path.join(GOLDEN, "disk2d_n64_truncated.json")))
+    w = I.disk_workload(64, "truncated")
+    ctx = context(lsh, w.phase, w.moduli, w.A0, "scalar", "truncated", precision=precision, max_loads=2)
+    rep = ctx.solve(w.loads, "symmlq", tol=1e-12, maxit=2000)
+    assert rep["status"] == lsh.OK and max(rep["rel_residual"]) <= 1e-11
+    assert rel_max_err(ctx.effective().T, gold["A_star"]) <= 1e-10
+
+
+def test_symmlq_filtered_indefinite_matches_oracle_symmlq(lsh):
+    w = I.disk_workload(32, "filtered")
+    pb = problem(w.phase, w.moduli, w.A0, "scalar", "filtered")
+    loads = np.array([[1.0, 0.0], [0.6, -0.8]])
+    hist = []
+    solvers.symmlq(pb, loads[0], tol=1e-10, maxit=2000, history=hist)
+    ctx = context(lsh, w.phase, w.moduli, w.A0, "scalar", "filtered", max_loads=2)
+    rep = ctx.solve(loads, "symmlq", tol=1e-10, maxit=2000)
+    assert rep["status"] == lsh.OK
+    assert abs(rep["iterations"][0] - len(hist)) <= 1
+    assert rel_max_err(ctx.effective().T, _oracle_A(pb, loads, solvers.symmlq)) <= 1e-9
+
+
+@pytest.mark.parametrize("steps", [1, 2, 7])
+def test_symmlq_fixed_steps_match_the_oracle_field(lsh, steps):
+    # after a fixed number of steps both return the CG point of the last step
+    w = I.disk_workload(32, "filtered")
+    pb = problem(w.phase, w.moduli, w.A0, "scalar", "filtered")
+    loads = np.array([[1.0, 0.3], [0.0, 1.0]])
+    ctx = context(lsh, w.phase, w.moduli, w.A0, "scalar", "filtered", max_loads=2)
+    rep = ctx.solve(loads, "symmlq", tol=1e-14, maxit=steps)
+    assert rep["status"] == lsh.MAXIT and rep["iterations"] == [steps, steps]
+    for l in range(2):
+        ref = solvers.symmlq(pb, loads[l], tol=0.0, maxit=steps)["tau"]
+        out = ctx.field(l, "tau", device=False)
+        assert rel_max_err(out, ref) <= 1e-11
+
+
+def test_symmlq_elastic_indefinite_matches_oracle(lsh):
+    ph, mods, A0 = _elastic_indefinite()
+    pb = problem(ph, mods, A0, "elastic", "filtered")
+    loads = np.eye(6)[[0, 3, 5]]
+    ref = _oracle_A(pb, loads, solvers.symmlq)
+    for precision in ("fp64", "mixed"):
+        ctx = context(lsh, ph, mods, A0, "elastic", "filtered", precision=precision, max_loads=3)
+        rep = ctx.solve(loads, "symmlq", tol=1e-12, maxit=3000)
+        assert rep["status"] == lsh.OK
+        assert rel_max_err(ctx.effective().T, ref) <= 1e-10
+        assert max(rep["rel_residual"]) <= 1e-11
+
+
+def test_symmlq_zero_load_and_definite_system(lsh):
+    # a zero load stays at zero; on a definite system (A0 softer than both
+    # phases) SYMMLQ reaches the CG solution
+    w = I.disk_workload(32, "filtered")
+    A0 = 0.5 * np.eye(2)
+    ctx = context(lsh, w.phase, w.moduli, A0, "scalar", "filtered", max_loads=2)
+    rep = ctx.solve(np.array([[1.0, 0.0], [0.0, 0.0]]), "symmlq", tol=1e-12, maxit=2000)
+    assert rep["load_status"] == [lsh.OK, lsh.OK] and rep["iterations"][1] == 0
+    assert np.all(ctx.effective()[1] == 0.0)
+    A_sy = ctx.effective()[0].copy()
+    rep = ctx.solve(np.array([[1.0, 0.0], [0.0, 0.0]]), "cg", tol=1e-12, maxit=2000)
+    assert rel_max_err(ctx.effective()[0], A_sy) <= 1e-10
 
 
 def test_eyre_milton_disk_against_golden_and_oracle(lsh):
