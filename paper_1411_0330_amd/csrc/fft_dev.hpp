@@ -20,6 +20,23 @@ template <> struct Vec2<float> { using type = float2; };
 template <> struct Vec2<double> { using type = double2; };
 template <typename T> using cpx = typename Vec2<T>::type;
 
+// Streaming (non-temporal) global access of one complex value: fields and
+// spectra are touched once per pass and come back from HBM in the next one.
+template <typename V>
+__device__ __forceinline__ V ld_stream(const V* p) {
+  using T = std::remove_cv_t<std::remove_reference_t<decltype(V{}.x)>>;
+  typedef T N __attribute__((ext_vector_type(2)));
+  const N v = __builtin_nontemporal_load(reinterpret_cast<const N*>(p));
+  return V{v.x, v.y};
+}
+template <typename V>
+__device__ __forceinline__ void st_stream(V* p, const V& v) {
+  using T = std::remove_cv_t<std::remove_reference_t<decltype(V{}.x)>>;
+  typedef T N __attribute__((ext_vector_type(2)));
+  const N w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<N*>(p));
+}
+
 template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
 template <typename V> __device__ __forceinline__ V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
 template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
