@@ -180,6 +180,24 @@ lsh_status lsh_solver_buffer_bytes(const lsh_ctx* ctx, int solver, size_t* bytes
 lsh_status lsh_bind_solver_buffer(lsh_ctx* ctx, void* dev_ptr, size_t bytes);
 
 /*
+ * Initial guess tau_0 for load slot `load` (0..max_loads-1) of the next
+ * lsh_solve (warm start; the default is tau_0 = 0).  tau: c x grid field,
+ * component-major with x fastest (the lsh_get_field layout), FP64 or FP32
+ * (dtype), host or device memory (mem; device memory is read in stream order
+ * and may be reused after the call returns).  It is copied into the FP64
+ * solution slot of that load, so the fields of the previous solve are no
+ * longer available (lsh_get_field returns LSH_ESTATE until the next solve).
+ * Values outside I0 are ignored (tau vanishes there).  tau = NULL clears the
+ * guess of that slot.  A guess applies to the next lsh_solve only.  The solve
+ * then starts from r_0 = b - L tau_0 (one extra FP64 application) with the
+ * same stopping rule ||b - L tau|| <= tol ||b||, so a guess that already meets
+ * it takes no iteration; the fixed-point schemes start their iteration at
+ * tau_0, and the mixed-precision solve begins with an FP64 refinement step.
+ * Errors: LSH_EINVAL (slot, dtype, mem), LSH_ESTATE (no workspace bound).
+ */
+lsh_status lsh_set_initial_guess(lsh_ctx* ctx, int load, const void* tau, int dtype, int mem);
+
+/*
  * Solve eq. (13) for nload (1..max_loads) macroscopic loads p_l (host,
  * nload x c row-major FP64; Mandel in elasticity), starting from tau = 0,
  * until ||b - L tau||_2 <= tol ||b||_2 with b = p on I0 (mixed precision: the

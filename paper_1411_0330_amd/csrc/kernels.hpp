@@ -53,7 +53,7 @@ enum : int { XF_PLAIN = 0, XF_CG = 1, XF_IRX = 2 };
 enum : int { XI_APPLY = 0, XI_CG = 1, XI_BASIC = 2, XI_IRRES = 3, XI_RESNORM = 4, XI_STRAIN = 5, XI_EM = 6,
               XI_CGR = 7 };
 enum : int { Z_GAMMA = 0, Z_FWD = 1 };
-enum : int { SC_INIT = 0, SC_ALPHA = 1, SC_BETA = 2, SC_BASIC = 3, SC_OUTER = 4, SC_SUM = 5 };
+enum : int { SC_INIT = 0, SC_ALPHA = 1, SC_BETA = 2, SC_BASIC = 3, SC_OUTER = 4, SC_SUM = 5, SC_INITG = 6 };
 
 constexpr int kMaxPhases = 32;
 constexpr int kStatusOk = 0, kStatusBreakdown = -5, kStatusNumeric = -6;
@@ -1153,6 +1153,62 @@ __global__ __launch_bounds__(256) void k_cginit(const Geo g, T* __restrict__ x, 
   }
   const double s = block_sum<256>(part, red);
   if (threadIdx.x == 0) partials[(long long)l * pstride + blockIdx.x] = s;
+}
+
+// Initial guesses (flag per load in gflag): the guess is kept on I0 and
+// zeroed elsewhere; the other loads start from x = 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_guessmask(const Geo g, T* __restrict__ x, const uint8_t* __restrict__ phase,
+                                                   const uint8_t* __restrict__ i0, const double* __restrict__ vcoef,
+                                                   const uint8_t* __restrict__ gflag) {
+  const int l = blockIdx.y;
+  const long long F = field_elems(g);
+  const bool guessed = gflag[l] != 0;
+  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kEwUnroll; ++u) {
+    const long long e = b0 + (long long)u * 256;
+    if (e < F) {
+      const long long vox = e % g.nvox;
+      const bool inside = vcoef != nullptr ? vcoef[vox] != 0.0 : i0[phase[vox]] != 0;
+      T* xe = x + (long long)l * F + e;
+      *xe = (guessed && inside) ? *xe : T(0);
+    }
+  }
+}
+
+// r = b - q with q = L x0 on the guessed loads, r = b on the others (b = p on
+// I0); partial ||b||^2 into group l and ||r||^2 into group ngroups + l.
+template <typename T>
+__global__ __launch_bounds__(256) void k_guessinit(const Geo g, const T* __restrict__ q, T* __restrict__ r,
+                                                   const uint8_t* __restrict__ phase, const uint8_t* __restrict__ i0,
+                                                   const double* __restrict__ vcoef, const double* __restrict__ loads,
+                                                   const uint8_t* __restrict__ gflag, double* __restrict__ partials,
+                                                   const int pstride, const int ngroups) {
+  __shared__ double red[4];
+  const int l = blockIdx.y;
+  const long long F = field_elems(g);
+  const bool guessed = gflag[l] != 0;
+  double pb = 0.0, pr = 0.0;
+  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kEwUnroll; ++u) {
+    const long long e = b0 + (long long)u * 256;
+    if (e < F) {
+      const int j = (int)(e / g.nvox);
+      const long long vox = e - (long long)j * g.nvox;
+      const bool inside = vcoef != nullptr ? vcoef[vox] != 0.0 : i0[phase[vox]] != 0;
+      const T bv = inside ? static_cast<T>(loads[l * g.c + j]) : T(0);
+      const T rv = guessed ? bv - q[(long long)l * F + e] : bv;
+      r[(long long)l * F + e] = rv;
+      pb += (double)bv * bv;
+      pr += (double)rv * rv;
+    }
+  }
+  const double sb = block_sum<256>(pb, red);
+  if (threadIdx.x == 0) partials[(long long)l * pstride + blockIdx.x] = sb;
+  const double sr = block_sum<256>(pr, red);
+  if (threadIdx.x == 0) partials[(long long)(ngroups + l) * pstride + blockIdx.x] = sr;
 }
 
 // d = 0 and partial ||r||^2 for the loads still refined (inner solve start)

@@ -164,11 +164,15 @@ struct lsh_ctx {
   size_t ws_need = 0, ws_size = 0;
   struct {
     size_t x64, r64, p64, d32, r32, p32, s64m, s64n, s32m, s32n, phase, i0, ptab64, ptab32, vc64, vc32, tw64, tw32,
-        wt64, wt32, loads, wgrad, st_out, st_in, mstate, partials, sums, end;
+        wt64, wt32, loads, wgrad, st_out, st_in, mstate, guess, partials, sums, end;
   } off{};
   long long pstride = 0, nsums = 0;
   int twoff[3] = {0, 0, 0};
   int wstride = 0;
+
+  // initial guesses for the next solve (per load; the guess itself is in x64),
+  // and the flags of the solve in progress (staging of their upload)
+  std::vector<uint8_t> h_guess, h_guess_up;
 
   // host staging kept alive across asynchronous copies
   std::vector<double> h_ptab64, h_loads;
@@ -327,6 +331,8 @@ void compute_layout(lsh_ctx* ctx) {
   ctx->off.st_out = take(sizeof(LoadState) * L);
   ctx->off.st_in = take(sizeof(LoadState) * L);
   ctx->off.mstate = take(sizeof(MinresState) * L);
+  ctx->off.guess = take(L);
+  ctx->h_guess.assign(L, 0);
   // partial sums: the largest grid of any reducing kernel, per group
   // (the fused CG step writes the x pass's and the z pass's partials side by side)
   long long pmax = xinv_blocks(ctx->geo, 2) + zg_blocks_max<float>(ctx->geo);
@@ -784,6 +790,45 @@ lsh_status cg_init(lsh_ctx* ctx, int nload, T* x, T* r, LoadState* st, double to
   return scal(ctx, SC_INIT, nload, nb, st, tol);
 }
 
+// flags of the solve in progress (lsh_solve stages them in h_guess_up)
+bool any_guess(const lsh_ctx* ctx, int nload) {
+  for (int l = 0; l < nload && l < (int)ctx->h_guess_up.size(); ++l)
+    if (ctx->h_guess_up[l]) return true;
+  return false;
+}
+
+// Start of an FP64 solve on x (the solution slots).  Without initial guesses:
+// cg_init (x = 0, r = b).  With them (flags uploaded to off.guess): the
+// guesses are masked to I0 and the other loads zeroed; with r given, one
+// operator application q = L x gives r = b - q, and the solver scalars start
+// from ||r||^2 with the tolerance relative to ||b|| (SC_INITG); without r,
+// only ||b||^2 is formed and x keeps the guesses.
+lsh_status guess_init(lsh_ctx* ctx, int nload, double* x, double* r, LoadState* st, double tol) {
+  if (!any_guess(ctx, nload)) return cg_init<double>(ctx, nload, x, r, st, tol);
+  const Geo& g = ctx->geo;
+  const int nb = (int)((ctx->F + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
+  const uint8_t* gflag = ctx->ptr<uint8_t>(ctx->off.guess);
+  {
+    Scope sc(ctx, K_INIT);
+    hipLaunchKernelGGL((k_guessmask<double>), dim3(nb, nload), dim3(256), 0, ctx->stream, g, x,
+                       ctx->ptr<uint8_t>(ctx->off.phase), ctx->ptr<uint8_t>(ctx->off.i0), Sel<double>::vc(ctx), gflag);
+    STCHK(check_launch(ctx, 0, "guess mask"));
+  }
+  if (r == nullptr) return cg_init<double>(ctx, nload, nullptr, nullptr, st, tol);
+  STCHK(forward_part<double>(ctx, 0, nload, XF_PLAIN, x, nullptr, nullptr, nullptr, nullptr, true));
+  double* q = reinterpret_cast<double*>(Sel<double>::sm(ctx));
+  STCHK(inverse_x<double>(ctx, 0, nload, XI_APPLY, x, q, nullptr, nullptr, nullptr, nullptr));
+  {
+    Scope sc(ctx, K_INIT);
+    hipLaunchKernelGGL((k_guessinit<double>), dim3(nb, nload), dim3(256), 0, ctx->stream, g, q, r,
+                       ctx->ptr<uint8_t>(ctx->off.phase), ctx->ptr<uint8_t>(ctx->off.i0), Sel<double>::vc(ctx),
+                       ctx->ptr<double>(ctx->off.loads), gflag, ctx->ptr<double>(ctx->off.partials),
+                       (int)ctx->pstride, nload);
+    STCHK(check_launch(ctx, 0, "guess init"));
+  }
+  return scal(ctx, SC_INITG, nload, nb, st, tol);
+}
+
 template <typename T>
 lsh_status cg_update(lsh_ctx* ctx, int nload, T* r, const T* q, LoadState* st) {
   const long long nvec = ctx->F / Vec16<T>::n;
@@ -965,8 +1010,8 @@ lsh_status mr_loop(lsh_ctx* ctx, int nload, double tol, int maxit, std::vector<L
   LoadState* st = ctx->ptr<LoadState>(ctx->off.st_out);
   MinresState* ms = ctx->ptr<MinresState>(ctx->off.mstate);
   double* parts = ctx->ptr<double>(ctx->off.partials);
-  // x = 0, v = b and ||b||^2; then v = b/||b|| and the rotation state
-  STCHK(cg_init<double>(ctx, nload, x, v, st, tol));
+  // x = 0 (or the guess), v = b - L x and its norm; then v = r_0/||r_0|| and the rotation state
+  STCHK(guess_init(ctx, nload, x, v, st, tol));
   {
     Scope sc(ctx, K_INIT);
     hipLaunchKernelGGL(k_mr_start, dim3((unsigned)((F + 255) / 256), nload), dim3(256), 0, ctx->stream, F, v, vp, w1,
@@ -1040,7 +1085,7 @@ lsh_status sy_loop(lsh_ctx* ctx, int nload, double tol, int maxit, std::vector<L
   LoadState* st = ctx->ptr<LoadState>(ctx->off.st_out);
   MinresState* ms = ctx->ptr<MinresState>(ctx->off.mstate);
   double* parts = ctx->ptr<double>(ctx->off.partials);
-  STCHK(cg_init<double>(ctx, nload, x, v, st, tol));   // x = 0, v = b, ||b||^2
+  STCHK(guess_init(ctx, nload, x, v, st, tol));   // x = 0 (or the guess), v = b - L x, norms
   {
     Scope sc(ctx, K_INIT);
     hipLaunchKernelGGL(k_sy_start, dim3((unsigned)((F + 255) / 256), nload), dim3(256), 0, ctx->stream, F, v, vp,
@@ -1638,6 +1683,11 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
   ctx->h_loads = ctx->last_loads;
   HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.loads, ctx->h_loads.data(), ctx->h_loads.size() * sizeof(double),
                         hipMemcpyHostToDevice, ctx->stream));
+  // initial guesses apply to this solve only
+  ctx->h_guess_up.assign(ctx->h_guess.begin(), ctx->h_guess.begin() + nload);
+  std::fill(ctx->h_guess.begin(), ctx->h_guess.end(), 0);
+  HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.guess, ctx->h_guess_up.data(), (size_t)nload, hipMemcpyHostToDevice,
+                        ctx->stream));
 
   LoadState* sto = ctx->ptr<LoadState>(ctx->off.st_out);
   LoadState* sti = ctx->ptr<LoadState>(ctx->off.st_in);
@@ -1650,7 +1700,7 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
   std::vector<double> res2(nload, 0.0), bb(nload, 0.0);
 
   if (solver == LSH_SOLVER_BASIC || solver == LSH_SOLVER_EYRE_MILTON) {
-    STCHK(cg_init<double>(ctx, nload, x64, nullptr, sto, tol));
+    STCHK(guess_init(ctx, nload, x64, nullptr, sto, tol));   // tau_0 = 0 or the guess
     STCHK(basic_loop(ctx, nload, x64, sto, ctx->off.st_out, maxit, hst,
                      solver == LSH_SOLVER_BASIC ? XI_BASIC : XI_EM));
     STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
@@ -1662,7 +1712,7 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
   } else if (ctx->precision == LSH_FP64) {
     double* r = ctx->ptr<double>(ctx->off.r64);
     double* p = ctx->ptr<double>(ctx->off.p64);
-    STCHK(cg_init<double>(ctx, nload, x64, r, sto, tol));
+    STCHK(guess_init(ctx, nload, x64, r, sto, tol));
     STCHK(cg_loop<double>(ctx, nload, x64, r, p, sto, ctx->off.st_out, maxit, hst));
     STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
     for (int l = 0; l < nload; ++l) iters[l] = hst[l].iters, apps64 += hst[l].iters;
@@ -1671,22 +1721,28 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
     float* d = ctx->ptr<float>(ctx->off.d32);
     float* r = ctx->ptr<float>(ctx->off.r32);
     float* p = ctx->ptr<float>(ctx->off.p32);
-    STCHK(cg_init<double>(ctx, nload, x64, nullptr, sto, tol));  // x64 = 0, outer ||b||^2
-    STCHK(cg_init<float>(ctx, nload, d, r, sti, 1e-4));          // d = 0, r = b
+    STCHK(guess_init(ctx, nload, x64, nullptr, sto, tol));  // x64 = 0 or the guess, outer ||b||^2
+    STCHK(cg_init<float>(ctx, nload, d, r, sti, 1e-4));      // d = 0, r = b
     STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
     double eta = 1e-4;
     int budget = maxit;
+    // from initial guesses the first pass is the refinement alone (d = 0):
+    // r = b - L x64 in FP64, then the inner solve restarts from it
+    bool refine_first = any_guess(ctx, nload);
     while (true) {
-      // inner FP32 solve, then refresh the residual in FP64 (x64 += d inside)
-      STCHK(cg_loop<float>(ctx, nload, d, r, p, sti, ctx->off.st_in, budget, hin));
-      STCHK(read_states(ctx, ctx->off.st_in, nload, hin));
-      int used = 0;
-      for (int l = 0; l < nload; ++l) {
-        iters[l] += hin[l].iters;
-        apps32 += hin[l].iters;
-        used = std::max(used, hin[l].iters);
+      if (!refine_first) {
+        // inner FP32 solve, then refresh the residual in FP64 (x64 += d inside)
+        STCHK(cg_loop<float>(ctx, nload, d, r, p, sti, ctx->off.st_in, budget, hin));
+        STCHK(read_states(ctx, ctx->off.st_in, nload, hin));
+        int used = 0;
+        for (int l = 0; l < nload; ++l) {
+          iters[l] += hin[l].iters;
+          apps32 += hin[l].iters;
+          used = std::max(used, hin[l].iters);
+        }
+        budget -= used;
       }
-      budget -= used;
+      refine_first = false;
       ctx->nact = 0;
       for (auto& sv : hst) ctx->nact += sv.active != 0;
       STCHK(forward_part<double>(ctx, 0, nload, XF_IRX, nullptr, x64, nullptr, d, sto, true));
@@ -1813,6 +1869,42 @@ static lsh_status copy_field_out(lsh_ctx* ctx, const double* src, long long n, v
     float* f = static_cast<float*>(dst);
     for (long long i = 0; i < n; ++i) f[i] = (float)h[(size_t)i];
   }
+  return LSH_OK;
+}
+
+lsh_status lsh_set_initial_guess(lsh_ctx* ctx, int load, const void* tau, int dtype, int mem) {
+  if (!ctx) return LSH_EINVAL;
+  if (load < 0 || load >= ctx->max_loads) return fail(ctx, LSH_EINVAL, "load out of range");
+  if (!tau) {
+    ctx->h_guess[load] = 0;
+    return LSH_OK;
+  }
+  if (dtype != LSH_F64 && dtype != LSH_F32) return fail(ctx, LSH_EINVAL, "bad dtype");
+  if (mem != LSH_HOST && mem != LSH_DEVICE) return fail(ctx, LSH_EINVAL, "bad memory space");
+  if (!ctx->ws) return fail(ctx, LSH_ESTATE, "workspace not bound");
+  const long long F = ctx->F;
+  double* x = ctx->ptr<double>(ctx->off.x64) + (long long)load * F;
+  if (mem == LSH_DEVICE) {
+    if (dtype == LSH_F64) {
+      HIPCHK(hipMemcpyAsync(x, tau, F * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    } else {
+      Scope sc(ctx, K_COPY);
+      hipLaunchKernelGGL((k_convert<float, double>), dim3((unsigned)((F + 255) / 256)), dim3(256), 0, ctx->stream, F,
+                         static_cast<const float*>(tau), x);
+      STCHK(check_launch(ctx, 0, "convert"));
+    }
+  } else if (dtype == LSH_F64) {
+    HIPCHK(hipMemcpyAsync(x, tau, F * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  } else {
+    std::vector<double> h((size_t)F);
+    const float* f = static_cast<const float*>(tau);
+    for (long long i = 0; i < F; ++i) h[(size_t)i] = (double)f[i];
+    HIPCHK(hipMemcpyAsync(x, h.data(), F * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->h_guess[load] = 1;
+  ctx->have_solution = false;   // the solution slot of this load now holds the guess
   return LSH_OK;
 }
 

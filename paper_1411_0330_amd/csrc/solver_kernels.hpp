@@ -31,7 +31,7 @@ static __global__ __launch_bounds__(256) void k_mr_start(const long long F, doub
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i >= F) return;
   const long long o = (long long)l * F + i;
-  const double sc = st[l].bb > 0.0 ? 1.0 / sqrt(st[l].bb) : 0.0;
+  const double sc = st[l].rr > 0.0 ? 1.0 / sqrt(st[l].rr) : 0.0;
   v[o] *= sc;
   vp[o] = 0.0;
   w1[o] = 0.0;
@@ -119,7 +119,7 @@ static __global__ __launch_bounds__(256) void k_mr_scal(const int mode, const do
     M.alpha = M.beta = M.delta1 = M.eps = 0.0;
     M.c = -1.0;
     M.s = 0.0;
-    M.phi = sqrt(L.bb);
+    M.phi = sqrt(L.rr);   // ||r_0|| (= ||b|| from x_0 = 0)
     M.delta2 = M.epsk = M.t = M.inv_beta = 0.0;
     M.gamma2 = 1.0;
     M.apply = 0;
@@ -183,7 +183,7 @@ static __global__ __launch_bounds__(256) void k_sy_start(const long long F, doub
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i >= F) return;
   const long long o = (long long)l * F + i;
-  const double sc = st[l].bb > 0.0 ? 1.0 / sqrt(st[l].bb) : 0.0;
+  const double sc = st[l].rr > 0.0 ? 1.0 / sqrt(st[l].rr) : 0.0;
   const double vv = v[o] * sc;
   v[o] = vv;
   vp[o] = 0.0;
@@ -211,7 +211,7 @@ static __global__ __launch_bounds__(256) void k_sy_scal(const int mode, const do
     M.c = -1.0;
     M.s = 0.0;
     M.z1 = M.z2 = M.zbar = M.wc = M.ws = M.t = M.inv_beta = 0.0;
-    M.first = sqrt(L.bb);
+    M.first = sqrt(L.rr);   // ||r_0|| (= ||b|| from x_0 = 0)
     M.apply = SY_NONE;
     return;
   }
@@ -318,17 +318,32 @@ static __global__ __launch_bounds__(256) void k_scal(const int mode, const doubl
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x != 0) return;
   const double S = red[0];
+  double S2 = S;
+  if (mode == SC_INITG) {
+    // ||r_0||^2 of a start from initial guesses, group ngroups + grp
+    __syncthreads();
+    double s2 = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) s2 += partials[(long long)(gridDim.x + grp) * pstride + i];
+    red[threadIdx.x] = s2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    S2 = red[0];
+  }
+  if (threadIdx.x != 0) return;
   if (mode == SC_SUM) {
     sums[grp] = S;
     return;
   }
   LoadState& L = st[grp];
-  if (mode == SC_INIT) {
+  if (mode == SC_INIT || mode == SC_INITG) {
+    // SC_INITG: S = ||b||^2 (tolerance), S2 = ||b - L x_0||^2 (start)
     L.bb = S;
-    L.rr = S;
-    L.res2 = S;
+    L.rr = S2;
+    L.res2 = S2;
     L.tol2 = tol * tol * S;
     L.alpha = 0.0;
     L.beta = 0.0;
@@ -336,8 +351,10 @@ static __global__ __launch_bounds__(256) void k_scal(const int mode, const doubl
     L.iters = 0;
     L.first = 1;
     L.pending = 0;
-    L.status = isfinite(S) ? kStatusOk : kStatusNumeric;
-    L.active = (S > 0.0 && isfinite(S)) ? 1 : 0;
+    const bool fin = isfinite(S) && isfinite(S2);
+    L.status = fin ? kStatusOk : kStatusNumeric;
+    // a guess that already meets the tolerance needs no iteration
+    L.active = (S > 0.0 && fin && (mode == SC_INIT || S2 > L.tol2)) ? 1 : 0;
     return;
   }
   if (!L.active) return;

@@ -64,6 +64,7 @@ _SIGS = {
     "lsh_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_double, C.c_int,
                             C.POINTER(LoadReport), C.POINTER(SolveReport)]),
     "lsh_get_field": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int]),
+    "lsh_set_initial_guess": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_int]),
     "lsh_get_effective": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "lsh_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "lsh_forward_dft": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
@@ -288,6 +289,29 @@ class Context:
             "outer_iterations": summ.outer_iterations,
             "seconds": summ.seconds,
         }
+
+    def set_initial_guess(self, load, tau):
+        """Warm start of the next solve for load slot `load`
+        (lsh_set_initial_guess): tau of shape (c, *shape), a torch tensor on
+        the device or a host array, float64 or float32; None clears it."""
+        if tau is None:
+            return self._check(self.lib.lsh_set_initial_guess(self.h, int(load), None, F64, HOST))
+        if hasattr(tau, "data_ptr"):
+            import torch
+            assert tau.dtype in (torch.float64, torch.float32)
+            keep = tau.contiguous()
+            code = F64 if keep.dtype == torch.float64 else F32
+            mem = DEVICE if keep.is_cuda else HOST
+            ptr = keep.data_ptr()
+        else:
+            keep = np.ascontiguousarray(tau)
+            assert keep.dtype in (np.float64, np.float32)
+            code = F64 if keep.dtype == np.float64 else F32
+            mem = HOST
+            ptr = keep.ctypes.data
+        if tuple(keep.shape) != (self.c,) + self.shape:
+            raise ValueError(f"expected a guess of shape {(self.c,) + self.shape}, got {tuple(keep.shape)}")
+        return self._check(self.lib.lsh_set_initial_guess(self.h, int(load), C.c_void_p(ptr), code, mem))
 
     def effective(self):
         """(nload, c) array: row l is A0 p_l + <tau_l>."""
