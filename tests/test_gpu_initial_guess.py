@@ -125,3 +125,20 @@ def test_guess_errors(lsh):
     with pytest.raises(lsh.LshError) as e:
         ctx.field(0, "tau", device=False)
     assert e.value.status == lsh.ESTATE
+
+
+@pytest.mark.parametrize("solver,precision", [("cg", "fp64"), ("cg", "mixed"), ("symmlq", "fp64")])
+def test_resume_after_the_iteration_limit(lsh, solver, precision):
+    # checkpoint / resume: stop at maxit, read tau, restart from it
+    ph, mods, A0 = _disk()
+    pb = problem(ph, mods, A0, "scalar", "filtered")
+    exact = [solvers.cg(pb, p, tol=1e-13, maxit=5000)["tau"] for p in LOADS]
+    ctx = context(lsh, ph, mods, A0, "scalar", "filtered", precision=precision, max_loads=2)
+    first = ctx.solve(LOADS, solver, tol=1e-10, maxit=12)
+    assert first["status"] == lsh.MAXIT
+    taus = [ctx.field(l, "tau", device=False) for l in range(2)]
+    for l in range(2):
+        ctx.set_initial_guess(l, taus[l])
+    rest = ctx.solve(LOADS, solver, tol=1e-10, maxit=5000)
+    assert rest["status"] == lsh.OK and max(rest["rel_residual"]) <= 1e-10
+    assert rel_max_err(ctx.effective().T, effective.effective_matrix(A0, LOADS, exact)) <= 1e-8
