@@ -104,6 +104,16 @@ constexpr int line_share() {
   return (TX * 2 * (int)sizeof(T) < 128) ? 128 / (TX * 2 * (int)sizeof(T)) : 1;
 }
 
+// Requested waves per SIMD of the fused x pass: the FP32 six-component
+// 128-point instance (the mixed elastic 256^3 path) fits 5 waves in 93 VGPRs
+// without spilling, against 4 at the allocator's own 100 (2.64 -> 2.58 ms);
+// 1 leaves every other instance unconstrained.  (The matching C2R instance
+// spills at 4 waves and measured slower, so it keeps its allocation.)
+template <typename T, int MX, int P, int C>
+constexpr int xfwdc_waves() {
+  return (sizeof(T) == 4 && C == 6 && MX == 128 && P == 4) ? 5 : 1;
+}
+
 // ----------------------------------------------------------------------------
 // x forward: R2C along rows
 // ----------------------------------------------------------------------------
@@ -326,7 +336,7 @@ struct XfwdcArgs {
 };
 
 template <typename T, int MX, int P, int C>
-__global__ __launch_bounds__(256) void k_xfwdc(const XfwdcArgs<T> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(xfwdc_waves<T, MX, P, C>()))) void k_xfwdc(const XfwdcArgs<T> a) {
   constexpr int TR = MX / P;
   constexpr int RPW = 256 / TR;
   constexpr int TABW = 2 * C * C + 5;   // phase table row, see phase_row
