@@ -1166,14 +1166,17 @@ __global__ __launch_bounds__(256) void k_cginit(const Geo g, T* __restrict__ x, 
 }
 
 // Initial guesses (flag per load in gflag): the guess is kept on I0 and
-// zeroed elsewhere; the other loads start from x = 0.
+// zeroed elsewhere; the other loads, and zero loads (whose solution is 0 and
+// which never iterate), start from x = 0.
 template <typename T>
 __global__ __launch_bounds__(256) void k_guessmask(const Geo g, T* __restrict__ x, const uint8_t* __restrict__ phase,
                                                    const uint8_t* __restrict__ i0, const double* __restrict__ vcoef,
-                                                   const uint8_t* __restrict__ gflag) {
+                                                   const uint8_t* __restrict__ gflag, const double* __restrict__ loads) {
   const int l = blockIdx.y;
   const long long F = field_elems(g);
-  const bool guessed = gflag[l] != 0;
+  bool nonzero = false;
+  for (int j = 0; j < g.c; ++j) nonzero |= loads[l * g.c + j] != 0.0;
+  const bool guessed = gflag[l] != 0 && nonzero;
   const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
 #pragma unroll
   for (int u = 0; u < kEwUnroll; ++u) {

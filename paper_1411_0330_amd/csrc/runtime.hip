@@ -811,7 +811,8 @@ lsh_status guess_init(lsh_ctx* ctx, int nload, double* x, double* r, LoadState* 
   {
     Scope sc(ctx, K_INIT);
     hipLaunchKernelGGL((k_guessmask<double>), dim3(nb, nload), dim3(256), 0, ctx->stream, g, x,
-                       ctx->ptr<uint8_t>(ctx->off.phase), ctx->ptr<uint8_t>(ctx->off.i0), Sel<double>::vc(ctx), gflag);
+                       ctx->ptr<uint8_t>(ctx->off.phase), ctx->ptr<uint8_t>(ctx->off.i0), Sel<double>::vc(ctx), gflag,
+                       ctx->ptr<double>(ctx->off.loads));
     STCHK(check_launch(ctx, 0, "guess mask"));
   }
   if (r == nullptr) return cg_init<double>(ctx, nload, nullptr, nullptr, st, tol);

@@ -142,3 +142,17 @@ def test_resume_after_the_iteration_limit(lsh, solver, precision):
     rest = ctx.solve(LOADS, solver, tol=1e-10, maxit=5000)
     assert rest["status"] == lsh.OK and max(rest["rel_residual"]) <= 1e-10
     assert rel_max_err(ctx.effective().T, effective.effective_matrix(A0, LOADS, exact)) <= 1e-8
+
+
+@pytest.mark.parametrize("solver", ["cg", "symmlq", "basic"])
+def test_zero_load_ignores_its_guess(lsh, solver):
+    # the solution of a zero load is zero whatever the guess
+    ph, mods, A0 = _disk()
+    ctx = context(lsh, ph, mods, A0, "scalar", "filtered", max_loads=2)
+    ctx.solve(LOADS, solver, tol=1e-10, maxit=5000)
+    tau = ctx.field(1, "tau", device=False)
+    ctx.set_initial_guess(1, tau)
+    rep = ctx.solve(np.array([[1.0, 0.0], [0.0, 0.0]]), solver, tol=1e-10, maxit=5000)
+    assert rep["load_status"][1] == lsh.OK and rep["iterations"][1] == 0
+    assert np.all(ctx.field(1, "tau", device=False) == 0.0)
+    assert np.all(ctx.effective()[1] == 0.0)
