@@ -275,8 +275,8 @@ def bench_gradient(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on a single GPU; --gpus must be 1 "
-              "(the multi-GPU slab decomposition is a design note, not built).", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU; --gpus must be 1 "
+              "(a multi-GPU slab decomposition is designed but not implemented).", file=sys.stderr)
         sys.exit(2)
     if args.ensemble:
         return bench_ensemble(args)
