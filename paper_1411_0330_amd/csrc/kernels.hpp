@@ -125,6 +125,7 @@ __global__ __launch_bounds__(256) void k_xfwd(const Geo g, const int mode, const
                                               const LoadState* __restrict__ st) {
   constexpr int TR = MX / P;
   constexpr int RPW = 256 / TR;
+  constexpr int SEG = TR * (int)sizeof(cpx<T>);   // contiguous bytes per access instruction
   __shared__ cpx<T> lds[RPW * MX];
   __shared__ cpx<T> twl[2 * MX];
   const int l = blockIdx.y;
@@ -152,18 +153,18 @@ __global__ __launch_bounds__(256) void k_xfwd(const Geo g, const int mode, const
       const int n = t + TR * i;
       cpx<T> pv{0, 0};
       if (valid) {
-        const cpx<T> rv = ld_stream(r2 + n);
+        const cpx<T> rv = ld_seg<SEG>(r2 + n);
         if (first) {
           pv = rv;
         } else {
-          const cpx<T> po = ld_stream(p2 + n);
+          const cpx<T> po = ld_seg<SEG>(p2 + n);
           if (pend) {
-            const cpx<T> xo = ld_stream(x2 + n);
-            st_stream(x2 + n, cpx<T>{xo.x + alpha * po.x, xo.y + alpha * po.y});
+            const cpx<T> xo = ld_seg<SEG>(x2 + n);
+            st_seg<SEG>(x2 + n, cpx<T>{xo.x + alpha * po.x, xo.y + alpha * po.y});
           }
           pv = cpx<T>{rv.x + beta * po.x, rv.y + beta * po.y};
         }
-        st_stream(p2 + n, pv);
+        st_seg<SEG>(p2 + n, pv);
       }
       v[i] = pv;
     }
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(256) void k_xfwd(const Geo g, const int mode, const
   } else {
     const cpx<T>* s2 = reinterpret_cast<const cpx<T>*>(src + roff);
 #pragma unroll
-    for (int i = 0; i < P; ++i) v[i] = valid ? ld_stream(s2 + t + TR * i) : cpx<T>{0, 0};
+    for (int i = 0; i < P; ++i) v[i] = valid ? ld_seg<SEG>(s2 + t + TR * i) : cpx<T>{0, 0};
   }
 
   cpx<T>* lrow = lds + slot * MX;
@@ -203,15 +204,15 @@ __global__ __launch_bounds__(256) void k_xfwd(const Geo g, const int mode, const
     const cpx<T> z = v[i];
     if (k == 0) {
       if (valid) {
-        st_stream(smain + so, cpx<T>{z.x + z.y, T(0)});
-        st_stream(snyq + (long long)l * nyq_cpx(g) + row, cpx<T>{z.x - z.y, T(0)});
+        st_seg<SEG>(smain + so, cpx<T>{z.x + z.y, T(0)});
+        snyq[(long long)l * nyq_cpx(g) + row] = cpx<T>{z.x - z.y, T(0)};
       }
     } else {
       const cpx<T> zm = lrow[MX - k];
       const cpx<T> a = cpx<T>{z.x + zm.x, z.y - zm.y};   // Z + conj(Zm)
       const cpx<T> b = cpx<T>{z.x - zm.x, z.y + zm.y};   // Z - conj(Zm)
       const cpx<T> wo = cmul(twl[k], mul_neg_i(b));
-      if (valid) st_stream(smain + so + k, cpx<T>{T(0.5) * (a.x + wo.x), T(0.5) * (a.y + wo.y)});
+      if (valid) st_seg<SEG>(smain + so + k, cpx<T>{T(0.5) * (a.x + wo.x), T(0.5) * (a.y + wo.y)});
     }
   }
 }
@@ -339,6 +340,7 @@ template <typename T, int MX, int P, int C>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(xfwdc_waves<T, MX, P, C>()))) void k_xfwdc(const XfwdcArgs<T> a) {
   constexpr int TR = MX / P;
   constexpr int RPW = 256 / TR;
+  constexpr int SEG = TR * (int)sizeof(cpx<T>);   // contiguous bytes per access instruction
   constexpr int TABW = 2 * C * C + 5;   // phase table row, see phase_row
   __shared__ cpx<T> lds[RPW * MX];
   __shared__ cpx<T> twl[2 * MX];
@@ -372,18 +374,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(xfwdc_waves
       const int n = t + TR * i;
       cpx<T> pv{0, 0};
       if (valid) {
-        const cpx<T> rv = ld_stream(r2 + n);
+        const cpx<T> rv = ld_seg<SEG>(r2 + n);
         if (first) {
           pv = rv;
         } else {
-          const cpx<T> po = ld_stream(p2 + n);
+          const cpx<T> po = ld_seg<SEG>(p2 + n);
           if (pend) {
-            const cpx<T> xo = ld_stream(x2 + n);
-            st_stream(x2 + n, cpx<T>{xo.x + alpha * po.x, xo.y + alpha * po.y});
+            const cpx<T> xo = ld_seg<SEG>(x2 + n);
+            st_seg<SEG>(x2 + n, cpx<T>{xo.x + alpha * po.x, xo.y + alpha * po.y});
           }
           pv = cpx<T>{rv.x + beta * po.x, rv.y + beta * po.y};
         }
-        st_stream(p2 + n, pv);
+        st_seg<SEG>(p2 + n, pv);
       }
       v[j][i] = pv;
     }
@@ -439,15 +441,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(xfwdc_waves
       const cpx<T> z = v[j][i];
       if (k == 0) {
         if (valid) {
-          st_stream(a.smain + so, cpx<T>{z.x + z.y, T(0)});
-          st_stream(a.snyq + (long long)l * nyq_cpx(g) + row, cpx<T>{z.x - z.y, T(0)});
+          st_seg<SEG>(a.smain + so, cpx<T>{z.x + z.y, T(0)});
+          a.snyq[(long long)l * nyq_cpx(g) + row] = cpx<T>{z.x - z.y, T(0)};
         }
       } else {
         const cpx<T> zm = lrow[MX - k];
         const cpx<T> s1 = cpx<T>{z.x + zm.x, z.y - zm.y};   // Z + conj(Zm)
         const cpx<T> d1 = cpx<T>{z.x - zm.x, z.y + zm.y};   // Z - conj(Zm)
         const cpx<T> wo = cmul(twl[k], mul_neg_i(d1));
-        if (valid) st_stream(a.smain + so + k, cpx<T>{T(0.5) * (s1.x + wo.x), T(0.5) * (s1.y + wo.y)});
+        if (valid) st_seg<SEG>(a.smain + so + k, cpx<T>{T(0.5) * (s1.x + wo.x), T(0.5) * (s1.y + wo.y)});
       }
     }
   }
@@ -463,6 +465,7 @@ __global__ __launch_bounds__(TX*(NY / P)) void k_y(const Geo g, cpx<T>* __restri
                                                   cpx<T>* __restrict__ snyq, const cpx<T>* __restrict__ twy,
                                                   const LoadState* __restrict__ st, const int main_tiles) {
   constexpr int TY = NY / P;
+  constexpr int SEG = TX * (int)sizeof(cpx<T>);   // contiguous bytes per access instruction
   __shared__ cpx<T> lds[TX * NY];
   __shared__ cpx<T> twl[NY];
   const int l = blockIdx.y;
@@ -499,26 +502,27 @@ __global__ __launch_bounds__(TX*(NY / P)) void k_y(const Geo g, cpx<T>* __restri
   }
   cpx<T> v[P];
 #pragma unroll
-  for (int i = 0; i < P; ++i) v[i] = valid ? ld_stream(base + (long long)(t + TY * i) * es_g) : cpx<T>{0, 0};
+  for (int i = 0; i < P; ++i) v[i] = valid ? ld_seg<SEG>(base + (long long)(t + TY * i) * es_g) : cpx<T>{0, 0};
   __syncthreads();
   fft_pencil<NY, P, DIR, T>(v, t, lp, es_l, twl, 1);
   if (valid) {
 #pragma unroll
-    for (int i = 0; i < P; ++i) st_stream(base + (long long)(t + TY * i) * es_g, v[i]);
+    for (int i = 0; i < P; ++i) st_seg<SEG>(base + (long long)(t + TY * i) * es_g, v[i]);
   }
 }
 
-// Global access of the z passes: streaming in FP64; plain in FP32, where the
-// issue-bound pass measured slower with streaming hints (2.00 against 1.85 ms
-// at 256^3 x 6 elastic loads) while the FP64 pass measured faster.
-template <typename T>
+// Global access of the z passes: streaming in FP64 on whole-line segments;
+// plain in FP32, where the issue-bound pass measured slower with streaming
+// hints (2.00 against 1.85 ms at 256^3 x 6 elastic loads) while the FP64
+// pass measured faster.
+template <typename T, int W>
 __device__ __forceinline__ cpx<T> z_load(const cpx<T>* p) {
-  if constexpr (sizeof(T) == 8) return ld_stream(p);
+  if constexpr (sizeof(T) == 8) return ld_seg<W>(p);
   else return *p;
 }
-template <typename T>
+template <typename T, int W>
 __device__ __forceinline__ void z_store(cpx<T>* p, const cpx<T>& v) {
-  if constexpr (sizeof(T) == 8) st_stream(p, v);
+  if constexpr (sizeof(T) == 8) st_seg<W>(p, v);
   else *p = v;
 }
 
@@ -537,6 +541,7 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
                                                    const LoadState* __restrict__ st, const int main_tiles,
                                                    double* __restrict__ qpart, const int pstride) {
   constexpr int TZ = NZ / P;
+  constexpr int SEG = TX * (int)sizeof(cpx<T>);   // contiguous bytes per access instruction
   constexpr int NT = TX * TZ;
   __shared__ cpx<T> lds[TX * NZ];
   __shared__ cpx<T> twl[NZ];
@@ -577,7 +582,7 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
   for (int j = 0; j < C; ++j)
 #pragma unroll
     for (int i = 0; i < P; ++i)
-      v[j][i] = valid ? z_load<T>(base + j * cstride + (long long)(t + TZ * i) * es_g) : cpx<T>{0, 0};
+      v[j][i] = valid ? z_load<T, SEG>(base + j * cstride + (long long)(t + TZ * i) * es_g) : cpx<T>{0, 0};
   __syncthreads();
   fft_pencil_multi<NZ, P, -1, T, C>(v, t, lp, TX, twl, 1);
   if (zmode == Z_GAMMA) {
@@ -618,7 +623,7 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
 #pragma unroll
     for (int j = 0; j < C; ++j)
 #pragma unroll
-      for (int i = 0; i < P; ++i) z_store<T>(base + j * cstride + (long long)(t + TZ * i) * es_g, v[j][i]);
+      for (int i = 0; i < P; ++i) z_store<T, SEG>(base + j * cstride + (long long)(t + TZ * i) * es_g, v[j][i]);
   }
 }
 
@@ -639,6 +644,7 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zgm(const Geo g, const GreenPar
                                                     const int main_tiles, const int nload,
                                                     double* __restrict__ qpart, const int pstride) {
   constexpr int TZ = NZ / P;
+  constexpr int SEG = TX * (int)sizeof(cpx<T>);   // contiguous bytes per access instruction
   constexpr int NT = TX * TZ;
   constexpr int NE = C * (C + 1) / 2;
   __shared__ cpx<T> lds[TX * NZ];
@@ -697,7 +703,7 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zgm(const Geo g, const GreenPar
 #pragma unroll
     for (int j = 0; j < C; ++j)
 #pragma unroll
-      for (int i = 0; i < P; ++i) dst[j][i] = z_load<T>(b + j * cstride + (long long)(t + TZ * i) * es_g);
+      for (int i = 0; i < P; ++i) dst[j][i] = z_load<T, SEG>(b + j * cstride + (long long)(t + TZ * i) * es_g);
   };
   const double wk = (kx == 0 || kx == g.mx) ? 1.0 : 2.0;
   cpx<T>* lp = lds + xl;
@@ -740,7 +746,7 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zgm(const Geo g, const GreenPar
 #pragma unroll
       for (int j = 0; j < C; ++j)
 #pragma unroll
-        for (int i = 0; i < P; ++i) z_store<T>(b + j * cstride + (long long)(t + TZ * i) * es_g, v[j][i]);
+        for (int i = 0; i < P; ++i) z_store<T, SEG>(b + j * cstride + (long long)(t + TZ * i) * es_g, v[j][i]);
     }
     l = ln;
   }
@@ -777,6 +783,7 @@ template <typename T, int MX, int P, int C>
 __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
   constexpr int TR = MX / P;
   constexpr int RPW = 256 / TR;
+  constexpr int SEG = TR * (int)sizeof(cpx<T>);   // contiguous bytes per access instruction
   constexpr int TABW = 2 * C * C + 5;
   __shared__ cpx<T> lds[RPW * MX];
   __shared__ cpx<T> twl[2 * MX];
@@ -805,8 +812,8 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
     const long long srow = (long long)j * vrows + vrc;
     const cpx<T>* sm = a.smain + (long long)l * main_cpx(g) + srow * MX;
 #pragma unroll
-    for (int i = 0; i < P; ++i) gam[j][i] = ld_stream(sm + t + TR * i);
-    nqs[j] = ld_stream(a.snyq + (long long)l * nyq_cpx(g) + srow);
+    for (int i = 0; i < P; ++i) gam[j][i] = ld_seg<SEG>(sm + t + TR * i);
+    nqs[j] = a.snyq[(long long)l * nyq_cpx(g) + srow];
   }
   // repack each component's half spectrum as the half-length complex
   // transform 2Z = 2E + i 2O, then the inverse transforms of all components
@@ -854,7 +861,7 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
     if (a.mode != XI_STRAIN) {
 #pragma unroll
       for (int j = 0; j < C; ++j) {
-        const cpx<T> tv = ld_stream(reinterpret_cast<const cpx<T>*>(a.tau + fo + (long long)j * g.nvox + vox));
+        const cpx<T> tv = ld_seg<SEG>(reinterpret_cast<const cpx<T>*>(a.tau + fo + (long long)j * g.nvox + vox));
         t0[j] = tv.x;
         t1[j] = tv.y;
       }
@@ -886,7 +893,7 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
       const T al = static_cast<T>(a.st[l].alpha);
 #pragma unroll
       for (int j = 0; j < C; ++j) {
-        const cpx<T> rv = ld_stream(reinterpret_cast<const cpx<T>*>(a.rin + fo + (long long)j * g.nvox + vox));
+        const cpx<T> rv = ld_seg<SEG>(reinterpret_cast<const cpx<T>*>(a.rin + fo + (long long)j * g.nvox + vox));
         const T q0 = in0 * (loc_row<T, C>(L0, vm, 0, iso, j, t0) + g0[j]);
         const T q1 = in1 * (loc_row<T, C>(L1, vm, 0, iso, j, t1) + g1[j]);
         res[j] = cpx<T>{rv.x - al * q0, rv.y - al * q1};
@@ -960,11 +967,11 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
       if (a.mode == XI_IRRES) {
 #pragma unroll
         for (int j = 0; j < C; ++j)
-          st_stream(reinterpret_cast<float2*>(a.rout + fo + (long long)j * g.nvox + vox),
+          st_seg<TR * (int)sizeof(float2)>(reinterpret_cast<float2*>(a.rout + fo + (long long)j * g.nvox + vox),
                     float2{static_cast<float>(res[j].x), static_cast<float>(res[j].y)});
       } else if (a.mode != XI_RESNORM) {
 #pragma unroll
-        for (int j = 0; j < C; ++j) st_stream(reinterpret_cast<cpx<T>*>(a.out + fo + (long long)j * g.nvox + vox), res[j]);
+        for (int j = 0; j < C; ++j) st_seg<SEG>(reinterpret_cast<cpx<T>*>(a.out + fo + (long long)j * g.nvox + vox), res[j]);
       }
     }
   });
