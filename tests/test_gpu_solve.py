@@ -225,10 +225,15 @@ def test_fd_and_consistent_solves_match_oracle(lsh):
             assert abs(vals[0] - vals[1]) < 1e-10
 
 
-def test_full_size_elastic_rsa_256_mixed_against_fp64_and_bounds(lsh):
-    # the benchmark's workload and launch configuration: 256^3, six loads, filtered, mixed CG to 1e-6
+def test_full_size_elastic_rsa_256_mixed_against_fp64_and_bounds(lsh, tmp_path):
+    # the benchmark's workload and launch configuration: 256^3, six loads, filtered, mixed CG to 1e-6,
+    # kernel shapes from the committed autotuner cache (a copy, so that nothing writes the package file)
     w = I.elastic_rsa_workload(256, tol=1e-6)
+    import shutil
     import torch
+    cache = tmp_path / "tune_cache.txt"
+    shutil.copy(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1411_0330_amd",
+                             "tune_cache.txt"), cache)
     phase_dev = torch.from_numpy(w.phase).to("cuda:0")
     res = {}
     for precision, tol in (("mixed", 1e-6), ("fp64", 1e-9)):
@@ -236,6 +241,9 @@ def test_full_size_elastic_rsa_256_mixed_against_fp64_and_bounds(lsh):
         ctx.set_reference(w.A0)
         ctx.set_phases(phase_dev, w.moduli)
         ctx.set_green("filtered")
+        if precision == "mixed":
+            _, hit = ctx.autotune(6, cache)
+            assert hit
         rep = ctx.solve(w.loads, "cg", tol=tol, maxit=3000)
         assert rep["status"] == lsh.OK and max(rep["rel_residual"]) <= tol
         res[precision] = ctx.effective().T.copy()

@@ -13,6 +13,7 @@
   evaluated by the oracle at those wave-vectors only.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -153,13 +154,21 @@ def _plane_wave_case(shape, physics, variant, nload, seed):
 
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_operator_full_size_plane_waves(lsh, dtype):
-    # the benchmark's shape and batch: 256^3 elasticity, 6 loads, filtered
+def test_operator_full_size_plane_waves(lsh, dtype, tmp_path):
+    # the benchmark's shape and batch: 256^3 elasticity, 6 loads, filtered; FP32 with the
+    # benchmark's kernel shapes (the committed autotuner cache, read from a copy)
+    import shutil
     shape, nload, variant = (256, 256, 256), 6, "filtered"
     w = I.elastic_rsa_workload(256)
     tau, gam, A0 = _plane_wave_case(shape, "elastic", variant, nload, seed=3)
     ctx = context(lsh, w.phase, w.moduli, A0, "elastic", variant, precision="mixed" if dtype == "f32" else "fp64",
                   max_loads=nload)
+    if dtype == "f32":
+        cache = tmp_path / "tune_cache.txt"
+        shutil.copy(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1411_0330_amd",
+                                 "tune_cache.txt"), cache)
+        _, hit = ctx.autotune(nload, cache)
+        assert hit
     out = ctx.apply(to_dev(tau, dtype)).cpu().numpy()
     pb = problem(w.phase, w.moduli, A0, "elastic", variant)
     _, dinv, in_i0 = op.phase_tables(pb)
