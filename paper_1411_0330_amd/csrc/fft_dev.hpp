@@ -308,9 +308,10 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[P], int t, cpx<T>* lds, i
 // The same transform on C pencils held by the same threads (v[j] = pencil j):
 // each stage reads its twiddles once for all pencils; the exchanges run pencil
 // by pencil through the one exchange buffer.
-template <int N, int P, int NS, int DIR, typename T, int C>
+template <int N, int P, int NS, int DIR, typename T, int C, int CG = 1>
 __device__ __forceinline__ void fft_stages_multi(cpx<T> (&v)[C][P], int t, cpx<T>* lds, int es,
-                                                 const cpx<T>* __restrict__ tw, int tstride) {
+                                                 const cpx<T>* __restrict__ tw, int tstride, int cs = 0) {
+  static_assert(C % CG == 0, "components per exchange must divide the component count");
   if constexpr (NS < N) {
     constexpr int P2 = pow2_part(P);
     constexpr int R = (NS == 1) ? P : ((N / NS < P2) ? N / NS : P2);
@@ -331,55 +332,65 @@ __device__ __forceinline__ void fft_stages_multi(cpx<T> (&v)[C][P], int t, cpx<T
         });
       });
     }
-    static_for<0, C>([&](auto j_) {
-      constexpr int j = decltype(j_)::value;
-      static_for<0, G>([&](auto i_) {
-        constexpr int i = decltype(i_)::value;
-        cpx<T> u[R];
-        static_for<0, R>([&](auto r_) {
-          constexpr int r = decltype(r_)::value;
-          u[r] = v[j][i + r * G];
+    // CG components per exchange: component jj of a group uses lds + jj cs
+    static_for<0, C / CG>([&](auto g_) {
+      constexpr int g0 = decltype(g_)::value * CG;
+      static_for<0, CG>([&](auto jj_) {
+        constexpr int jj = decltype(jj_)::value;
+        constexpr int j = g0 + jj;
+        static_for<0, G>([&](auto i_) {
+          constexpr int i = decltype(i_)::value;
+          cpx<T> u[R];
+          static_for<0, R>([&](auto r_) {
+            constexpr int r = decltype(r_)::value;
+            u[r] = v[j][i + r * G];
+          });
+          if constexpr (NS > 1) {
+            static_for<1, R>([&](auto r_) {
+              constexpr int r = decltype(r_)::value;
+              u[r] = cmul(u[r], w[i][r]);
+            });
+          }
+          dft<R, DIR>(u);
+          if constexpr (last) {
+            static_for<0, R>([&](auto r_) {
+              constexpr int r = decltype(r_)::value;
+              v[j][i + r * G] = u[r];
+            });
+          } else {
+            const int b = t + TT * i;
+            const int base = (b / NS) * NS * R + b % NS;
+            static_for<0, R>([&](auto r_) {
+              constexpr int r = decltype(r_)::value;
+              lds[jj * cs + (base + r * NS) * es] = u[r];
+            });
+          }
         });
-        if constexpr (NS > 1) {
-          static_for<1, R>([&](auto r_) {
-            constexpr int r = decltype(r_)::value;
-            u[r] = cmul(u[r], w[i][r]);
-          });
-        }
-        dft<R, DIR>(u);
-        if constexpr (last) {
-          static_for<0, R>([&](auto r_) {
-            constexpr int r = decltype(r_)::value;
-            v[j][i + r * G] = u[r];
-          });
-        } else {
-          const int b = t + TT * i;
-          const int base = (b / NS) * NS * R + b % NS;
-          static_for<0, R>([&](auto r_) {
-            constexpr int r = decltype(r_)::value;
-            lds[(base + r * NS) * es] = u[r];
-          });
-        }
       });
       if constexpr (!last) {
         __syncthreads();
-        static_for<0, P>([&](auto q_) {
-          constexpr int q = decltype(q_)::value;
-          v[j][q] = lds[(t + TT * q) * es];
+        static_for<0, CG>([&](auto jj_) {
+          constexpr int jj = decltype(jj_)::value;
+          static_for<0, P>([&](auto q_) {
+            constexpr int q = decltype(q_)::value;
+            v[g0 + jj][q] = lds[jj * cs + (t + TT * q) * es];
+          });
         });
         __syncthreads();
       }
     });
-    if constexpr (!last) fft_stages_multi<N, P, NS * R, DIR, T, C>(v, t, lds, es, tw, tstride);
+    if constexpr (!last) fft_stages_multi<N, P, NS * R, DIR, T, C, CG>(v, t, lds, es, tw, tstride, cs);
   }
 }
 
-template <int N, int P, int DIR, typename T, int C>
+// CG > 1: CG components share each exchange (one barrier pair per group),
+// component jj of a group in lds + jj cs.
+template <int N, int P, int DIR, typename T, int C, int CG = 1>
 __device__ __forceinline__ void fft_pencil_multi(cpx<T> (&v)[C][P], int t, cpx<T>* lds, int es,
-                                                 const cpx<T>* __restrict__ tw, int tstride) {
+                                                 const cpx<T>* __restrict__ tw, int tstride, int cs = 0) {
   static_assert(N == 1 || (P <= N && N % P == 0 && odd_part(N) == odd_part(P)),
                 "points per thread must divide the pencil length and carry its odd factor");
-  fft_stages_multi<N, P, 1, DIR, T, C>(v, t, lds, es, tw, tstride);
+  fft_stages_multi<N, P, 1, DIR, T, C, CG>(v, t, lds, es, tw, tstride, cs);
 }
 
 template <int N, int P, int DIR, typename T>

@@ -342,7 +342,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(xfwdc_waves
   constexpr int RPW = 256 / TR;
   constexpr int SEG = TR * (int)sizeof(cpx<T>);   // contiguous bytes per access instruction
   constexpr int TABW = 2 * C * C + 5;   // phase table row, see phase_row
-  __shared__ cpx<T> lds[RPW * MX];
+  // FP32 six components: two components share each FFT exchange (the LDS of
+  // five workgroups per CU still fits)
+  constexpr int CG = (sizeof(T) == 4 && C == 6) ? 2 : 1;
+  __shared__ cpx<T> lds[CG * RPW * MX];
   __shared__ cpx<T> twl[2 * MX];
   __shared__ T tab[kMaxPhases * TABW];
   __shared__ double red[4];
@@ -426,7 +429,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(xfwdc_waves
   if (!valid) part = 0.0;
   // R2C of every component: half-length transforms, then the unpacking
   cpx<T>* lrow = lds + slot * MX;
-  fft_pencil_multi<MX, P, -1, T, C>(v, t, lrow, 1, twl, 2);
+  fft_pencil_multi<MX, P, -1, T, C, CG>(v, t, lrow, 1, twl, 2, RPW * MX);
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     __syncthreads();
@@ -543,7 +546,10 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
   constexpr int TZ = NZ / P;
   constexpr int SEG = TX * (int)sizeof(cpx<T>);   // contiguous bytes per access instruction
   constexpr int NT = TX * TZ;
-  __shared__ cpx<T> lds[TX * NZ];
+  // FP32 six components: three components share each FFT exchange (a third of
+  // the barriers) where their buffers fit in 96 KiB of LDS
+  constexpr int CG = (sizeof(T) == 4 && C == 6 && 3 * TX * NZ * (int)sizeof(cpx<T>) <= 96 * 1024) ? 3 : 1;
+  __shared__ cpx<T> lds[CG * TX * NZ];
   __shared__ cpx<T> twl[NZ];
   __shared__ double red[(NT + 63) / 64];
   const int l = blockIdx.y;
@@ -584,7 +590,7 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
     for (int i = 0; i < P; ++i)
       v[j][i] = valid ? z_load<T, SEG>(base + j * cstride + (long long)(t + TZ * i) * es_g) : cpx<T>{0, 0};
   __syncthreads();
-  fft_pencil_multi<NZ, P, -1, T, C>(v, t, lp, TX, twl, 1);
+  fft_pencil_multi<NZ, P, -1, T, C, CG>(v, t, lp, TX, twl, 1, TX * NZ);
   if (zmode == Z_GAMMA) {
     double quad = 0.0;
     if (valid) {
@@ -617,7 +623,7 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
       const double s = block_sum<NT>(quad * wk / (double)g.nvox, red);
       if (tid == 0) qpart[(long long)l * pstride + blockIdx.x] = s;
     }
-    fft_pencil_multi<NZ, P, 1, T, C>(v, t, lp, TX, twl, 1);
+    fft_pencil_multi<NZ, P, 1, T, C, CG>(v, t, lp, TX, twl, 1, TX * NZ);
   }
   if (valid) {
 #pragma unroll
@@ -785,7 +791,9 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
   constexpr int RPW = 256 / TR;
   constexpr int SEG = TR * (int)sizeof(cpx<T>);   // contiguous bytes per access instruction
   constexpr int TABW = 2 * C * C + 5;
-  __shared__ cpx<T> lds[RPW * MX];
+  // FP32 six components: three components share each FFT exchange
+  constexpr int CG = (sizeof(T) == 4 && C == 6) ? 3 : 1;
+  __shared__ cpx<T> lds[CG * RPW * MX];
   __shared__ cpx<T> twl[2 * MX];
   __shared__ T tab[kMaxPhases * TABW];
   __shared__ double red[4];
@@ -836,7 +844,7 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
     }
   }
   __syncthreads();
-  fft_pencil_multi<MX, P, 1, T, C>(gam, t, lrow, 1, twl, 2);
+  fft_pencil_multi<MX, P, 1, T, C, CG>(gam, t, lrow, 1, twl, 2, RPW * MX);
 
   // the route above returns N^d times the inverse DFT: a.scale = 1/N^d
   const T sc = a.scale;
