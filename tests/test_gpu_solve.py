@@ -262,3 +262,19 @@ def test_full_size_elastic_rsa_256_mixed_against_fp64_and_bounds(lsh, tmp_path):
     K = (C64[:3, :3].sum()) / 9.0
     mu = (np.trace(C64) - C64[:3, :3].sum() / 3.0) / 10.0
     assert 1.243 <= K <= 1.767 and 0.650 <= mu <= 1.102, (K, mu)
+
+
+@pytest.mark.parametrize("green", ["filtered", "truncated"])
+def test_checkerboard_converges_to_keller_dykhne_on_large_grids(lsh, green):
+    # the 2D checkerboard's effective conductivity is sqrt(a1 a2) (Keller-Dykhne); the
+    # discrete A*_h approaches it as the grid is refined (O(h) trend, Section 5)
+    target = cf.keller_dykhne(1.0, 10.0)
+    errs = []
+    for n in (64, 128, 256, 512):
+        ph = I.checkerboard_2d(n)
+        ctx = context(lsh, ph, np.stack([np.eye(2), 10.0 * np.eye(2)]), 0.5 * np.eye(2), "scalar", green)
+        rep = ctx.solve(np.array([[1.0, 0.0]]), "cg", tol=1e-10, maxit=20000)
+        assert rep["status"] == lsh.OK
+        errs.append(abs(ctx.effective()[0][0] - target))
+    assert all(e2 < e1 for e1, e2 in zip(errs, errs[1:])), errs
+    assert errs[-1] < 0.5 * errs[0], errs
