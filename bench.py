@@ -11,9 +11,14 @@ fields of every load copied out.
 The metric is voxel-iterations per second: voxels times operator
 applications (FP32 inner, FP64 refinement and strain applications alike),
 summed over loads, per second of wall time with inputs already in HBM.  The
-same workload is also solved once with the plain FP64 path for comparison,
-the dominant kernel's algorithmic bandwidth is measured live with HIP events,
-and the CPU oracle is timed on a bounded sample.
+timed steps run the production path (iteration graphs replayed, no kernel
+events).  One more step with per-kernel HIP events on the context's stream
+gives every kernel's mean duration and algorithmic bandwidth (the roofline
+of the dominant kernel).  The accuracy of C* is measured against the GPU's
+FP64 path solved to 1e-10, and the time to reach a C* error of 1e-6 is
+compared between the mixed and the plain FP64 paths over a tolerance sweep.
+A plain 1 GiB device copy gives the on-box copy bandwidth, and the CPU
+oracle is timed on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -41,10 +46,12 @@ def parse():
     ap.add_argument("--maxit", type=int, default=2000)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-timing", action="store_true", help="do not bracket kernels with HIP events")
+    ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP-event pass")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the FP64 1e-10 reference and the time-to-accuracy sweep")
     ap.add_argument("--no-small", action="store_true", help="skip the 64^2 launch-bound leg")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="first run a plain 1 GiB device copy (y = 1.0 * x) to calibrate HBM counters")
+                    help="only run a plain 1 GiB device copy (y = 1.0 * x) first, to calibrate HBM counters")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel shapes")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: the package's tune_cache.txt, written by the autotuner on MI355X)")
@@ -112,13 +119,46 @@ def measured_traffic(kernel):
     return rec.get("bytes_per_launch", {}).get(kernel)
 
 
-def roofline_from(ktimes):
+# Algorithmic bytes per voxel of one load (FP32 elastic path, c = 6, s = 4,
+# one phase byte): a CG voxel-iteration 15 c s + 1 (the three read+write
+# passes of the operator plus the CG vector sweeps), an FP64 refinement
+# application 11 c 8 (x64 += d, r = b - L x64 in FP64, r to FP32), a strain
+# pass 6 c 8 (three FP64 read+write passes) and the tau copy-out c (8 + 4).
+B_CG32, B_IR64, B_STRAIN, B_TAUOUT = 15 * 6 * 4 + 1, 11 * 6 * 8, 6 * 6 * 8, 6 * 12
+
+
+def copy_bandwidth(dev, nbytes=1 << 30, reps=10):
+    """GB/s of a plain device copy of nbytes (read + write counted): the
+    faster of torch's copy and scale (y = 1.0 * x) kernels, timed with events
+    on torch's stream around torch's own kernels."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    best = {}
+    for name, fn in (("copy", lambda: y.copy_(x)), ("scale", lambda: torch.mul(x, 1.0, out=y))):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        best[name] = 2.0 * nbytes / (a.elapsed_time(b) / reps * 1e-3) / 1e9
+    del x, y
+    return max(best.values()), best
+
+
+def roofline_from(ktimes, copy_gbs=None):
     """Dominant kernel class by time; its algorithmic GB/s against the HBM peak."""
     best = max(ktimes.items(), key=lambda kv: kv[1][0])
     name, (ms, launches, nbytes) = best
     achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     total_ms = sum(v[0] for v in ktimes.values())
     total_bytes = sum(v[2] for v in ktimes.values())
+    extra = {}
+    if copy_gbs:
+        extra = {"copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
     return {
         "kernel": name,
         "bound": "hbm",
@@ -133,58 +173,58 @@ def roofline_from(ktimes):
         "launches": launches,
         "all_kernels_GBps": round(total_bytes / (total_ms * 1e-3) / 1e9, 1) if total_ms > 0 else 0.0,
         "kernel_time_share": round(ms / total_ms, 3) if total_ms > 0 else 0.0,
+        "source": "HIP events on the context's stream around every launch of one extra step (eager launches)",
+        **extra,
     }
 
 
-def cpu_baseline(w, target_s=20.0):
-    """The oracle on a bounded sample: one operator application of one load of
-    this workload with its full forward/inverse FFTs and local term, and the
-    Green table and product on a few kz-planes, scaled to the whole grid."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n=128, reps=5):
+    """The oracle as it stands, timed on the host: the median of `reps` full
+    FP64 operator applications (eq. 13: FFTs, Green table product, local
+    term) on the same elastic RSA recipe at n^3 (one load), after one
+    application that builds and caches its Green table."""
     import numpy as np
-    import scipy.fft as sfft
 
-    from oracle import green
     from oracle import operator as op
+    from paper_1411_0330_amd import inputs as I
 
+    w = I.elastic_rsa_workload(n, seed=0)
     pb = op.Problem(w.phase, w.moduli, w.A0, w.physics, w.green)
     tau = op.rhs(pb, w.loads[0])
-    axes = tuple(range(1, pb.d + 1))
+    op._TABLE_CACHE.clear()
     t0 = time.perf_counter()
-    th = sfft.fftn(tau, axes=axes, workers=-1)
-    t_fwd = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    loc = op.local_apply(pb, tau)
-    t_loc = time.perf_counter() - t0
-    n0 = pb.shape[0]
-    planes = 0
-    t_planes = 0.0
-    out = np.zeros_like(th)
-    budget = max(2.0, target_s - t_fwd - 2 * t_loc)
-    while planes < n0:
+    q = op.apply(pb, tau)
+    t_first = time.perf_counter() - t0
+    ts = []
+    for _ in range(reps):
         t0 = time.perf_counter()
-        sl = slice(planes, planes + 1)
-        G = green.table(pb.shape, pb.physics, pb.A0, pb.green, a_slice=sl)
-        out[:, sl] = np.einsum("...ij,j...->i...", G, th[:, sl])
-        t_planes += time.perf_counter() - t0
-        planes += 1
-        if t_planes >= budget * 0.6:
-            break
-    t0 = time.perf_counter()
-    res = sfft.ifftn(out, axes=axes, workers=-1).real + loc
-    t_inv = time.perf_counter() - t0
-    del res
-    est = t_fwd + t_inv + t_loc + t_planes * n0 / planes
+        q = op.apply(pb, q / max(float(np.max(np.abs(q))), 1e-300))
+        ts.append(time.perf_counter() - t0)
+    med = float(np.median(ts))
     nvox = int(w.phase.size)
     return {
-        "value": nvox / est,
+        "value": nvox / med,
         "unit": "voxel-iterations/s",
         "cores": os.cpu_count(),
         "kind": "oracle",
-        "sample": (f"one FP64 operator application (1 of 6 loads) of the 256^3 elastic workload: full "
-                   f"forward/inverse FFTs (scipy, all {os.cpu_count()} threads) and local term, Green table "
-                   f"and product on {planes} of {n0} kz-planes (single-threaded NumPy), scaled to the grid; "
-                   f"estimated {est:.1f} s per application"),
-        "seconds_measured": round(t_fwd + t_inv + t_loc + t_planes, 2),
+        "sample": (f"median of {reps} full FP64 oracle applications of eq. (13) (one load) on the {n}^3 instance "
+                   f"of the same elastic RSA recipe (radius {8 * n / 256:g} voxels, f={w.info['fraction']:.3f}), "
+                   f"Green table cached by a first application ({t_first:.1f} s); scipy FFTs on all "
+                   f"{os.cpu_count()} threads, the table product and local term single-threaded NumPy; "
+                   f"CPU: {cpu_model()}"),
+        "seconds_per_application": round(med, 4),
+        "seconds_measured": round(t_first + sum(ts), 2),
     }
 
 
@@ -272,6 +312,23 @@ def bench_gradient(args):
           flush=True)
 
 
+def solve_once(ctx, w, phase_dev, tol, maxit):
+    """One solve (material set from HBM, solve, C*), wall-timed; returns (seconds, report, C*)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.set_phases(phase_dev, w.moduli)
+    rep = ctx.solve(w.loads, "cg", tol=tol, maxit=maxit)
+    C = ctx.effective().T.copy()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, rep, C
+
+
+def rel_err(C, Cref):
+    import numpy as np
+    return float(np.max(np.abs(C - Cref)) / np.max(np.abs(Cref)))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -291,19 +348,16 @@ def main():
 
     lsh.load()
     dev = "cuda:0"
+    copy_gbs, copy_all = copy_bandwidth(dev)
+    log(f"plain 1 GiB device copy: {copy_all} GB/s (read + write)")
     if args.copy_probe:
-        # a plain elementwise copy of known size: reads 1 GiB, writes 1 GiB
-        xc = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        yc = torch.empty_like(xc)
-        torch.mul(xc, 1.0, out=yc)
-        torch.cuda.synchronize()
-        del xc, yc
-        log("copy probe: 1 GiB read + 1 GiB written by one elementwise kernel")
+        return
     log(f"building the {args.grid}^3 RSA microstructure")
     w = I.elastic_rsa_workload(args.grid, seed=0, tol=args.tol)
     phase_dev = torch.from_numpy(w.phase).to(dev)
     nload = w.loads.shape[0]
     shape = w.phase.shape
+    nvox = int(w.phase.size)
 
     # ---------------- mixed precision (the measured path) ----------------
     ctx = lsh.Context(shape, "elastic", "mixed", max_loads=nload, device=dev)
@@ -320,20 +374,28 @@ def main():
     log(f"warmup {args.warmup} step(s)")
     if args.warmup > 0:
         run_steps(ctx, lsh, w, phase_dev, args.warmup, args)
-    if not args.no_timing:
-        ctx.set_timing(True)
-    log(f"timing {args.steps} step(s)")
+    log(f"timing {args.steps} step(s) (graphs, no kernel events)")
     secs, vox_apps, rep, eff = run_steps(ctx, lsh, w, phase_dev, args.steps, args)
-    ktimes = ctx.kernel_times() if not args.no_timing else {}
-    if not args.no_timing:
-        ctx.set_timing(False)
     value = vox_apps / secs
+    ms_step = secs / args.steps * 1e3
     C_mixed = eff.T.copy()
-    log(f"mixed: {secs / args.steps * 1e3:.1f} ms/step, {value:.3e} voxel-it/s, "
+    log(f"mixed: {ms_step:.1f} ms/step, {value:.3e} voxel-it/s, "
         f"fp32 apps {rep['applications_fp32']}, fp64 apps {rep['applications_fp64']}, "
         f"outer {rep['outer_iterations']}, residuals {max(rep['rel_residual']):.2e}")
-    del ctx
-    torch.cuda.empty_cache()
+    ktimes = {}
+    ms_instr = None
+    if not args.no_timing:
+        # one more step with every launch bracketed by HIP events (eager launches)
+        ctx.set_timing(True)
+        s_i, _, _, _ = run_steps(ctx, lsh, w, phase_dev, 1, args)
+        ktimes = ctx.kernel_times()
+        ctx.set_timing(False)
+        ms_instr = s_i * 1e3
+        log(f"instrumented step: {ms_instr:.1f} ms")
+    # per-step algorithmic bytes (section on measurement: CG, refinement, strain and copy-out)
+    step_bytes = nvox * (B_CG32 * rep["applications_fp32"] + B_IR64 * rep["applications_fp64"]
+                         + nload * (B_STRAIN + B_TAUOUT))
+    step_gbs = step_bytes / (ms_step * 1e-3) / 1e9
 
     out = {
         "metric": METRIC,
@@ -342,7 +404,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": secs / args.steps * 1e3,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -359,32 +421,68 @@ def main():
         "iterations": {"fp32_applications": rep["applications_fp32"], "fp64_applications": rep["applications_fp64"],
                        "outer_refinements": rep["outer_iterations"], "per_load": rep["iterations"],
                        "final_rel_residual_fp64": rep["rel_residual"]},
+        "step_algorithmic": {"bytes": step_bytes, "GBps": round(step_gbs, 1),
+                             "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                             "frac_of_copy": round(step_gbs / copy_gbs, 4),
+                             "per_unit_B": {"cg32": B_CG32, "ir64": B_IR64, "strain": B_STRAIN, "tau_out": B_TAUOUT}},
     }
     if tuned:
         out["kernel_shapes"] = tuned
     if ktimes:
-        out["roofline"] = roofline_from(ktimes)
+        out["roofline"] = roofline_from(ktimes, copy_gbs)
+        out["ms_per_step_instrumented"] = ms_instr
         out["kernels"] = {k: {"ms": round(v[0], 3), "launches": v[1],
+                              "mean_ms": round(v[0] / v[1], 4),
                               "alg_GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else 0.0}
                           for k, v in ktimes.items() if v[1] > 0}
 
-    # ---------------- FP64 comparison on the same workload ----------------
+    # ---------------- accuracy of C* and time to a C* error of 1e-6 ----------------
     if not args.no_fp64:
-        ctx = lsh.Context(shape, "elastic", "fp64", max_loads=nload, device=dev)
-        ctx.set_reference(w.A0)
-        ctx.set_green(w.green)
-        run_steps(ctx, lsh, w, phase_dev, 1, args, keep_fields=False)        # warm
-        s64, va64, rep64, eff64 = run_steps(ctx, lsh, w, phase_dev, 1, args)
+        ctx64 = lsh.Context(shape, "elastic", "fp64", max_loads=nload, device=dev)
+        ctx64.set_reference(w.A0)
+        ctx64.set_green(w.green)
+        solve_once(ctx64, w, phase_dev, args.tol, args.maxit)                  # warm
+        s64, va64, rep64, eff64 = run_steps(ctx64, lsh, w, phase_dev, 1, args)
         C64 = eff64.T.copy()
-        diff = float(np.max(np.abs(C_mixed - C64)) / np.max(np.abs(C64)))
         out["fp64"] = {"value": va64 / s64, "ms_per_step": s64 * 1e3,
                        "fp64_applications": rep64["applications_fp64"],
                        "final_rel_residual": max(rep64["rel_residual"])}
-        out["mixed_vs_fp64"] = {"speedup_time_to_solution": s64 / (secs / args.steps),
-                                "C_star_rel_diff": diff}
-        log(f"fp64: {s64 * 1e3:.1f} ms/step, speedup {s64 / (secs / args.steps):.2f}x, C* rel diff {diff:.2e}")
-        del ctx
-        torch.cuda.empty_cache()
+        log(f"fp64: {s64 * 1e3:.1f} ms/step at tol {args.tol:g}")
+        acc = {"speedup_same_tol": s64 / (secs / args.steps), "C_star_rel_diff_same_tol": rel_err(C_mixed, C64)}
+        if not args.no_accuracy:
+            t_ref, rep_ref, C_ref = solve_once(ctx64, w, phase_dev, 1e-10, args.maxit)
+            log(f"fp64 reference to 1e-10: {t_ref:.2f} s, residual {max(rep_ref['rel_residual']):.2e}")
+            acc.update({
+                "reference": "GPU FP64 path, CG to 1e-10 (C* error measure max|dC*|/max|C*|)",
+                "reference_rel_residual": max(rep_ref["rel_residual"]),
+                "C_star_rel_err_mixed": rel_err(C_mixed, C_ref),
+                "C_star_rel_err_fp64": rel_err(C64, C_ref),
+            })
+            # loosest tolerance of each path whose C* error is <= 1e-6, and its solve time
+            sweep = {}
+            for name, c in (("mixed", ctx), ("fp64", ctx64)):
+                rows = []
+                for tol in (1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7):
+                    solve_once(c, w, phase_dev, tol, args.maxit)
+                    t, r, C = solve_once(c, w, phase_dev, tol, args.maxit)
+                    rows.append({"tol": tol, "seconds": round(t, 4), "C_star_rel_err": rel_err(C, C_ref),
+                                 "applications": r["applications_fp32"] + r["applications_fp64"]})
+                    if rows[-1]["C_star_rel_err"] <= 1e-6:
+                        break
+                sweep[name] = rows
+                log(f"sweep {name}: {rows}")
+            hit = {k: next((r for r in v if r["C_star_rel_err"] <= 1e-6), None) for k, v in sweep.items()}
+            acc["sweep"] = sweep
+            if hit["mixed"] and hit["fp64"]:
+                acc["time_to_1e-6_mixed_s"] = hit["mixed"]["seconds"]
+                acc["time_to_1e-6_fp64_s"] = hit["fp64"]["seconds"]
+                acc["speedup_time_to_accuracy_1e-6"] = hit["fp64"]["seconds"] / hit["mixed"]["seconds"]
+            log(f"accuracy: {acc}")
+            del C_ref
+        out["mixed_vs_fp64"] = acc
+        del ctx64
+    del ctx
+    torch.cuda.empty_cache()
     out["C_star_mandel"] = [[round(x, 8) for x in row] for row in C_mixed.tolist()]
 
     # ---------------- a launch-bound grid: 2D disk 64^2, multi-kernel (eager, graphs) vs persistent ----------------
@@ -406,9 +504,8 @@ def main():
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         its = max(r["iterations"])
-        small[mode] = {"ms_per_solve": round(dt * 1e3, 3),
-                                                   "us_per_iteration": round(dt * 1e6 / its, 2),
-                                                   "iterations": its}
+        small[mode] = {"ms_per_solve": round(dt * 1e3, 3), "us_per_iteration": round(dt * 1e6 / its, 2),
+                       "iterations": its}
         del ctxs
     if small:
         out["disk64_fp64_cg"] = small
@@ -417,7 +514,7 @@ def main():
     # ---------------- CPU oracle on a bounded sample ----------------
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

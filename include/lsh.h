@@ -47,7 +47,7 @@ typedef enum {
   LSH_ENOMEM = -2,      /* workspace missing or too small */
   LSH_EHIP = -3,        /* HIP runtime error */
   LSH_EHYP2 = -4,       /* A_phase - A0 neither zero nor definite (hypothesis (2)) */
-  LSH_EBREAKDOWN = -5,  /* CG breakdown: p.Lp vanished */
+  LSH_EBREAKDOWN = -5,  /* CG breakdown: |p.Lp| at rounding level (see lsh_solve) */
   LSH_ENUMERIC = -6,    /* NaN or Inf met during the solve */
   LSH_ESTATE = -7       /* call out of order (e.g. solve before phases are set) */
 } lsh_status;
@@ -125,7 +125,8 @@ lsh_status lsh_set_reference(lsh_ctx* ctx, const double* A0);
  * values (no sub-voxel averaging of eq. def_ah).  Hypothesis (2) is checked
  * at lsh_solve/lsh_apply time against the current A0: every other phase needs
  * A_phase - A0 definite (either sign), else LSH_EHYP2.  Phase ids >= nphase are
- * an error (checked on host data; device data must be valid).
+ * LSH_EINVAL with the context unchanged: host maps are checked on the host,
+ * device maps (which need a bound workspace) by a kernel during the call.
  */
 lsh_status lsh_set_phases(lsh_ctx* ctx, const uint8_t* phase, int mem, int nphase,
                           const double* moduli);
@@ -229,8 +230,15 @@ lsh_status lsh_set_initial_guess(lsh_ctx* ctx, int load, const void* tau, int dt
  * max|a - a0| < a0).  CG is guaranteed to converge when the system is positive
  * definite (A0 softer than every phase, Section 5); with A0 between the phases
  * the system is symmetric indefinite and CG proceeds, reporting
- * LSH_EBREAKDOWN if p.Lp vanishes.  Loads converge independently: a converged
- * load is frozen while the others iterate.
+ * LSH_EBREAKDOWN for a load whose |p.Lp| falls to g r.r or below, with
+ * g = eps (max over the phases of ||(A - A0)^{-1}||_2 + ||A0^{-1}||_2) a bound
+ * of ||L||_2 times eps = 1e-12 (FP64 fields) or 1e-6 (FP32 fields of the
+ * mixed inner solve): as p.p >= r.r, the Rayleigh quotient of p is then below
+ * eps ||L||, unresolved at the field precision (per-voxel media use
+ * ||A0^{-1}|| alone).  In a mixed solve, a breakdown or NaN/Inf of the inner
+ * FP32 solve ends that load with that status after its progress is refined
+ * into the FP64 solution.  Loads converge independently: a converged load is
+ * frozen while the others iterate.
  */
 lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, double tol,
                      int maxit, lsh_load_report* reports, lsh_solve_report* summary);
@@ -238,13 +246,21 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
 /*
  * Copy a field of the last solve for load `load` into dst
  * ([component][z][y][x], dtype LSH_F64 or LSH_F32, host or device memory):
- *   LSH_FIELD_TAU     the polarisation tau;
- *   LSH_FIELD_STRAIN  p - Gamma tau on every voxel (the estimate of p + grad w_p).
+ *   LSH_FIELD_TAU     the polarisation tau, the unknown of eq. (13);
+ *   LSH_FIELD_STRAIN  p - Gamma tau on every voxel: the estimate of
+ *                     p + grad w_p that the proof of the equivalence lemma of
+ *                     Section 2.2.2 reads off the Lippmann--Schwinger equation
+ *                     (equal to (A - A0)^{-1} tau on I0 at convergence); one
+ *                     extra FP64 operator pass, computed during the call.
+ * LSH_ESTATE without a solve (or after lsh_set_initial_guess overwrote the
+ * load's solution slot); LSH_EINVAL for a load beyond the last solve's.
  */
 lsh_status lsh_get_field(lsh_ctx* ctx, int load, int which, void* dst, int dtype, int mem);
 
-/* Mean stress A0 p_l + <tau_l> of the last solve, host FP64 array nload x c.
- * With the c unit loads, row l is column l of the homogenised matrix A*_h. */
+/* Mean stress A0 p_l + <tau_l> of the last solve, host FP64 array nload x c:
+ * the discrete homogenised matrix of Theorem 4, A*_h p = A0 p + <tau_h(p)>,
+ * with the mean over the voxels reduced in FP64 in a fixed order.  With the
+ * c unit loads, row l is column l of A*_h.  LSH_ESTATE without a solve. */
 lsh_status lsh_get_effective(lsh_ctx* ctx, double* sigma_mean);
 
 /*

@@ -34,6 +34,8 @@ UNITS = [
     ("k_y.hip", "k_y_f64.o", ["-DLSH_Y_TYPE=double"]),
     ("k_z.hip", "k_z_f32.o", ["-DLSH_Z_TYPE=float"]),
     ("k_z.hip", "k_z_f64.o", ["-DLSH_Z_TYPE=double"]),
+    ("k_z.hip", "k_zs_f32.o", ["-DLSH_Z_TYPE=float", "-DLSH_Z_STORED"]),
+    ("k_z.hip", "k_zs_f64.o", ["-DLSH_Z_TYPE=double", "-DLSH_Z_STORED"]),
     ("k_tiny.hip", "k_tiny_f32.o", ["-DLSH_TINY_TYPE=float"]),
     ("k_tiny.hip", "k_tiny_f64.o", ["-DLSH_TINY_TYPE=double"]),
     ("runtime.hip", "runtime.o", []),
@@ -62,7 +64,9 @@ def build(verbose: bool = True, jobs: int | None = None) -> str:
     subprocess.run([sys.executable, os.path.join(CSRC, "gen_consts.py")], check=True)
     jobs = jobs or min(len(UNITS), max(1, (os.cpu_count() or 2)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        for obj in ex.map(_compile, UNITS):
+        futs = [ex.submit(_compile, u) for u in UNITS]
+        for f in cf.as_completed(futs):
+            obj = f.result()
             if verbose:
                 print(f"[build] compiled {obj}", flush=True)
     tmp = LIB + ".tmp"

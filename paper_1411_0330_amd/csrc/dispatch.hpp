@@ -100,6 +100,11 @@ template <typename T> int launch_y(hipStream_t s, const Geo& g, int dir, cpx<T>*
 template <typename T> int launch_zg(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb,
                                     int zmode, cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw, const LoadState* st,
                                     int nload, int variant = 0, double* qpart = nullptr, int pstride = 0);
+// the Green pass with the stored operator tb.st (3D, three or six components;
+// -1 elsewhere); launch_zg forwards to it when tb.st is bound
+template <typename T> int launch_zg_stored(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb,
+                                           cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload,
+                                           int variant, double* qpart, int pstride);
 // x forward of conjugate gradients over all components of a voxel row (returns
 // the workgroups per load, i.e. the partials written per load)
 template <typename T> int launch_xfwdc(hipStream_t s, const XfwdcArgs<T>& a, int nload);

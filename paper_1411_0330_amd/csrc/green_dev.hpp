@@ -45,7 +45,47 @@ struct GreenTabs {
   int wstride;
   const cpx<T>* tw[3];
   const T* tab;
+  const T* st;   // stored operator of the z pass (layout below), or nullptr
 };
+
+// ----------------------------------------------------------------------------
+// Stored operator of the z pass.  The matrix of one wave-vector (the upper
+// triangle of green_matrix, padded with zeros to NG groups of four entries)
+// is formed once per reference medium, in FP64, and kept in the field type.
+// Group g of wave-vector (kx, ky, kz) sits at
+//   main spectrum  ((kz ny + ky) NG + g) mx + kx
+//   Nyquist plane  nz ny mx NG + (kz NG + g) ny + ky
+// (in units of four entries), so the TX pencils of a z tile read each group
+// as one contiguous run of TX quads.
+// ----------------------------------------------------------------------------
+template <typename T>
+struct alignas(4 * sizeof(T)) Quad {
+  T a, b, c, d;
+};
+
+template <int C>
+constexpr int store_groups() {
+  return (C * (C + 1) / 2 + 3) / 4;
+}
+
+// The NE = C(C+1)/2 entries of the wave-vector whose group 0 is at q, groups
+// `gstride` quads apart.
+template <typename T, int C>
+__device__ __forceinline__ void stored_matrix(const Quad<T>* __restrict__ q, const long long gstride,
+                                              T (&G)[C * (C + 1) / 2]) {
+  constexpr int NE = C * (C + 1) / 2, NG = store_groups<C>();
+  T e[4 * NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const Quad<T> v = q[g * gstride];
+    e[4 * g] = v.a;
+    e[4 * g + 1] = v.b;
+    e[4 * g + 2] = v.c;
+    e[4 * g + 3] = v.d;
+  }
+#pragma unroll
+  for (int i = 0; i < NE; ++i) G[i] = e[i];
+}
 
 // Stored symmetric table applied to a c-vector
 template <typename T, int D>

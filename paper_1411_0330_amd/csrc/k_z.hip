@@ -1,8 +1,17 @@
 // z pass fused with the Green operator; instances for one element type
-// (LSH_Z_TYPE) so that FP32 and FP64 compile in parallel.
+// (LSH_Z_TYPE) so that FP32 and FP64 compile in parallel.  Built twice per
+// type: without LSH_Z_STORED the operator is formed on the fly (launch_zg);
+// with it, from the stored table (launch_zg_stored, three- and
+// six-component 3D fields), in a unit of its own so both compile in parallel.
 #include "dispatch.hpp"
 
 namespace lsh {
+
+#ifdef LSH_Z_STORED
+constexpr bool kGS = true;
+#else
+constexpr bool kGS = false;
+#endif
 
 template <typename T, int NZ, int C, int TX, int P>
 static int z_inst(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, int zmode, cpx<T>* sm,
@@ -11,8 +20,10 @@ static int z_inst(hipStream_t s, const Geo& g, const GreenParams& gp, const Gree
   const int xtiles = (g.mx + TX - 1) / TX;
   const int main_tiles = g.ny * xtiles;
   const int nyq_tiles = (g.ny + TX - 1) / TX;
-  hipLaunchKernelGGL((k_zg<T, NZ, P, TX, C>), dim3(main_tiles + nyq_tiles, nload), dim3(NT), 0, s, g, gp, tb, zmode,
-                     sm, sn, tw, st, main_tiles, qp, ps);
+  // stored operator: one workgroup per (tile, load), the loads of a tile adjacent on one XCD
+  const dim3 grid = kGS ? dim3((main_tiles + nyq_tiles) * nload, 1) : dim3(main_tiles + nyq_tiles, nload);
+  hipLaunchKernelGGL((k_zg<T, NZ, P, TX, C, kGS>), grid, dim3(NT), 0, s, g, gp, tb, zmode, sm, sn, tw, st,
+                     main_tiles, qp, ps, nload);
   return main_tiles + nyq_tiles;
 }
 
@@ -45,7 +56,7 @@ static int z_var(hipStream_t s, const Geo& g, const GreenParams& gp, const Green
 template <typename T, int NZ, int C>
 static int z_one(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, int zmode, cpx<T>* sm,
                  cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload, double* qp, int ps, int variant = 0) {
-  if constexpr (sizeof(T) == 4 && (NZ == 128 || NZ == 256) && C != 2) {
+  if constexpr (!kGS && sizeof(T) == 4 && (NZ == 128 || NZ == 256) && C != 2) {
     if (variant == 4 && zmode == Z_GAMMA && gp.variant != kGreenFD)
       return zm_inst<T, NZ, C>(s, g, gp, tb, sm, sn, tw, st, nload, qp, ps);
   }
@@ -83,6 +94,16 @@ static int z_c(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTa
   }
 }
 
+#ifdef LSH_Z_STORED
+template <typename T>
+int launch_zg_stored(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, cpx<T>* sm,
+                     cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload, int v, double* qp, int ps) {
+  if (g.nz == 1 || tb.st == nullptr) return -1;
+  if (g.c == 3) return z_c<T, 3>(s, g, gp, tb, Z_GAMMA, sm, sn, tw, st, nload, v, qp, ps);
+  if (g.c == 6) return z_c<T, 6>(s, g, gp, tb, Z_GAMMA, sm, sn, tw, st, nload, v, qp, ps);
+  return -1;
+}
+#else
 template <typename T>
 int launch_zg(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, int zmode, cpx<T>* sm,
               cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload, int v, double* qp, int ps) {
@@ -90,16 +111,27 @@ int launch_zg(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTab
     if (g.nz != 1) return -1;
     return z_one<T, 1, 2>(s, g, gp, tb, zmode, sm, sn, tw, st, nload, qp, ps);
   }
+  // the stored operator (where bound) serves the Green pass of every shape
+  // except the multi-load one (4), which forms its matrices itself
+  if (zmode == Z_GAMMA && tb.st != nullptr && g.nz > 1 && v != 4)
+    return launch_zg_stored<T>(s, g, gp, tb, sm, sn, tw, st, nload, v, qp, ps);
   if (g.c == 3) return z_c<T, 3>(s, g, gp, tb, zmode, sm, sn, tw, st, nload, v, qp, ps);
   if (g.c == 6) return z_c<T, 6>(s, g, gp, tb, zmode, sm, sn, tw, st, nload, v, qp, ps);
   return -1;
 }
+#endif
 
 #ifndef LSH_Z_TYPE
 #error "define LSH_Z_TYPE"
 #endif
+#ifdef LSH_Z_STORED
+template int launch_zg_stored<LSH_Z_TYPE>(hipStream_t, const Geo&, const GreenParams&, const GreenTabs<LSH_Z_TYPE>&,
+                                          cpx<LSH_Z_TYPE>*, cpx<LSH_Z_TYPE>*, const cpx<LSH_Z_TYPE>*,
+                                          const LoadState*, int, int, double*, int);
+#else
 template int launch_zg<LSH_Z_TYPE>(hipStream_t, const Geo&, const GreenParams&, const GreenTabs<LSH_Z_TYPE>&, int,
                                    cpx<LSH_Z_TYPE>*, cpx<LSH_Z_TYPE>*, const cpx<LSH_Z_TYPE>*, const LoadState*,
                                    int, int, double*, int);
+#endif
 
 }  // namespace lsh

@@ -537,12 +537,30 @@ __device__ __forceinline__ void z_store(cpx<T>* p, const cpx<T>& v) {
 // (Parseval), w_k = 1 on the kx = 0 and kx = nx/2 planes and 2 elsewhere
 // (the half spectrum of a real field), one FP64 partial per workgroup at
 // qpart[load * pstride + blockIdx.x].
-template <typename T, int NZ, int P, int TX, int C>
+// Workgroup id -> (tile, load) of the z pass with the stored operator: the
+// nload workgroups of one tile are dispatched one after another on one XCD
+// (ids are dealt round-robin to the 8 XCDs), so the operator entries of the
+// tile are read from HBM once and then from that XCD's L2.  Tiles past the
+// last whole group of 8 keep a plain order.
+__device__ __forceinline__ void xcd_load_tile(const int id, const int ntile, const int nload, int& tile, int& l) {
+  const int full = (ntile / 8) * 8 * nload;
+  if (id < full) {
+    const int x = id % 8, slot = id / 8;
+    tile = (slot / nload) * 8 + x;
+    l = slot % nload;
+  } else {
+    const int r = id - full;
+    tile = (ntile / 8) * 8 + r / nload;
+    l = r % nload;
+  }
+}
+
+template <typename T, int NZ, int P, int TX, int C, bool GS>
 __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenParams gp, const GreenTabs<T> tb,
                                                    const int zmode, cpx<T>* __restrict__ smain,
                                                    cpx<T>* __restrict__ snyq, const cpx<T>* __restrict__ twz,
                                                    const LoadState* __restrict__ st, const int main_tiles,
-                                                   double* __restrict__ qpart, const int pstride) {
+                                                   double* __restrict__ qpart, const int pstride, const int nload) {
   constexpr int TZ = NZ / P;
   constexpr int SEG = TX * (int)sizeof(cpx<T>);   // contiguous bytes per access instruction
   constexpr int NT = TX * TZ;
@@ -552,7 +570,13 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
   __shared__ cpx<T> lds[CG * TX * NZ];
   __shared__ cpx<T> twl[NZ];
   __shared__ double red[(NT + 63) / 64];
-  const int l = blockIdx.y;
+  int l, tid_tile;
+  if constexpr (GS) {
+    xcd_load_tile(blockIdx.x, main_tiles + (g.ny + TX - 1) / TX, nload, tid_tile, l);
+  } else {
+    l = blockIdx.y;
+    tid_tile = blockIdx.x;
+  }
   if (st != nullptr && !st[l].active) return;
   const int tid = threadIdx.x;
   for (int i = tid; i < NZ; i += TX * TZ) twl[i] = twz[i];
@@ -561,9 +585,9 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
   long long es_g, cstride;
   int kx, ky;
   bool valid;
-  if ((int)blockIdx.x < main_tiles) {
+  if (tid_tile < main_tiles) {
     const int xtiles = (g.mx + TX - 1) / TX;
-    const int tile = xcd_tile<line_share<T, TX>()>(blockIdx.x, main_tiles);
+    const int tile = xcd_tile<line_share<T, TX>()>(tid_tile, main_tiles);
     const int xc = tile % xtiles;
     ky = tile / xtiles;
     kx = xc * TX + xl;
@@ -572,7 +596,7 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
     es_g = (long long)g.ny * g.mx;
     cstride = (long long)g.nz * g.ny * g.mx;
   } else {
-    ky = (blockIdx.x - main_tiles) * TX + xl;
+    ky = (tid_tile - main_tiles) * TX + xl;
     kx = g.mx;
     valid = ky < g.ny;
     base = snyq + (long long)l * nyq_cpx(g) + (valid ? ky : 0);
@@ -594,16 +618,40 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
   if (zmode == Z_GAMMA) {
     double quad = 0.0;
     if (valid) {
+      // stored operator: group 0 of (kx, ky, kz = t) and the steps between
+      // groups and between the thread's wave-vectors (kz += TZ)
+      constexpr int NG = store_groups<C>();
+      const Quad<T>* sq = nullptr;
+      long long sgs = 0, skz = 0;
+      if constexpr (GS) {
+        const Quad<T>* s4 = reinterpret_cast<const Quad<T>*>(tb.st);
+        const long long nmain = (long long)g.nz * g.ny * g.mx;
+        if (kx < g.mx) {
+          sq = s4 + (((long long)t * g.ny + ky) * NG) * g.mx + kx;
+          sgs = g.mx;
+          skz = (long long)TZ * g.ny * NG * g.mx;
+        } else {
+          sq = s4 + nmain * NG + ((long long)t * NG) * g.ny + ky;
+          sgs = g.ny;
+          skz = (long long)TZ * NG * g.ny;
+        }
+      }
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         const int kz = t + TZ * i;
-        const int k[3] = {kx, ky, kz};
-        const long long tidx = (kx < g.mx) ? ((long long)kz * g.ny + ky) * g.mx + kx
-                                           : (long long)g.nz * g.ny * g.mx + (long long)kz * g.ny + ky;
         cpx<T> w[C];
 #pragma unroll
         for (int j = 0; j < C; ++j) w[j] = v[j][i];
-        green_apply<T, C>(gp, tb, k, tidx, w);
+        if constexpr (GS) {
+          T Gm[C * (C + 1) / 2];
+          stored_matrix<T, C>(sq + i * skz, sgs, Gm);
+          sym_apply<T, C>(Gm, w);
+        } else {
+          const int k[3] = {kx, ky, kz};
+          const long long tidx = (kx < g.mx) ? ((long long)kz * g.ny + ky) * g.mx + kx
+                                             : (long long)g.nz * g.ny * g.mx + (long long)kz * g.ny + ky;
+          green_apply<T, C>(gp, tb, k, tidx, w);
+        }
         if (qpart != nullptr) {
           // one wave-vector's terms in the field type (tau_hat . Gamma_hat tau_hat >= 0:
           // no cancellation), the sum over wave-vectors in FP64
@@ -615,13 +663,13 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
 #pragma unroll
         for (int j = 0; j < C; ++j) v[j][i] = w[j];
         // one wave-vector's operator at a time: bounds the registers of the alias sums
-        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (!GS) __builtin_amdgcn_sched_barrier(0);
       }
     }
     if (qpart != nullptr) {
       const double wk = (kx == 0 || kx == g.mx) ? 1.0 : 2.0;
       const double s = block_sum<NT>(quad * wk / (double)g.nvox, red);
-      if (tid == 0) qpart[(long long)l * pstride + blockIdx.x] = s;
+      if (tid == 0) qpart[(long long)l * pstride + tid_tile] = s;
     }
     fft_pencil_multi<NZ, P, 1, T, C, CG>(v, t, lp, TX, twl, 1, TX * NZ);
   }
@@ -1003,6 +1051,41 @@ __device__ __forceinline__ double sinc_pi(double x) {   // sin(pi x)/(pi x)
   return sinpi(x) / (3.14159265358979323846 * x);
 }
 
+// Stored operator of the z pass (layout in green_dev.hpp): green_matrix in
+// FP64 at every wave-vector of the half spectrum, rounded to TO.
+template <typename TO, int C>
+__global__ __launch_bounds__(256) void k_green_store(const Geo g, const GreenParams gp, const GreenTabs<double> tb,
+                                                     Quad<TO>* __restrict__ out) {
+  constexpr int NE = C * (C + 1) / 2, NG = store_groups<C>();
+  const long long nmain = (long long)g.nz * g.ny * g.mx;
+  const long long total = nmain + (long long)g.nz * g.ny;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= total) return;
+  int k[3];
+  Quad<TO>* q;
+  long long gs;
+  if (id < nmain) {
+    k[0] = (int)(id % g.mx);
+    k[1] = (int)((id / g.mx) % g.ny);
+    k[2] = (int)(id / ((long long)g.mx * g.ny));
+    q = out + (((long long)k[2] * g.ny + k[1]) * NG) * g.mx + k[0];
+    gs = g.mx;
+  } else {
+    const long long r = id - nmain;
+    k[0] = g.mx;
+    k[1] = (int)(r % g.ny);
+    k[2] = (int)(r / g.ny);
+    q = out + nmain * NG + ((long long)k[2] * NG) * g.ny + k[1];
+    gs = g.ny;
+  }
+  double G[NE];
+  green_matrix<double, C>(gp, tb, k, 0, G);
+  double e[4 * NG];
+  for (int i = 0; i < 4 * NG; ++i) e[i] = i < NE ? G[i] : 0.0;
+  for (int j = 0; j < NG; ++j)
+    q[j * gs] = Quad<TO>{(TO)e[4 * j], (TO)e[4 * j + 1], (TO)e[4 * j + 2], (TO)e[4 * j + 3]};
+}
+
 template <int C>
 __global__ __launch_bounds__(256) void k_consistent_table(const Geo g, const GreenParams gp, const int nmax,
                                                           double* __restrict__ tab64, float* __restrict__ tab32) {
@@ -1338,6 +1421,14 @@ __global__ __launch_bounds__(256) void k_voxset(const long long v0, const long l
     const double s = block_sum<256>(bad, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
   }
+}
+
+// Sets *flag when a phase id of a device map is nphase or more (every writer
+// stores the same value, so the race is benign); grid-stride over the voxels.
+static __global__ __launch_bounds__(256) void k_phase_check(const uint8_t* __restrict__ phase, const long long nvox,
+                                                     const int nphase, int* __restrict__ flag) {
+  for (long long v = (long long)blockIdx.x * 256 + threadIdx.x; v < nvox; v += (long long)gridDim.x * 256)
+    if ((int)phase[v] >= nphase) *flag = 1;
 }
 
 // ----------------------------------------------------------------------------

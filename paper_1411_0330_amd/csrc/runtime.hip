@@ -12,6 +12,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <thread>
@@ -155,16 +156,32 @@ struct lsh_ctx {
   bool cg_fused = true;    // CG with p.Lp from the x and z passes and r updated in the x-inverse pass
   bool persistent = true;  // small grids: the whole CG loop of a load in one workgroup
   bool tab_em = false;     // second table matrix: (A-A0)(A+A0)^{-1} (Eyre--Milton) instead of A-A0
+  // stored operator of the z pass (filtered operator, 3D, three or six
+  // components; FP32 entries in a mixed context, FP64 in an FP64 one): formed
+  // once per reference medium instead of at every application.  LSH_GSTORE=0
+  // keeps the operator formed on the fly.
+  bool gstore = true;
+  bool gst_dirty = true;
   char* sbuf = nullptr;    // bound solver buffer (MINRES fields)
   size_t sbuf_size = 0;
   int tune[2][NPASS] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // kernel-shape variant per (FP32/FP64, pass)
+  // CG breakdown threshold g (|p.Lp| <= g r.r) for FP32 and FP64 fields:
+  // eps times a bound of ||L||_2 (max ||(A - A0)^{-1}|| over the phases plus
+  // ||A0^{-1}||, which bounds every Green operator)
+  double bd_guard[2] = {0.0, 0.0};
 
   // workspace
   char* ws = nullptr;
   size_t ws_need = 0, ws_size = 0;
+  int ws_device = -1;   // device holding the workspace (-1: unknown)
+  // spectrum buffers used instead of the workspace's while set (the
+  // allocation-free operator: main spectrum in the caller's output, Nyquist
+  // plane in the per-device scratch array)
+  void* ovr_sm = nullptr;
+  void* ovr_sn = nullptr;
   struct {
     size_t x64, r64, p64, d32, r32, p32, s64m, s64n, s32m, s32n, phase, i0, ptab64, ptab32, vc64, vc32, tw64, tw32,
-        wt64, wt32, loads, wgrad, st_out, st_in, mstate, guess, partials, sums, end;
+        wt64, wt32, loads, wgrad, st_out, st_in, mstate, guess, partials, sums, gst, end;
   } off{};
   long long pstride = 0, nsums = 0;
   int twoff[3] = {0, 0, 0};
@@ -289,6 +306,9 @@ void drain_timers(lsh_ctx* ctx) {
 }
 
 // ------------------------- layout ----------------------------------------
+// grids whose z pass has a stored-operator instance
+bool gst_shape(const lsh_ctx* ctx) { return ctx->dim == 3 && ctx->n[2] > 1 && (ctx->c == 3 || ctx->c == 6); }
+
 void compute_layout(lsh_ctx* ctx) {
   const long long L = ctx->max_loads, F = ctx->F, c = ctx->c;
   const long long V = ctx->geo.nvox;
@@ -341,6 +361,13 @@ void compute_layout(lsh_ctx* ctx) {
   ctx->off.partials = take(sizeof(double) * L * c * pmax);
   ctx->nsums = L * c;
   ctx->off.sums = take(sizeof(double) * L * c);
+  // stored z-pass operator: NG quads of the field type per half-spectrum wave-vector
+  ctx->off.gst = 0;
+  if (gst_shape(ctx)) {
+    const long long nk = (long long)ctx->n[2] * ctx->n[1] * (ctx->n[0] / 2 + 1);
+    const int ng = c == 6 ? store_groups<6>() : store_groups<3>();
+    ctx->off.gst = take((mixed ? sizeof(float) : sizeof(double)) * 4 * ng * nk);
+  }
   ctx->off.end = o;
   ctx->ws_need = o;
 }
@@ -405,6 +432,7 @@ lsh_status build_tables(lsh_ctx* ctx) {
   bool all_iso = true;
   ctx->h_ptab32.assign((size_t)kMaxPhases * tabw, 0.f);
   ctx->h_i0.assign(256, 0);
+  double lmax = 0.0;   // max over phases of ||(A - A0)^{-1}||_2
   for (int p = 0; p < ctx->nphase; ++p) {
     double D[36], Dinv[36];
     bool zero = true;
@@ -428,6 +456,7 @@ lsh_status build_tables(lsh_ctx* ctx) {
       return fail(ctx, LSH_EHYP2,
                   "phase " + std::to_string(p) + ": A - A0 is neither zero nor definite (hypothesis (2))");
     if (!invert(c, D, Dinv)) return fail(ctx, LSH_EHYP2, "phase " + std::to_string(p) + ": A - A0 is singular");
+    for (int i = 0; i < c; ++i) lmax = std::max(lmax, 1.0 / std::fabs(ev[i]));
     // second matrix: A - A0 (basic scheme) or (A - A0)(A + A0)^{-1} (Eyre--Milton)
     double S2[36];
     if (ctx->tab_em) {
@@ -467,6 +496,16 @@ lsh_status build_tables(lsh_ctx* ctx) {
     ctx->h_i0[p] = 1;
   }
   ctx->iso = (all_iso || ctx->mat_voxel) ? 1 : 0;
+  {
+    // per-voxel media: ||A0^{-1}|| alone (a smaller bound, a stricter test)
+    double ev0[6];
+    sym_eigvals(c, ctx->A0.data(), ev0);
+    double e0 = ev0[0];
+    for (int i = 1; i < c; ++i) e0 = std::min(e0, ev0[i]);
+    const double lbound = lmax + 1.0 / e0;
+    ctx->bd_guard[0] = 1e-6 * lbound;
+    ctx->bd_guard[1] = 1e-12 * lbound;
+  }
   for (size_t i = 0; i < ctx->h_ptab64.size(); ++i) ctx->h_ptab32[i] = (float)ctx->h_ptab64[i];
 
   // Green parameters
@@ -513,6 +552,26 @@ lsh_status build_tables(lsh_ctx* ctx) {
                                   ctx->series, t64, t32); break;
     }
     STCHK(check_launch(ctx, 0, "consistent table"));
+  }
+  if (gst_shape(ctx) && ctx->gstore && ctx->green == LSH_GREEN_FILTERED && ctx->gst_dirty) {
+    const long long nk = main_cpx(ctx->geo) / ctx->c + nyq_cpx(ctx->geo) / ctx->c;
+    const int nb = (int)((nk + 255) / 256);
+    GreenTabs<double> tb64{ctx->ptr<cpx<double>>(ctx->off.wt64), ctx->wstride, {nullptr, nullptr, nullptr}, nullptr,
+                           nullptr};
+    const bool mixed = ctx->precision == LSH_MIXED;
+#define LSH_GSTORE_BUILD(TO, CC)                                                                             \
+  hipLaunchKernelGGL((k_green_store<TO, CC>), dim3(nb), dim3(256), 0, ctx->stream, ctx->geo, gp, tb64,       \
+                     ctx->ptr<Quad<TO>>(ctx->off.gst))
+    if (ctx->c == 6) {
+      if (mixed) LSH_GSTORE_BUILD(float, 6);
+      else LSH_GSTORE_BUILD(double, 6);
+    } else {
+      if (mixed) LSH_GSTORE_BUILD(float, 3);
+      else LSH_GSTORE_BUILD(double, 3);
+    }
+#undef LSH_GSTORE_BUILD
+    STCHK(check_launch(ctx, 0, "stored Green operator"));
+    ctx->gst_dirty = false;
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->tables_dirty = false;
@@ -581,17 +640,30 @@ lsh_status prepare(lsh_ctx* ctx) {
 // ------------------------- operator pieces -------------------------------
 template <typename T> struct Sel;
 template <> struct Sel<double> {
-  static cpx<double>* sm(lsh_ctx* c) { return c->ptr<cpx<double>>(c->off.s64m); }
-  static cpx<double>* sn(lsh_ctx* c) { return c->ptr<cpx<double>>(c->off.s64n); }
+  static cpx<double>* sm(lsh_ctx* c) {
+    return c->ovr_sm ? static_cast<cpx<double>*>(c->ovr_sm) : c->ptr<cpx<double>>(c->off.s64m);
+  }
+  static cpx<double>* sn(lsh_ctx* c) {
+    return c->ovr_sn ? static_cast<cpx<double>*>(c->ovr_sn) : c->ptr<cpx<double>>(c->off.s64n);
+  }
   static const cpx<double>* tw(lsh_ctx* c, int a) { return c->ptr<cpx<double>>(c->off.tw64) + c->twoff[a]; }
   static const cpx<double>* wt(lsh_ctx* c) { return c->ptr<cpx<double>>(c->off.wt64); }
   static const double* ptab(lsh_ctx* c) { return c->ptr<double>(c->off.ptab64); }
   static const double* vc(lsh_ctx* c) { return c->mat_voxel ? c->ptr<double>(c->off.vc64) : nullptr; }
   static const double* gtab(lsh_ctx* c) { return reinterpret_cast<const double*>(c->gtab); }
+  static const double* gst(lsh_ctx* c) {
+    return (gst_shape(c) && c->gstore && c->green == LSH_GREEN_FILTERED && c->precision == LSH_FP64)
+               ? c->ptr<double>(c->off.gst)
+               : nullptr;
+  }
 };
 template <> struct Sel<float> {
-  static cpx<float>* sm(lsh_ctx* c) { return c->ptr<cpx<float>>(c->off.s32m); }
-  static cpx<float>* sn(lsh_ctx* c) { return c->ptr<cpx<float>>(c->off.s32n); }
+  static cpx<float>* sm(lsh_ctx* c) {
+    return c->ovr_sm ? static_cast<cpx<float>*>(c->ovr_sm) : c->ptr<cpx<float>>(c->off.s32m);
+  }
+  static cpx<float>* sn(lsh_ctx* c) {
+    return c->ovr_sn ? static_cast<cpx<float>*>(c->ovr_sn) : c->ptr<cpx<float>>(c->off.s32n);
+  }
   static const cpx<float>* tw(lsh_ctx* c, int a) { return c->ptr<cpx<float>>(c->off.tw32) + c->twoff[a]; }
   static const cpx<float>* wt(lsh_ctx* c) { return c->ptr<cpx<float>>(c->off.wt32); }
   static const float* ptab(lsh_ctx* c) { return c->ptr<float>(c->off.ptab32); }
@@ -600,6 +672,11 @@ template <> struct Sel<float> {
     if (!c->gtab) return nullptr;
     const long long nk = main_cpx(c->geo) / c->c + nyq_cpx(c->geo) / c->c;
     return reinterpret_cast<const float*>(c->gtab + align_up(sizeof(double) * nk * (c->c * (c->c + 1) / 2)));
+  }
+  static const float* gst(lsh_ctx* c) {
+    return (gst_shape(c) && c->gstore && c->green == LSH_GREEN_FILTERED && c->precision == LSH_MIXED)
+               ? c->ptr<float>(c->off.gst)
+               : nullptr;
   }
 };
 
@@ -613,6 +690,8 @@ void tune_from_env(lsh_ctx* ctx) {
   if (f && f[0] == '0') ctx->cg_fused = false;
   const char* pe = std::getenv("LSH_PERSISTENT");
   if (pe && pe[0] == '0') ctx->persistent = false;
+  const char* gs = std::getenv("LSH_GSTORE");
+  if (gs && gs[0] == '0') ctx->gstore = false;
   const char* e = std::getenv("LSH_TUNE");
   if (!e) return;
   const char* names[NPASS] = {"xfwd", "y", "zg", "xinv"};
@@ -662,7 +741,7 @@ lsh_status forward_part(lsh_ctx* ctx, int l0, int nload, int xmode, const T* src
   {
     Scope sc(ctx, kcls<T>(K_ZG), nl * 2.0 * spec);
     GreenTabs<T> tb{Sel<T>::wt(ctx), ctx->wstride, {Sel<T>::tw(ctx, 0), Sel<T>::tw(ctx, 1), Sel<T>::tw(ctx, 2)},
-                    Sel<T>::gtab(ctx)};
+                    Sel<T>::gtab(ctx), Sel<T>::gst(ctx)};
     STCHK(check_launch(ctx,
                        launch_zg<T>(ctx->stream, g, ctx->gp, tb, gamma ? Z_GAMMA : Z_FWD, sm, sn, Sel<T>::tw(ctx, 2),
                                     st, nload, tv<T>(ctx, PASS_ZG)),
@@ -754,12 +833,12 @@ lsh_status cg_fused_step(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* s
   {
     Scope sc(ctx, kcls<T>(K_ZG), nl * 2.0 * spec);
     GreenTabs<T> tb{Sel<T>::wt(ctx), ctx->wstride, {Sel<T>::tw(ctx, 0), Sel<T>::tw(ctx, 1), Sel<T>::tw(ctx, 2)},
-                    Sel<T>::gtab(ctx)};
+                    Sel<T>::gtab(ctx), Sel<T>::gst(ctx)};
     nbz = launch_zg<T>(ctx->stream, g, ctx->gp, tb, Z_GAMMA, sm, sn, Sel<T>::tw(ctx, 2), st, nload,
                        tv<T>(ctx, PASS_ZG), parts + nbx, (int)ctx->pstride);
     STCHK(check_launch(ctx, nbz, "z/Green"));
   }
-  if (scalars) STCHK(scal(ctx, SC_ALPHA, nload, nbx + nbz, st, 0.0));
+  if (scalars) STCHK(scal(ctx, SC_ALPHA, nload, nbx + nbz, st, ctx->bd_guard[sizeof(T) == 8 ? 1 : 0]));
   {
     Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
     STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, 1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y)),
@@ -922,7 +1001,7 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
     ta.g = ctx->geo;
     ta.gp = ctx->gp;
     ta.tb = GreenTabs<T>{Sel<T>::wt(ctx), ctx->wstride, {Sel<T>::tw(ctx, 0), Sel<T>::tw(ctx, 1), Sel<T>::tw(ctx, 2)},
-                         Sel<T>::gtab(ctx)};
+                         Sel<T>::gtab(ctx), nullptr};
     ta.x = x;
     ta.r = r;
     ta.p = p;
@@ -936,6 +1015,7 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
     ta.vcoef = Sel<T>::vc(ctx);
     ta.st = st;
     ta.maxit = maxit;
+    ta.guard = ctx->bd_guard[sizeof(T) == 8 ? 1 : 0];
     {
       Scope sc(ctx, K_TINY);
       STCHK(check_launch(ctx, launch_tiny_cg<T>(ctx->stream, ta, nload), "persistent CG"));
@@ -947,7 +1027,7 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
     STCHK(forward_part<T>(ctx, 0, nload, XF_CG, r, p, x, nullptr, st, true));
     int np = 0;
     STCHK(inverse_x<T>(ctx, 0, nload, XI_CG, p, q, nullptr, st, ctx->ptr<double>(ctx->off.partials), &np));
-    STCHK(scal(ctx, SC_ALPHA, nload, np, st, 0.0));
+    STCHK(scal(ctx, SC_ALPHA, nload, np, st, ctx->bd_guard[sizeof(T) == 8 ? 1 : 0]));
     return cg_update<T>(ctx, nload, r, q, st);
   };
   const long long key = (long long)nload * 4 + (st_off == ctx->off.st_in ? 1 : 0) + (ctx->cg_fused ? 2 : 0);
@@ -1417,9 +1497,15 @@ lsh_status lsh_bind_workspace(lsh_ctx* ctx, void* dev_ptr, size_t bytes) {
                 "a device phase map or per-voxel moduli must be set again after rebinding the workspace");
   ctx->ws = static_cast<char*>(dev_ptr);
   ctx->ws_size = bytes;
+  {
+    hipPointerAttribute_t attr;
+    ctx->ws_device = hipPointerGetAttributes(&attr, dev_ptr) == hipSuccess ? attr.device : -1;
+    (void)hipGetLastError();
+  }
   ctx->graph_epoch++;
   ctx->consts_ready = false;
   ctx->tables_dirty = true;
+  ctx->gst_dirty = true;
   ctx->phase_dirty = ctx->have_phase;
   ctx->have_solution = false;
   return LSH_OK;
@@ -1452,6 +1538,7 @@ lsh_status lsh_set_reference(lsh_ctx* ctx, const double* A0) {
   }
   ctx->A0.assign(A0, A0 + c * c);
   ctx->have_ref = true;
+  ctx->gst_dirty = true;
   if (ctx->mat_voxel) ctx->have_phase = false;  // per-voxel coefficients were formed against the old A0
   ctx->tables_dirty = true;
   ctx->have_solution = false;
@@ -1479,6 +1566,17 @@ lsh_status lsh_set_phases(lsh_ctx* ctx, const uint8_t* phase, int mem, int nphas
     ctx->phase_dev_src = nullptr;
   } else {
     if (!ctx->ws) return fail(ctx, LSH_ESTATE, "bind the workspace before passing a device phase map");
+    // ids are checked on the device before the map is accepted (the flag
+    // lives in the reduction-results slot of the workspace)
+    int* flag = ctx->ptr<int>(ctx->off.sums);
+    HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
+    const long long nb = std::min<long long>(((long long)V + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_phase_check, dim3((unsigned)nb), dim3(256), 0, ctx->stream, phase, (long long)V, nphase, flag);
+    STCHK(check_launch(ctx, 0, "phase check"));
+    int hflag = 0;
+    HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (hflag != 0) return fail(ctx, LSH_EINVAL, "device phase map holds an id >= nphase");
     ctx->phase_host.clear();
     ctx->phase_dev_src = phase;
   }
@@ -1597,6 +1695,7 @@ lsh_status lsh_set_green(lsh_ctx* ctx, int variant) {
     return fail(ctx, LSH_EINVAL, "the finite-difference operator is defined for scalar problems only");
   ctx->green = variant;
   ctx->tables_dirty = true;
+  ctx->gst_dirty = true;
   ctx->have_solution = false;
   return LSH_OK;
 }
@@ -1730,6 +1829,10 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
     // from initial guesses the first pass is the refinement alone (d = 0):
     // r = b - L x64 in FP64, then the inner solve restarts from it
     bool refine_first = any_guess(ctx, nload);
+    // breakdown or non-finite values met by a load's inner solve end that load
+    // (with that status) once its progress so far is refined into x64
+    std::vector<int> inner_bad(nload, 0);
+    bool stalled = false;
     while (true) {
       if (!refine_first) {
         // inner FP32 solve, then refresh the residual in FP64 (x64 += d inside)
@@ -1740,8 +1843,13 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
           iters[l] += hin[l].iters;
           apps32 += hin[l].iters;
           used = std::max(used, hin[l].iters);
+          if (hst[l].active && hin[l].status != kStatusOk) inner_bad[l] = hin[l].status;
         }
-        budget -= used;
+        // every pass costs budget, and a pass in which no inner solve moved
+        // (all stopped at once: breakdown, NaN/Inf, or an FP32 residual that
+        // vanished while the FP64 one did not) is the last
+        budget -= std::max(used, 1);
+        stalled = used == 0;
       }
       refine_first = false;
       ctx->nact = 0;
@@ -1753,6 +1861,18 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
       STCHK(scal(ctx, SC_OUTER, nload, np, sto, 0.0));
       ++outer;
       STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
+      bool ended = false;
+      for (int l = 0; l < nload; ++l)
+        if (hst[l].active && inner_bad[l] != kStatusOk) {
+          hst[l].active = 0;
+          hst[l].status = inner_bad[l];
+          ended = true;
+        }
+      if (ended) {
+        HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.st_out, hst.data(), sizeof(LoadState) * nload,
+                              hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+      }
       bool any = false;
       double worst = 0.0;
       for (int l = 0; l < nload; ++l) {
@@ -1761,7 +1881,7 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
           worst = std::max(worst, std::sqrt(hst[l].res2 / hst[l].bb));
         }
       }
-      if (!any || budget <= 0) break;
+      if (!any || budget <= 0 || stalled) break;
       eta = std::max(1e-4, 0.5 * tol / std::max(worst, 1e-300));
       eta = std::min(eta, 0.5);
       // restart the inner solve on the loads still refining

@@ -361,13 +361,16 @@ static __global__ __launch_bounds__(256) void k_scal(const int mode, const doubl
   if (mode == SC_ALPHA) {
     L.pq = S;
     // p.Lp may be negative when A0 lies between the phases (indefinite
-    // system): CG proceeds; it breaks down only when p.Lp vanishes.
+    // system): CG proceeds; it breaks down when p.Lp is at rounding level,
+    // |p.Lp| <= g r.r with g = eps ||L|| from the host (tol argument): the
+    // Rayleigh quotient of p (p.p >= r.r) is then below eps times the bound
+    // of the operator, beyond what the field precision resolves.
     // the previous step (if any) was applied to x by this iteration's x pass
     L.pending = 0;
     if (!isfinite(S)) {
       L.status = kStatusNumeric;
       L.active = 0;
-    } else if (S == 0.0) {
+    } else if (fabs(S) <= tol * L.rr) {
       L.status = kStatusBreakdown;
       L.active = 0;
     } else {

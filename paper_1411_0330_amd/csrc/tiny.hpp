@@ -32,6 +32,7 @@ struct TinyArgs {
   const T* vcoef;
   LoadState* st;
   int maxit;
+  double guard;   // CG breakdown when |p.Lp| <= guard r.r (see k_scal)
 };
 
 // workgroup sum of one double, returned to every thread (fixed order)
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(NT) void k_tiny_cg(const TinyArgs<T> a) {
       status = kStatusNumeric;
       break;
     }
-    if (pq == 0.0) {
+    if (fabs(pq) <= a.guard * rr) {
       status = kStatusBreakdown;
       break;
     }

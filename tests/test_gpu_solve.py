@@ -227,7 +227,10 @@ def test_fd_and_consistent_solves_match_oracle(lsh):
 
 def test_full_size_elastic_rsa_256_mixed_against_fp64_and_bounds(lsh, tmp_path):
     # the benchmark's workload and launch configuration: 256^3, six loads, filtered, mixed CG to 1e-6,
-    # kernel shapes from the committed autotuner cache (a copy, so that nothing writes the package file)
+    # kernel shapes from the committed autotuner cache (a copy, so that nothing writes the package file).
+    # The oracle cannot solve 256^3 in a test; the reference is the GPU's FP64 path solved to 1e-10, whose
+    # kernels are oracle-pinned at 64^3 and 128^3 (A* within 1e-10) and at this size by the plane-wave
+    # operator test (1e-11).  Target: the mixed A* within 1e-6 of it (max|dC*| / max|C*|, Theorem 4).
     w = I.elastic_rsa_workload(256, tol=1e-6)
     import shutil
     import torch
@@ -236,7 +239,7 @@ def test_full_size_elastic_rsa_256_mixed_against_fp64_and_bounds(lsh, tmp_path):
                              "tune_cache.txt"), cache)
     phase_dev = torch.from_numpy(w.phase).to("cuda:0")
     res = {}
-    for precision, tol in (("mixed", 1e-6), ("fp64", 1e-9)):
+    for precision, tol in (("mixed", 1e-6), ("fp64", 1e-10)):
         ctx = lsh.Context(w.phase.shape, "elastic", precision, max_loads=6)
         ctx.set_reference(w.A0)
         ctx.set_phases(phase_dev, w.moduli)
@@ -250,7 +253,7 @@ def test_full_size_elastic_rsa_256_mixed_against_fp64_and_bounds(lsh, tmp_path):
         del ctx
         torch.cuda.empty_cache()
     C, C64 = res["mixed"], res["fp64"]
-    assert rel_max_err(C, C64) <= 1e-5
+    assert rel_max_err(C, C64) <= 1e-6
     assert np.abs(C64 - C64.T).max() <= 1e-7 * np.abs(C64).max()
     # Voigt and Reuss bounds of the discrete problem (A0 softer than both phases)
     f = float(w.phase.mean())
