@@ -334,14 +334,21 @@ lsh_status lsh_get_variants(const lsh_ctx* ctx, int32_t* variants);
 lsh_status lsh_autotune(lsh_ctx* ctx, int nload, const char* cache_path, int32_t* variants, int* from_cache);
 
 /*
- * Ensembles: solve n independent contexts (distinct, typically one
- * microstructure each, each on its own HIP stream of default priority) with
- * lsh_solve from a pool of nthreads host threads (< 1: 4), so that the work of
- * small grids overlaps on the GPU.  Per context i: nloads[i], loads[i],
- * reports[i] (array of nloads[i] lsh_load_report, or reports NULL),
- * summaries[i] and statuses[i] (each array may be NULL).  Returns the first
- * error status, else LSH_MAXIT if any context stopped at maxit, else LSH_OK.
- * Contexts sharing one stream are still correct but serialise.
+ * Ensembles (the stochastic-homogenisation use of Section 2.1: one
+ * microstructure per member): solve n independent contexts (distinct, each on
+ * its own HIP stream of default priority) as lsh_solve would, each, so that the
+ * work of small grids overlaps on the GPU.  The solves run as cooperative
+ * fibers on the calling thread: up to nthreads members are in flight (< 1:
+ * 4); a member runs until it waits for the GPU (its solver states or results),
+ * then the next one enqueues its work.  Every HIP call is made from the calling
+ * thread, one member at a time (no concurrent graph captures), and each
+ * member's sequence of launches is the one of its own lsh_solve, so results
+ * equal those of solving the members one after another.  Per context i:
+ * nloads[i], loads[i], reports[i] (array of nloads[i] lsh_load_report, or
+ * reports NULL), summaries[i] and statuses[i] (each array may be NULL).
+ * Returns the first error status, else LSH_MAXIT if any context stopped at
+ * maxit, else LSH_OK.  Contexts sharing one stream are still correct but
+ * serialise.  Not reentrant from within an ensemble solve.
  */
 lsh_status lsh_solve_many(int n, lsh_ctx* const* ctxs, int solver, const int32_t* nloads,
                           const double* const* loads, double tol, int maxit,

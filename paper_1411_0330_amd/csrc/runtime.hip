@@ -11,12 +11,16 @@
 #include <atomic>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <sstream>
 #include <string>
 #include <thread>
 #include <vector>
+
+#include <sys/mman.h>
+#include <ucontext.h>
 
 #include "dispatch.hpp"
 #include "solver_kernels.hpp"
@@ -174,6 +178,11 @@ struct lsh_ctx {
   char* ws = nullptr;
   size_t ws_need = 0, ws_size = 0;
   int ws_device = -1;   // device holding the workspace (-1: unknown)
+  // pinned host staging of the state and result reads (the solver scalars
+  // and sums come back through it without blocking the host thread), and the
+  // event a wait records
+  void* hpin = nullptr;
+  hipEvent_t wait_ev = nullptr;
   // spectrum buffers used instead of the workspace's while set (the
   // allocation-free operator: main spectrum in the caller's output, Nyquist
   // plane in the per-device scratch array)
@@ -305,6 +314,82 @@ void drain_timers(lsh_ctx* ctx) {
   ctx->pending.clear();
 }
 
+// ------------------------- waits and the ensemble fibers ----------------
+// lsh_solve_many runs the solves of an ensemble as fibers (user-level
+// contexts) on the calling thread.  Every wait for the GPU inside a solve
+// (wait_stream) records an event on the context's stream and, inside a
+// fiber, hands the thread to the next fiber until the event has passed; so
+// the members' kernels overlap on their own streams while every HIP call
+// comes from one host thread, one member at a time.
+struct Fiber {
+  ucontext_t uc{};
+  void* stack = nullptr;
+  size_t stack_bytes = 0;
+  bool done = false;
+  std::function<void()> body;
+};
+
+struct FiberSched {
+  ucontext_t main{};
+  Fiber* cur = nullptr;
+};
+thread_local FiberSched t_fibers;
+
+void fiber_yield() {
+  Fiber* f = t_fibers.cur;
+  if (f) swapcontext(&f->uc, &t_fibers.main);
+}
+
+void fiber_entry() {
+  Fiber* f = t_fibers.cur;
+  f->body();
+  f->done = true;
+  swapcontext(&f->uc, &t_fibers.main);
+}
+
+// Wait until the work queued on the context's stream has finished.
+lsh_status wait_stream(lsh_ctx* ctx) {
+  if (t_fibers.cur == nullptr) {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return LSH_OK;
+  }
+  if (!ctx->wait_ev) HIPCHK(hipEventCreateWithFlags(&ctx->wait_ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(ctx->wait_ev, ctx->stream));
+  while (true) {
+    const hipError_t q = hipEventQuery(ctx->wait_ev);
+    if (q == hipSuccess) break;
+    if (q != hipErrorNotReady) return fail(ctx, LSH_EHIP, std::string("event query: ") + hipGetErrorString(q));
+    fiber_yield();
+    if (ctx->ws_device >= 0) {
+      int cur = -1;
+      if (hipGetDevice(&cur) == hipSuccess && cur != ctx->ws_device) HIPCHK(hipSetDevice(ctx->ws_device));
+    }
+  }
+  return LSH_OK;
+}
+
+// Pinned staging: the LoadState records of max_loads loads, then max_loads c doubles.
+lsh_status pinned(lsh_ctx* ctx, void** out) {
+  if (!ctx->hpin) {
+    const size_t bytes = sizeof(LoadState) * ctx->max_loads + sizeof(double) * ctx->max_loads * ctx->c;
+    HIPCHK(hipHostMalloc(&ctx->hpin, bytes, hipHostMallocDefault));
+  }
+  *out = ctx->hpin;
+  return LSH_OK;
+}
+
+// Copy n bytes from the device into host memory h through the pinned staging
+// (at byte offset `at` of it), waiting with wait_stream.
+lsh_status read_back(lsh_ctx* ctx, void* h, const void* dev, size_t n, size_t at) {
+  void* p = nullptr;
+  STCHK(pinned(ctx, &p));
+  char* stage = static_cast<char*>(p) + at;
+  HIPCHK(hipMemcpyAsync(stage, dev, n, hipMemcpyDeviceToHost, ctx->stream));
+  STCHK(wait_stream(ctx));
+  std::memcpy(h, stage, n);
+  return LSH_OK;
+}
+
 // ------------------------- layout ----------------------------------------
 // grids whose z pass has a stored-operator instance
 bool gst_shape(const lsh_ctx* ctx) { return ctx->dim == 3 && ctx->n[2] > 1 && (ctx->c == 3 || ctx->c == 6); }
@@ -419,7 +504,7 @@ lsh_status upload_consts(lsh_ctx* ctx) {
                         hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.wt32, ctx->h_wt32.data(), ctx->h_wt32.size() * sizeof(float),
                         hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  STCHK(wait_stream(ctx));
   ctx->consts_ready = true;
   return LSH_OK;
 }
@@ -573,7 +658,7 @@ lsh_status build_tables(lsh_ctx* ctx) {
     STCHK(check_launch(ctx, 0, "stored Green operator"));
     ctx->gst_dirty = false;
   }
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  STCHK(wait_stream(ctx));
   ctx->tables_dirty = false;
   ctx->graph_epoch++;
   return LSH_OK;
@@ -626,7 +711,7 @@ lsh_status prepare(lsh_ctx* ctx) {
       HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.phase, ctx->phase_host.data(), V, hipMemcpyHostToDevice,
                             ctx->stream));
     }
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    STCHK(wait_stream(ctx));
     ctx->phase_dev_src = nullptr;
     ctx->phase_dirty = false;
   }
@@ -934,9 +1019,7 @@ lsh_status cg_flush(lsh_ctx* ctx, int nload, T* x, const T* p, LoadState* st) {
 
 lsh_status read_states(lsh_ctx* ctx, size_t off, int nload, std::vector<LoadState>& h) {
   h.resize(nload);
-  HIPCHK(hipMemcpyAsync(h.data(), ctx->ws + off, sizeof(LoadState) * nload, hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  return LSH_OK;
+  return read_back(ctx, h.data(), ctx->ws + off, sizeof(LoadState) * nload, 0);
 }
 
 int check_period(lsh_ctx* ctx, int nload) {
@@ -1247,9 +1330,8 @@ lsh_status effective(lsh_ctx* ctx, int nload) {
   }
   STCHK(scal(ctx, SC_SUM, nload * ctx->c, nb, nullptr, 0.0));
   std::vector<double> sums((size_t)nload * ctx->c);
-  HIPCHK(hipMemcpyAsync(sums.data(), ctx->ws + ctx->off.sums, sums.size() * sizeof(double), hipMemcpyDeviceToHost,
-                        ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  STCHK(read_back(ctx, sums.data(), ctx->ws + ctx->off.sums, sums.size() * sizeof(double),
+                  sizeof(LoadState) * ctx->max_loads));
   const int c = ctx->c;
   ctx->sigma.assign((size_t)nload * c, 0.0);
   for (int l = 0; l < nload; ++l)
@@ -1314,7 +1396,8 @@ std::string tune_key(const lsh_ctx* ctx, int nload) {
   std::ostringstream k;
   k << "gfx950 " << ctx->n[0] << "x" << ctx->n[1] << "x" << ctx->n[2] << " c" << ctx->c
     << (ctx->precision == LSH_MIXED ? " mixed" : " fp64") << " L" << nload << " green" << ctx->green
-    << (ctx->mat_voxel ? " voxel" : (ctx->iso ? " iso" : " full"));
+    << (ctx->mat_voxel ? " voxel" : (ctx->iso ? " iso" : " full"))
+    << ((Sel<float>::gst(const_cast<lsh_ctx*>(ctx)) || Sel<double>::gst(const_cast<lsh_ctx*>(ctx))) ? " stored" : "");
   return k.str();
 }
 
@@ -1476,6 +1559,8 @@ lsh_status lsh_destroy(lsh_ctx* ctx) {
   for (auto& G : ctx->graphs)
     if (G.exec) (void)hipGraphExecDestroy(G.exec);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->wait_ev) (void)hipEventDestroy(ctx->wait_ev);
+  if (ctx->hpin) (void)hipHostFree(ctx->hpin);
   delete ctx;
   return LSH_OK;
 }
@@ -1871,7 +1956,7 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
       if (ended) {
         HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.st_out, hst.data(), sizeof(LoadState) * nload,
                               hipMemcpyHostToDevice, ctx->stream));
-        HIPCHK(hipStreamSynchronize(ctx->stream));
+        STCHK(wait_stream(ctx));
       }
       bool any = false;
       double worst = 0.0;
@@ -1904,7 +1989,7 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
       if (patched) {
         HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.st_in, hin.data(), sizeof(LoadState) * nload,
                               hipMemcpyHostToDevice, ctx->stream));
-        HIPCHK(hipStreamSynchronize(ctx->stream));
+        STCHK(wait_stream(ctx));
       }
     }
     for (int l = 0; l < nload; ++l) {
@@ -1921,9 +2006,8 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
   if (!residual_known) {
     STCHK(true_residual(ctx, nload));
     std::vector<double> s(nload);
-    HIPCHK(hipMemcpyAsync(s.data(), ctx->ws + ctx->off.sums, sizeof(double) * nload, hipMemcpyDeviceToHost,
-                          ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    STCHK(read_back(ctx, s.data(), ctx->ws + ctx->off.sums, sizeof(double) * nload,
+                    sizeof(LoadState) * ctx->max_loads));
     STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
     for (int l = 0; l < nload; ++l) {
       res2[l] = s[l];
@@ -2234,27 +2318,61 @@ lsh_status lsh_solve_many(int n, lsh_ctx* const* ctxs, int solver, const int32_t
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == ctxs[i]) return fail(ctxs[i], LSH_EINVAL, "a context appears twice in one ensemble solve");
   }
-  if (nthreads < 1) nthreads = 4;
-  nthreads = std::min(nthreads, n);
+  if (t_fibers.cur != nullptr) return fail(ctxs[0], LSH_ESTATE, "lsh_solve_many called from inside an ensemble solve");
+  const int slots = std::min(std::max(nthreads, 1), n);
   std::vector<lsh_status> st(n, LSH_OK);
-  std::atomic<int> next{0};
-  auto worker = [&]() {
-    while (true) {
-      const int i = next.fetch_add(1);
-      if (i >= n) break;
-      lsh_ctx* c = ctxs[i];
-      // the worker runs on the device that holds the context's workspace
-      if (c->ws) {
-        hipPointerAttribute_t attr;
-        if (hipPointerGetAttributes(&attr, c->ws) == hipSuccess) (void)hipSetDevice(attr.device);
-      }
-      st[i] = lsh_solve(c, solver, nloads[i], loads[i], tol, maxit, reports ? reports[i] : nullptr,
-                        summaries ? &summaries[i] : nullptr);
+  // one member at a time per slot; a slot is a fiber with its own stack
+  // (reserved address space with a guard page, pages committed on use)
+  constexpr size_t kStack = 16u << 20, kGuard = 64u << 10;
+  std::vector<Fiber> fib(slots);
+  int next = 0;
+  bool setup_ok = true;
+  for (auto& f : fib) {
+    void* mem = mmap(nullptr, kStack, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS | MAP_NORESERVE, -1, 0);
+    if (mem == MAP_FAILED) {
+      setup_ok = false;
+      break;
     }
-  };
-  std::vector<std::thread> pool;
-  for (int t = 0; t < nthreads; ++t) pool.emplace_back(worker);
-  for (auto& th : pool) th.join();
+    (void)mprotect(mem, kGuard, PROT_NONE);
+    f.stack = mem;
+    f.stack_bytes = kStack;
+    f.body = [&]() {
+      while (true) {
+        const int i = next++;
+        if (i >= n) break;
+        lsh_ctx* c = ctxs[i];
+        if (c->ws_device >= 0) {
+          int cur = -1;
+          if (hipGetDevice(&cur) == hipSuccess && cur != c->ws_device) (void)hipSetDevice(c->ws_device);
+        }
+        st[i] = lsh_solve(c, solver, nloads[i], loads[i], tol, maxit, reports ? reports[i] : nullptr,
+                          summaries ? &summaries[i] : nullptr);
+      }
+    };
+    getcontext(&f.uc);
+    f.uc.uc_stack.ss_sp = static_cast<char*>(mem) + kGuard;
+    f.uc.uc_stack.ss_size = kStack - kGuard;
+    f.uc.uc_link = nullptr;
+    makecontext(&f.uc, fiber_entry, 0);
+  }
+  if (setup_ok) {
+    // round robin over the slots until every member is solved; each turn runs
+    // a fiber up to its next wait for the GPU
+    bool any = true;
+    while (any) {
+      any = false;
+      for (auto& f : fib) {
+        if (f.done) continue;
+        any = true;
+        t_fibers.cur = &f;
+        swapcontext(&t_fibers.main, &f.uc);
+        t_fibers.cur = nullptr;
+      }
+    }
+  }
+  for (auto& f : fib)
+    if (f.stack) munmap(f.stack, f.stack_bytes);
+  if (!setup_ok) return fail(ctxs[0], LSH_ENOMEM, "cannot reserve fiber stacks");
   lsh_status overall = LSH_OK;
   for (int i = 0; i < n; ++i) {
     if (statuses) statuses[i] = st[i];
