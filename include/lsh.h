@@ -290,6 +290,26 @@ lsh_status lsh_gradient(lsh_ctx* ctx, const double* W, void* grad, int dtype);
 lsh_status lsh_apply(lsh_ctx* ctx, int nload, const void* tau, void* out, int dtype);
 
 /*
+ * lsh_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same operator and kernels, with no scratch taken from the workspace.  The
+ * main spectrum is formed in `out` itself (it has exactly the bytes of the
+ * real output) and the Nyquist plane (kx = nx/2; nload * c * nz * ny complex
+ * values of dtype) in a fixed per-GPU scratch array of 64 MiB, a device
+ * global of the library that every GPU it runs on holds until the process
+ * ends; larger planes return LSH_ENOMEM before any GPU work.  Material
+ * tables are formed on first use after a change, as by lsh_apply; the
+ * solution fields of the workspace are not touched, so the last solve's
+ * results stay available.  `out` must be 256-byte aligned.  The call
+ * makes no device allocation (no hipMalloc, no allocating library call); the
+ * first call on a device looks up the scratch address once.  The scratch
+ * holds the last call's plane and needs no clearing (every entry is written
+ * before it is read); calls that overlap in time on one GPU (other streams or
+ * threads) share it and race.  Blocks until the result is in `out`.
+ */
+lsh_status lsh_apply_noalloc(lsh_ctx* ctx, int nload, const void* tau, void* out, int dtype);
+
+/*
  * Forward DFT of nload real fields (device, [load][component][z][y][x],
  * dtype LSH_F64/LSH_F32) into the library's packed half spectrum, copied to
  * `spec` (device): complex [load][component][nz][ny][nx/2] (interleaved

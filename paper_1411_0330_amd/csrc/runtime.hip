@@ -1505,6 +1505,42 @@ lsh_status voxel_setup(lsh_ctx* ctx, const TI* m, bool count_only, long long* nb
   return LSH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free operator (lsh_apply_noalloc): the Nyquist
+// plane of the spectrum (the main spectrum occupies exactly the caller's
+// output buffer).  A file-scope device array: every GPU the library runs on
+// holds one copy of kScratchBytes until the process ends.  Host code never
+// uses the array's name as an address (it is a host-side stand-in): the
+// device address comes from hipGetSymbolAddress, once per device with that
+// device current, and is kept per device.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {nullptr};
+
+lsh_status scratch_address(lsh_ctx* ctx, void** out) {
+  int dev = ctx->ws_device;
+  if (dev < 0) HIPCHK(hipGetDevice(&dev));
+  if (dev >= kMaxDevices) return fail(ctx, LSH_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev] == nullptr) {
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != dev) HIPCHK(hipSetDevice(dev));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || p == nullptr)
+      return fail(ctx, LSH_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return LSH_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -2151,6 +2187,45 @@ lsh_status lsh_apply(lsh_ctx* ctx, int nload, const void* tau, void* out, int dt
                            nullptr, nullptr, nullptr));
   }
   ctx->have_solution = false;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return LSH_OK;
+}
+
+lsh_status lsh_apply_noalloc(lsh_ctx* ctx, int nload, const void* tau, void* out, int dtype) {
+  if (!ctx) return LSH_EINVAL;
+  if (nload < 1 || nload > ctx->max_loads) return fail(ctx, LSH_EINVAL, "nload out of range");
+  if (!tau || !out || tau == out) return fail(ctx, LSH_EINVAL, "bad buffers");
+  if (reinterpret_cast<uintptr_t>(out) % kAlign != 0) return fail(ctx, LSH_EINVAL, "out not 256-byte aligned");
+  if (dtype != LSH_F64 && dtype != LSH_F32) return fail(ctx, LSH_EINVAL, "bad dtype");
+  if (dtype == LSH_F32 && ctx->precision != LSH_MIXED)
+    return fail(ctx, LSH_EINVAL, "FP32 application needs a mixed-precision context");
+  const size_t nyq = (size_t)nload * nyq_cpx(ctx->geo) * (dtype == LSH_F64 ? 16 : 8);
+  if (nyq > kScratchBytes)
+    return fail(ctx, LSH_ENOMEM, "the Nyquist plane of " + std::to_string(nload) + " loads needs " +
+                                     std::to_string(nyq) + " bytes, beyond the " + std::to_string(kScratchBytes) +
+                                     "-byte scratch of lsh_apply_noalloc");
+  STCHK(prepare(ctx));
+  void* sp = nullptr;
+  STCHK(scratch_address(ctx, &sp));
+  ctx->ovr_sm = out;
+  ctx->ovr_sn = sp;
+  lsh_status s;
+  if (dtype == LSH_F64) {
+    s = forward_part<double>(ctx, 0, nload, XF_PLAIN, static_cast<const double*>(tau), nullptr, nullptr, nullptr,
+                             nullptr, true);
+    if (s == LSH_OK)
+      s = inverse_x<double>(ctx, 0, nload, XI_APPLY, static_cast<const double*>(tau), static_cast<double*>(out),
+                            nullptr, nullptr, nullptr, nullptr);
+  } else {
+    s = forward_part<float>(ctx, 0, nload, XF_PLAIN, static_cast<const float*>(tau), nullptr, nullptr, nullptr,
+                            nullptr, true);
+    if (s == LSH_OK)
+      s = inverse_x<float>(ctx, 0, nload, XI_APPLY, static_cast<const float*>(tau), static_cast<float*>(out), nullptr,
+                           nullptr, nullptr, nullptr);
+  }
+  ctx->ovr_sm = nullptr;
+  ctx->ovr_sn = nullptr;
+  STCHK(s);
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return LSH_OK;
 }

@@ -67,6 +67,7 @@ _SIGS = {
     "lsh_set_initial_guess": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_int]),
     "lsh_get_effective": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "lsh_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
+    "lsh_apply_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "lsh_forward_dft": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "lsh_spectrum_bytes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_size_t)]),
     "lsh_set_variant": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
