@@ -26,8 +26,14 @@ FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
          "-I", CSRC, "-I", INCLUDE]
 
 UNITS = [
-    ("k_x.hip", "k_x_f32.o", ["-DLSH_X_TYPE=float"]),
-    ("k_x.hip", "k_x_f64.o", ["-DLSH_X_TYPE=double"]),
+    ("k_x.hip", "k_x_f32.o", ["-DLSH_X_TYPE=float", "-DLSH_X_PART=0"]),
+    ("k_x.hip", "k_x_f64.o", ["-DLSH_X_TYPE=double", "-DLSH_X_PART=0"]),
+    ("k_x.hip", "k_xi2_f32.o", ["-DLSH_X_TYPE=float", "-DLSH_X_PART=2"]),
+    ("k_x.hip", "k_xi2_f64.o", ["-DLSH_X_TYPE=double", "-DLSH_X_PART=2"]),
+    ("k_x.hip", "k_xi3_f32.o", ["-DLSH_X_TYPE=float", "-DLSH_X_PART=3"]),
+    ("k_x.hip", "k_xi3_f64.o", ["-DLSH_X_TYPE=double", "-DLSH_X_PART=3"]),
+    ("k_x.hip", "k_xi6_f32.o", ["-DLSH_X_TYPE=float", "-DLSH_X_PART=6"]),
+    ("k_x.hip", "k_xi6_f64.o", ["-DLSH_X_TYPE=double", "-DLSH_X_PART=6"]),
     ("k_xc.hip", "k_xc_f32.o", ["-DLSH_XC_TYPE=float"]),
     ("k_xc.hip", "k_xc_f64.o", ["-DLSH_XC_TYPE=double"]),
     ("k_y.hip", "k_y_f32.o", ["-DLSH_Y_TYPE=float"]),

@@ -121,6 +121,8 @@ inline bool tiny_grid(const Geo& g) {
   return (g.nx == 8 && (g.c == 3 || g.c == 6)) || (g.nx == 16 && g.c == 3);
 }
 template <typename T> int launch_xinv(hipStream_t s, const XinvArgs<T>& a, int nload, int variant = 0);
+// the C2R pass of C components (launch_xinv dispatches on the component count)
+template <typename T, int C> int launch_xinv_c(hipStream_t s, const XinvArgs<T>& a, int nload, int variant);
 
 // strided-pass shape of a variant: (pencils per workgroup, points per thread)
 template <typename T> constexpr int sv_tx(int n, int p0, int v) {

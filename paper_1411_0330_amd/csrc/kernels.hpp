@@ -1186,6 +1186,12 @@ __device__ __forceinline__ double2 vaxpy(double2 x, double s, double2 y) {
 
 constexpr int kEwUnroll = 4;
 
+// Workgroups per load (or per component group) of the grid-stride
+// initialisation and mean passes over n elements: at least 1024 elements per
+// workgroup, at most 1024 workgroups, so that each workgroup's fixed cost
+// (its reduction) is amortised; every count stays within the partials stride.
+inline int ew_blocks(long long n) { return (int)std::min<long long>((n + 1023) / 1024, 1024); }
+
 // r -= alpha q;  partial r.r      (per load, 16-byte vectors; x is updated
 // one step later inside the x forward pass, or by k_xflush)
 template <typename T>
@@ -1245,17 +1251,15 @@ __global__ __launch_bounds__(256) void k_cginit(const Geo g, T* __restrict__ x, 
   const int l = blockIdx.y;
   const long long F = field_elems(g);
   double part = 0.0;
-  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
-#pragma unroll
-  for (int u = 0; u < kEwUnroll; ++u) {
-    const long long e = b0 + (long long)u * 256;
-    if (e < F) {
-      const int j = (int)(e / g.nvox);
-      const long long vox = e - (long long)j * g.nvox;
-      const bool inside = vcoef != nullptr ? vcoef[vox] != 0.0 : i0[phase[vox]] != 0;
+  // grid-stride over the voxels (ew_blocks workgroups per load), all
+  // components of a voxel by one thread: one I0 test per voxel
+  for (long long v = (long long)blockIdx.x * 256 + threadIdx.x; v < g.nvox; v += (long long)gridDim.x * 256) {
+    const bool inside = vcoef != nullptr ? vcoef[v] != 0.0 : i0[phase[v]] != 0;
+    for (int j = 0; j < g.c; ++j) {
       const T val = inside ? static_cast<T>(loads[l * g.c + j]) : T(0);
-      if (x != nullptr) x[(long long)l * F + e] = T(0);
-      if (r != nullptr) r[(long long)l * F + e] = val;
+      const long long e = (long long)l * F + (long long)j * g.nvox + v;
+      if (x != nullptr) x[e] = T(0);
+      if (r != nullptr) r[e] = val;
       part += (double)val * val;
     }
   }
@@ -1275,14 +1279,10 @@ __global__ __launch_bounds__(256) void k_guessmask(const Geo g, T* __restrict__ 
   bool nonzero = false;
   for (int j = 0; j < g.c; ++j) nonzero |= loads[l * g.c + j] != 0.0;
   const bool guessed = gflag[l] != 0 && nonzero;
-  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
-#pragma unroll
-  for (int u = 0; u < kEwUnroll; ++u) {
-    const long long e = b0 + (long long)u * 256;
-    if (e < F) {
-      const long long vox = e % g.nvox;
-      const bool inside = vcoef != nullptr ? vcoef[vox] != 0.0 : i0[phase[vox]] != 0;
-      T* xe = x + (long long)l * F + e;
+  for (long long v = (long long)blockIdx.x * 256 + threadIdx.x; v < g.nvox; v += (long long)gridDim.x * 256) {
+    const bool inside = vcoef != nullptr ? vcoef[v] != 0.0 : i0[phase[v]] != 0;
+    for (int j = 0; j < g.c; ++j) {
+      T* xe = x + (long long)l * F + (long long)j * g.nvox + v;
       *xe = (guessed && inside) ? *xe : T(0);
     }
   }
@@ -1301,17 +1301,13 @@ __global__ __launch_bounds__(256) void k_guessinit(const Geo g, const T* __restr
   const long long F = field_elems(g);
   const bool guessed = gflag[l] != 0;
   double pb = 0.0, pr = 0.0;
-  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
-#pragma unroll
-  for (int u = 0; u < kEwUnroll; ++u) {
-    const long long e = b0 + (long long)u * 256;
-    if (e < F) {
-      const int j = (int)(e / g.nvox);
-      const long long vox = e - (long long)j * g.nvox;
-      const bool inside = vcoef != nullptr ? vcoef[vox] != 0.0 : i0[phase[vox]] != 0;
+  for (long long v = (long long)blockIdx.x * 256 + threadIdx.x; v < g.nvox; v += (long long)gridDim.x * 256) {
+    const bool inside = vcoef != nullptr ? vcoef[v] != 0.0 : i0[phase[v]] != 0;
+    for (int j = 0; j < g.c; ++j) {
+      const long long e = (long long)l * F + (long long)j * g.nvox + v;
       const T bv = inside ? static_cast<T>(loads[l * g.c + j]) : T(0);
-      const T rv = guessed ? bv - q[(long long)l * F + e] : bv;
-      r[(long long)l * F + e] = rv;
+      const T rv = guessed ? bv - q[e] : bv;
+      r[e] = rv;
       pb += (double)bv * bv;
       pr += (double)rv * rv;
     }
@@ -1331,15 +1327,10 @@ __global__ __launch_bounds__(256) void k_innerinit(const long long F, T* __restr
   const int l = blockIdx.y;
   if (!outer[l].active) return;
   double part = 0.0;
-  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
-#pragma unroll
-  for (int u = 0; u < kEwUnroll; ++u) {
-    const long long e = b0 + (long long)u * 256;
-    if (e < F) {
-      d[(long long)l * F + e] = T(0);
-      const double rv = r[(long long)l * F + e];
-      part += rv * rv;
-    }
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < F; e += (long long)gridDim.x * 256) {
+    d[(long long)l * F + e] = T(0);
+    const double rv = r[(long long)l * F + e];
+    part += rv * rv;
   }
   const double s = block_sum<256>(part, red);
   if (threadIdx.x == 0) partials[(long long)l * pstride + blockIdx.x] = s;
@@ -1353,12 +1344,8 @@ __global__ __launch_bounds__(256) void k_mean(const Geo g, const T* __restrict__
   const int grp = blockIdx.y;   // l * c + j
   const T* xp = x + (long long)grp * g.nvox;
   double part = 0.0;
-  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
-#pragma unroll
-  for (int u = 0; u < kEwUnroll; ++u) {
-    const long long e = b0 + (long long)u * 256;
-    if (e < g.nvox) part += (double)xp[e];
-  }
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < g.nvox; e += (long long)gridDim.x * 256)
+    part += (double)xp[e];
   const double s = block_sum<256>(part, red);
   if (threadIdx.x == 0) partials[(long long)grp * pstride + blockIdx.x] = s;
 }

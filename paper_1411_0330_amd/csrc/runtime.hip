@@ -886,18 +886,23 @@ lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T*
   return LSH_OK;
 }
 
-lsh_status scal(lsh_ctx* ctx, int mode, int ngroups, int nparts, LoadState* st, double tol);
+lsh_status scal(lsh_ctx* ctx, int mode, int ngroups, int nparts, LoadState* st, double tol, int l0 = 0);
 
 // One CG step with p.Lp known before the inverse passes: the x pass forms p
 // and sums p.(A - A0)^{-1} p, the z pass sums p.Gamma p over the spectrum
 // (Parseval), alpha follows, and the x-inverse pass updates r in place with
 // ||r||^2; q = Lp is never stored.
+// x, r, p and st are the bases of load 0; the step covers loads [l0, l0 + nload).
 template <typename T>
-lsh_status cg_fused_step(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, bool scalars = true) {
+lsh_status cg_fused_step(lsh_ctx* ctx, int l0, int nload, T* x, T* r, T* p, LoadState* st, bool scalars = true) {
   const Geo& g = ctx->geo;
-  cpx<T>* sm = Sel<T>::sm(ctx);
-  cpx<T>* sn = Sel<T>::sn(ctx);
-  double* parts = ctx->ptr<double>(ctx->off.partials);
+  x += (long long)l0 * ctx->F;
+  r += (long long)l0 * ctx->F;
+  p += (long long)l0 * ctx->F;
+  st += l0;
+  cpx<T>* sm = Sel<T>::sm(ctx) + (long long)l0 * main_cpx(g);
+  cpx<T>* sn = Sel<T>::sn(ctx) + (long long)l0 * nyq_cpx(g);
+  double* parts = ctx->ptr<double>(ctx->off.partials) + (long long)l0 * ctx->pstride;
   const double nl = std::min(ctx->nact, nload);
   const double cvs = (double)ctx->F * sizeof(T);
   const double spec = cvs + 2.0 * sizeof(T) * (double)nyq_cpx(g);
@@ -923,27 +928,29 @@ lsh_status cg_fused_step(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* s
                        tv<T>(ctx, PASS_ZG), parts + nbx, (int)ctx->pstride);
     STCHK(check_launch(ctx, nbz, "z/Green"));
   }
-  if (scalars) STCHK(scal(ctx, SC_ALPHA, nload, nbx + nbz, st, ctx->bd_guard[sizeof(T) == 8 ? 1 : 0]));
+  if (scalars) STCHK(scal(ctx, SC_ALPHA, nload, nbx + nbz, st, ctx->bd_guard[sizeof(T) == 8 ? 1 : 0], l0));
   {
     Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
     STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, 1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y)),
                        "y inverse"));
   }
-  STCHK(inverse_x<T>(ctx, 0, nload, XI_CGR, p, r, nullptr, st, parts, &nbi, r));
-  return scalars ? scal(ctx, SC_BETA, nload, nbi, st, 0.0) : LSH_OK;
+  STCHK(inverse_x<T>(ctx, l0, nload, XI_CGR, p, r, nullptr, st, parts, &nbi, r));
+  return scalars ? scal(ctx, SC_BETA, nload, nbi, st, 0.0, l0) : LSH_OK;
 }
 
-lsh_status scal(lsh_ctx* ctx, int mode, int ngroups, int nparts, LoadState* st, double tol) {
+// groups [l0, l0 + ngroups): the partials of group l at (l0 + l) pstride; st is already offset
+lsh_status scal(lsh_ctx* ctx, int mode, int ngroups, int nparts, LoadState* st, double tol, int l0) {
   Scope sc(ctx, K_SCAL);
-  hipLaunchKernelGGL(k_scal, dim3(ngroups), dim3(256), 0, ctx->stream, mode, ctx->ptr<double>(ctx->off.partials),
-                     (int)ctx->pstride, nparts, st, ctx->ptr<double>(ctx->off.sums), tol);
+  hipLaunchKernelGGL(k_scal, dim3(ngroups), dim3(256), 0, ctx->stream, mode,
+                     ctx->ptr<double>(ctx->off.partials) + (long long)l0 * ctx->pstride, (int)ctx->pstride, nparts,
+                     st, ctx->ptr<double>(ctx->off.sums) + l0, tol);
   return check_launch(ctx, 0, "scalars");
 }
 
 template <typename T>
 lsh_status cg_init(lsh_ctx* ctx, int nload, T* x, T* r, LoadState* st, double tol) {
   const Geo& g = ctx->geo;
-  const int nb = (int)((ctx->F + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
+  const int nb = ew_blocks(g.nvox);
   {
     Scope sc(ctx, K_INIT);
     hipLaunchKernelGGL((k_cginit<T>), dim3(nb, nload), dim3(256), 0, ctx->stream, g, x, r,
@@ -970,7 +977,7 @@ bool any_guess(const lsh_ctx* ctx, int nload) {
 lsh_status guess_init(lsh_ctx* ctx, int nload, double* x, double* r, LoadState* st, double tol) {
   if (!any_guess(ctx, nload)) return cg_init<double>(ctx, nload, x, r, st, tol);
   const Geo& g = ctx->geo;
-  const int nb = (int)((ctx->F + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
+  const int nb = ew_blocks(g.nvox);
   const uint8_t* gflag = ctx->ptr<uint8_t>(ctx->off.guess);
   {
     Scope sc(ctx, K_INIT);
@@ -1106,7 +1113,7 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
     return LSH_OK;
   }
   auto iteration = [&]() -> lsh_status {
-    if (ctx->cg_fused) return cg_fused_step<T>(ctx, nload, x, r, p, st);
+    if (ctx->cg_fused) return cg_fused_step<T>(ctx, 0, nload, x, r, p, st);
     STCHK(forward_part<T>(ctx, 0, nload, XF_CG, r, p, x, nullptr, st, true));
     int np = 0;
     STCHK(inverse_x<T>(ctx, 0, nload, XI_CG, p, q, nullptr, st, ctx->ptr<double>(ctx->off.partials), &np));
@@ -1321,7 +1328,7 @@ lsh_status true_residual(lsh_ctx* ctx, int nload) {
 
 lsh_status effective(lsh_ctx* ctx, int nload) {
   const Geo& g = ctx->geo;
-  const int nb = (int)((g.nvox + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
+  const int nb = ew_blocks(g.nvox);
   {
     Scope sc(ctx, K_MEAN);
     hipLaunchKernelGGL((k_mean<double>), dim3(nb, nload * ctx->c), dim3(256), 0, ctx->stream, g,
@@ -1368,10 +1375,10 @@ int pass_class(int pass, bool fp64) {
 lsh_status timing_iteration(lsh_ctx* ctx, int nload, bool fp64) {
   double* parts = ctx->ptr<double>(ctx->off.partials);
   if (!fp64 && ctx->cg_fused)
-    return cg_fused_step<float>(ctx, nload, ctx->ptr<float>(ctx->off.d32), ctx->ptr<float>(ctx->off.r32),
+    return cg_fused_step<float>(ctx, 0, nload, ctx->ptr<float>(ctx->off.d32), ctx->ptr<float>(ctx->off.r32),
                                 ctx->ptr<float>(ctx->off.p32), ctx->ptr<LoadState>(ctx->off.st_in), false);
   if (fp64 && ctx->cg_fused && ctx->precision != LSH_MIXED)
-    return cg_fused_step<double>(ctx, nload, ctx->ptr<double>(ctx->off.x64), ctx->ptr<double>(ctx->off.r64),
+    return cg_fused_step<double>(ctx, 0, nload, ctx->ptr<double>(ctx->off.x64), ctx->ptr<double>(ctx->off.r64),
                                  ctx->ptr<double>(ctx->off.p64), ctx->ptr<LoadState>(ctx->off.st_out), false);
   if (!fp64) {
     LoadState* st = ctx->ptr<LoadState>(ctx->off.st_in);
@@ -2006,7 +2013,7 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
       eta = std::max(1e-4, 0.5 * tol / std::max(worst, 1e-300));
       eta = std::min(eta, 0.5);
       // restart the inner solve on the loads still refining
-      const int nb = (int)((ctx->F + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
+      const int nb = ew_blocks(ctx->F);
       {
         Scope sc(ctx, K_INIT);
         hipLaunchKernelGGL((k_innerinit<float>), dim3(nb, nload), dim3(256), 0, ctx->stream, (long long)ctx->F, d, r,
