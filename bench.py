@@ -57,6 +57,8 @@ def parse():
                     help="instead: the 48-member lognormal ensemble, sequential vs concurrent streams")
     ap.add_argument("--gradient", action="store_true",
                     help="instead: forward + backward of the 192^3 sensitivity workload (FP64)")
+    ap.add_argument("--boolean", action="store_true",
+                    help="instead: the 128^3 Boolean conduction workload, FP64 CG against mixed precision")
     return ap.parse_args()
 
 
@@ -280,6 +282,51 @@ def bench_ensemble(args):
                    "voxels": int(sum(m.n ** 3 for m in members)), "members_in_flight": 4}}), flush=True)
 
 
+def bench_boolean(args):
+    """128^3 scalar conduction, Boolean model (667 spheres of radius 6, fraction 0.25), contrast
+    100, a0 = 0.5, filtered, the three unit gradients batched: FP64 CG to 1e-10 against FP32
+    fields with FP64 refinement to 1e-8; A* of each against the FP64 solve to 1e-12."""
+    import numpy as np
+    import torch
+
+    from paper_1411_0330_amd import inputs as I
+    from paper_1411_0330_amd import lsh
+
+    lsh.load()
+    w = I.boolean_workload(128)
+    phase_dev = torch.from_numpy(w.phase).to("cuda:0")
+    nvox = int(w.phase.size)
+    out = {"metric": "voxel-iterations/s, 3D conduction 128^3 Boolean, FP64 vs mixed", "unit": "voxel-iterations/s",
+           "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": f"128^3 Boolean model, {w.info['spheres']} spheres r=6 vox, fraction "
+                                  f"{w.info['fraction']:.4f}, a=100/1, a0=0.5, filtered, 3 unit gradients"}}
+    ref = None
+    for precision, tol in (("fp64", 1e-12), ("fp64", 1e-10), ("mixed", 1e-8)):
+        ctx = lsh.Context(w.phase.shape, "scalar", precision, max_loads=3)
+        ctx.set_reference(w.A0)
+        ctx.set_green(w.green)
+        solve_once(ctx, w, phase_dev, tol, 5000)
+        reps = max(1, args.steps)
+        ts, apps = [], 0
+        for _ in range(reps):
+            t, rep, C = solve_once(ctx, w, phase_dev, tol, 5000)
+            ts.append(t)
+        apps = rep["applications_fp32"] + rep["applications_fp64"]
+        t = float(np.median(ts))
+        row = {"tol": tol, "ms_per_solve": round(t * 1e3, 3), "value": apps * nvox / t, "applications": apps,
+               "iterations": rep["iterations"], "rel_residual": max(rep["rel_residual"])}
+        if ref is None:
+            ref = C
+        else:
+            row["A_star_rel_err"] = rel_err(C, ref)
+        out[f"{precision}_{tol:g}"] = row
+        log(f"{precision} tol {tol:g}: {row}")
+        del ctx
+    out["value"] = out["mixed_1e-08"]["value"]
+    out["speedup_mixed_vs_fp64"] = out["fp64_1e-10"]["ms_per_solve"] / out["mixed_1e-08"]["ms_per_solve"]
+    print(json.dumps(out), flush=True)
+
+
 def bench_gradient(args):
     """Forward (batched FP64 solve of e1 and the Mandel shear unit) and backward
     (lsh_gradient through torch.autograd) of J = C*_1111 + C*_1212 at 192^3."""
@@ -349,6 +396,8 @@ def main():
         return bench_ensemble(args)
     if args.gradient:
         return bench_gradient(args)
+    if args.boolean:
+        return bench_boolean(args)
 
     import numpy as np
     import torch

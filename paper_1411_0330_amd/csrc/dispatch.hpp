@@ -26,11 +26,18 @@ template <typename T> constexpr int p_odd(int n, int q) {
   while (q > 2 && (256 * f * q * 2 * (int)sizeof(T) > 48 * 1024 || f * q > 12)) q /= 2;
   return f * cmin(q, pow2_part(n));
 }
-template <typename T> constexpr int p_xfwd(int mx) { return odd_part(mx) > 1 ? p_odd<T>(mx, 4) : cmin(8, mx); }
+// row passes over a power-of-two half row: the most points per thread (at most
+// 8, at least 2) that still leave 128 contiguous bytes per access instruction
+// (16 FP32 or 8 FP64 threads per row); measured at mx = 64 (128^3 scalar, FP32
+// C2R): 8 points per thread, 5.1 TB/s; 4 points, 6.2 TB/s
+template <typename T> constexpr int p_row(int mx) {
+  return cmin(mx, cmax(2, cmin(8, mx / (128 / (2 * (int)sizeof(T))))));
+}
+template <typename T> constexpr int p_xfwd(int mx) { return odd_part(mx) > 1 ? p_odd<T>(mx, 4) : p_row<T>(mx); }
 template <typename T, int C> constexpr int p_xinv(int mx) {
   // six components: fewer points per thread keep the register file for occupancy
   if (odd_part(mx) > 1) return p_odd<T>(mx, C == 6 ? 2 : 4);
-  return cmin(C == 6 ? (sizeof(T) == 8 ? 2 : 4) : 8, mx);
+  return C == 6 ? cmin(sizeof(T) == 8 ? 2 : 4, mx) : p_row<T>(mx);
 }
 template <typename T> constexpr int p_y(int n) {
   return odd_part(n) > 1 ? p_odd<T>(n, 4) : cmin(sizeof(T) == 4 ? 16 : 8, n);
