@@ -27,17 +27,18 @@ namespace lsh {
 struct LoadState {
   double rr;     // r.r of the current residual
   double pq;     // p.Lp
-  double alpha;  // CG step
+  double alpha;  // CG step (of the newest step whose x update is pending)
   double beta;   // CG direction update
   double bb;     // ||b||^2
   double res2;   // last residual norm^2 (basic scheme, refinement)
   double tol2;   // tol^2 ||b||^2
+  double alpha2; // fused CG: step of the older of two pending steps
   int active;    // 1 while the load iterates
   int iters;     // operator applications spent
   int status;    // lsh_status of the load
   int first;     // next CG direction is p = r
-  int pending;   // x += alpha p of the last CG step is still to be applied
-  int pad;
+  int pending;   // CG steps whose x += alpha p is still to be applied (fused step: 0, 1 or 2)
+  int pbuf;      // fused step: direction buffer (0/1) holding the newest pending direction
 };
 
 struct Geo {
@@ -313,16 +314,22 @@ __device__ __forceinline__ T loc_row(const Loc<T>& L, bool vm, int which, bool i
 
 // ----------------------------------------------------------------------------
 // x forward for conjugate gradients with all c components of a voxel row in one
-// thread group: x += alpha p (the previous step, when pending), p = r + beta p,
-// the R2C transforms of every component, and the local quadratic form
-// p . (A - A0)^{-1} p (one FP64 partial per workgroup).  With the spectral form
-// of the z pass this gives p . Lp before the inverse passes run.
+// thread group: p_k = r + beta p_{k-1}, the R2C transforms of every component,
+// and the local quadratic form p . (A - A0)^{-1} p (one FP64 partial per
+// workgroup).  With the spectral form of the z pass this gives p . Lp before
+// the inverse passes run.  The directions alternate between two buffers (pin
+// holds p_{k-1}, pout p_{k-2} on entry and p_k on exit), and the solution
+// updates of the steps are applied in pairs: when two are pending, x += alpha2
+// p_{k-2} + alpha p_{k-1} before p_{k-2} is overwritten; with one pending (its
+// direction in pin, which survives this pass) x is not touched.  On average
+// x is read and written every second iteration.
 // ----------------------------------------------------------------------------
 template <typename T>
 struct XfwdcArgs {
   Geo g;
   const T* r;
-  T* p;
+  const T* pin;   // p_{k-1}
+  T* pout;        // p_k (holds p_{k-2} on entry)
   T* x;
   cpx<T>* smain;
   cpx<T>* snyq;
@@ -362,15 +369,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(xfwdc_waves
   const long long vrc = valid ? vr : 0;
   const long long fo = (long long)l * field_elems(g);
   const bool first = a.st[l].first != 0;
-  const bool pend = a.st[l].pending != 0;
+  const bool pair = a.st[l].pending == 2;
   const T beta = static_cast<T>(a.st[l].beta);
   const T alpha = static_cast<T>(a.st[l].alpha);
+  const T alpha2 = static_cast<T>(a.st[l].alpha2);
   cpx<T> v[C][P];
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     const long long roff = fo + (long long)j * g.nvox + vrc * (2 * MX);
     const cpx<T>* r2 = reinterpret_cast<const cpx<T>*>(a.r + roff);
-    cpx<T>* p2 = reinterpret_cast<cpx<T>*>(a.p + roff);
+    const cpx<T>* pi2 = reinterpret_cast<const cpx<T>*>(a.pin + roff);
+    cpx<T>* po2 = reinterpret_cast<cpx<T>*>(a.pout + roff);
     cpx<T>* x2 = reinterpret_cast<cpx<T>*>(a.x + roff);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
@@ -381,14 +390,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(xfwdc_waves
         if (first) {
           pv = rv;
         } else {
-          const cpx<T> po = ld_seg<SEG>(p2 + n);
-          if (pend) {
+          const cpx<T> po = ld_seg<SEG>(pi2 + n);
+          if (pair) {
+            const cpx<T> pp = ld_seg<SEG>(po2 + n);
             const cpx<T> xo = ld_seg<SEG>(x2 + n);
-            st_seg<SEG>(x2 + n, cpx<T>{xo.x + alpha * po.x, xo.y + alpha * po.y});
+            st_seg<SEG>(x2 + n, cpx<T>{xo.x + alpha2 * pp.x + alpha * po.x, xo.y + alpha2 * pp.y + alpha * po.y});
           }
           pv = cpx<T>{rv.x + beta * po.x, rv.y + beta * po.y};
         }
-        st_seg<SEG>(p2 + n, pv);
+        st_seg<SEG>(po2 + n, pv);
       }
       v[j][i] = pv;
     }
@@ -1237,6 +1247,34 @@ __global__ __launch_bounds__(256) void k_xflush(const long long nvec, T* __restr
   for (int u = 0; u < kEwUnroll; ++u) {
     const long long i = b0 + (long long)u * 256;
     if (i < nvec) xv[i] = vaxpy(xv[i], al, pv[i]);
+  }
+}
+
+// End of a fused CG solve: the pending steps of every load, x += alpha
+// p[pbuf] (+ alpha2 p[1 - pbuf] when two are pending), p[0] and p[1] the two
+// direction buffers.
+template <typename T>
+__global__ __launch_bounds__(256) void k_xflush2(const long long nvec, T* __restrict__ x, const T* __restrict__ p0,
+                                                 const T* __restrict__ p1, const LoadState* __restrict__ st) {
+  using V = typename Vec16<T>::type;
+  const int l = blockIdx.y;
+  const int np = st[l].pending;
+  if (np == 0) return;
+  const T al = static_cast<T>(st[l].alpha);
+  const T al2 = static_cast<T>(np == 2 ? st[l].alpha2 : 0.0);
+  const long long off = (long long)l * nvec;
+  V* xv = reinterpret_cast<V*>(x) + off;
+  const V* pn = reinterpret_cast<const V*>(st[l].pbuf ? p1 : p0) + off;
+  const V* po = reinterpret_cast<const V*>(st[l].pbuf ? p0 : p1) + off;
+  const long long b0 = (long long)blockIdx.x * 256 * kEwUnroll + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kEwUnroll; ++u) {
+    const long long i = b0 + (long long)u * 256;
+    if (i < nvec) {
+      V y = vaxpy(xv[i], al, pn[i]);
+      if (np == 2) y = vaxpy(y, al2, po[i]);
+      xv[i] = y;
+    }
   }
 }
 

@@ -189,7 +189,7 @@ struct lsh_ctx {
   void* ovr_sm = nullptr;
   void* ovr_sn = nullptr;
   struct {
-    size_t x64, r64, p64, d32, r32, p32, s64m, s64n, s32m, s32n, phase, i0, ptab64, ptab32, vc64, vc32, tw64, tw32,
+    size_t x64, r64, p64, p64b, d32, r32, p32, p32b, s64m, s64n, s32m, s32n, phase, i0, ptab64, ptab32, vc64, vc32, tw64, tw32,
         wt64, wt32, loads, wgrad, st_out, st_in, mstate, guess, partials, sums, gst, end;
   } off{};
   long long pstride = 0, nsums = 0;
@@ -218,7 +218,7 @@ struct lsh_ctx {
   struct IterGraph {
     hipGraphExec_t exec = nullptr;
     long long key = -1;
-  } graphs[3];
+  } graphs[5];   // CG FP64, CG FP32, fixed point; CG FP64 and FP32 of odd iterations (fused step)
   long long graph_epoch = 0;  // bumped whenever captured kernel arguments may change
 
   // timing
@@ -408,9 +408,11 @@ void compute_layout(lsh_ctx* ctx) {
   ctx->off.x64 = take(sizeof(double) * L * F);
   ctx->off.r64 = mixed ? 0 : take(sizeof(double) * L * F);
   ctx->off.p64 = mixed ? 0 : take(sizeof(double) * L * F);
+  ctx->off.p64b = mixed ? 0 : take(sizeof(double) * L * F);   // second direction buffer of the fused CG step
   ctx->off.d32 = mixed ? take(sizeof(float) * L * F) : 0;
   ctx->off.r32 = mixed ? take(sizeof(float) * L * F) : 0;
   ctx->off.p32 = mixed ? take(sizeof(float) * L * F) : 0;
+  ctx->off.p32b = mixed ? take(sizeof(float) * L * F) : 0;
   ctx->off.s64m = take(sizeof(double) * L * F);
   ctx->off.s64n = take(2 * sizeof(double) * L * nyq);
   ctx->off.s32m = mixed ? take(sizeof(float) * L * F) : 0;
@@ -886,19 +888,24 @@ lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T*
   return LSH_OK;
 }
 
-lsh_status scal(lsh_ctx* ctx, int mode, int ngroups, int nparts, LoadState* st, double tol, int l0 = 0);
+lsh_status scal(lsh_ctx* ctx, int mode, int ngroups, int nparts, LoadState* st, double tol, int l0 = 0,
+                int aux = -1);
 
 // One CG step with p.Lp known before the inverse passes: the x pass forms p
 // and sums p.(A - A0)^{-1} p, the z pass sums p.Gamma p over the spectrum
 // (Parseval), alpha follows, and the x-inverse pass updates r in place with
-// ||r||^2; q = Lp is never stored.
-// x, r, p and st are the bases of load 0; the step covers loads [l0, l0 + nload).
+// ||r||^2; q = Lp is never stored.  The direction goes to buffer `par` (pout),
+// the previous one is read from the other (pin); the x pass applies the
+// pending solution updates in pairs (k_xfwdc).
+// x, r, pin, pout and st are the bases of load 0; the step covers loads [l0, l0 + nload).
 template <typename T>
-lsh_status cg_fused_step(lsh_ctx* ctx, int l0, int nload, T* x, T* r, T* p, LoadState* st, bool scalars = true) {
+lsh_status cg_fused_step(lsh_ctx* ctx, int l0, int nload, T* x, T* r, const T* pin, T* pout, int par,
+                         LoadState* st, bool scalars = true) {
   const Geo& g = ctx->geo;
   x += (long long)l0 * ctx->F;
   r += (long long)l0 * ctx->F;
-  p += (long long)l0 * ctx->F;
+  pin += (long long)l0 * ctx->F;
+  pout += (long long)l0 * ctx->F;
   st += l0;
   cpx<T>* sm = Sel<T>::sm(ctx) + (long long)l0 * main_cpx(g);
   cpx<T>* sn = Sel<T>::sn(ctx) + (long long)l0 * nyq_cpx(g);
@@ -907,11 +914,14 @@ lsh_status cg_fused_step(lsh_ctx* ctx, int l0, int nload, T* x, T* r, T* p, Load
   const double cvs = (double)ctx->F * sizeof(T);
   const double spec = cvs + 2.0 * sizeof(T) * (double)nyq_cpx(g);
   const double mat = (ctx->mat_voxel ? 2.0 * sizeof(T) : 1.0) * g.nvox;
-  XfwdcArgs<T> xa{g, r, p, x, sm, sn, Sel<T>::tw(ctx, 0), st, ctx->nphase, ctx->iso, Sel<T>::ptab(ctx),
+  XfwdcArgs<T> xa{g, r, pin, pout, x, sm, sn, Sel<T>::tw(ctx, 0), st, ctx->nphase, ctx->iso, Sel<T>::ptab(ctx),
                   ctx->ptr<uint8_t>(ctx->off.phase), Sel<T>::vc(ctx), parts, (int)ctx->pstride};
   int nbx = 0, nbz = 0, nbi = 0;
   {
-    Scope sc(ctx, kcls<T>(K_XFWD), nl * ((ctx->xf_first ? 2.0 : 5.0) * cvs + spec + mat));
+    // fields: first step r in, p out; then r and p_{k-1} in, p_k out, and every
+    // second step (two pending updates) p_{k-2} and x in, x out as well
+    const double fields = ctx->xf_first ? 2.0 : (par == 0 ? 6.0 : 3.0);
+    Scope sc(ctx, kcls<T>(K_XFWD), nl * (fields * cvs + spec + mat));
     nbx = launch_xfwdc<T>(ctx->stream, xa, nload);
     STCHK(check_launch(ctx, nbx, "x forward (CG)"));
   }
@@ -928,22 +938,22 @@ lsh_status cg_fused_step(lsh_ctx* ctx, int l0, int nload, T* x, T* r, T* p, Load
                        tv<T>(ctx, PASS_ZG), parts + nbx, (int)ctx->pstride);
     STCHK(check_launch(ctx, nbz, "z/Green"));
   }
-  if (scalars) STCHK(scal(ctx, SC_ALPHA, nload, nbx + nbz, st, ctx->bd_guard[sizeof(T) == 8 ? 1 : 0], l0));
+  if (scalars) STCHK(scal(ctx, SC_ALPHA, nload, nbx + nbz, st, ctx->bd_guard[sizeof(T) == 8 ? 1 : 0], l0, par));
   {
     Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
     STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, 1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y)),
                        "y inverse"));
   }
-  STCHK(inverse_x<T>(ctx, l0, nload, XI_CGR, p, r, nullptr, st, parts, &nbi, r));
+  STCHK(inverse_x<T>(ctx, l0, nload, XI_CGR, pout, r, nullptr, st, parts, &nbi, r));
   return scalars ? scal(ctx, SC_BETA, nload, nbi, st, 0.0, l0) : LSH_OK;
 }
 
 // groups [l0, l0 + ngroups): the partials of group l at (l0 + l) pstride; st is already offset
-lsh_status scal(lsh_ctx* ctx, int mode, int ngroups, int nparts, LoadState* st, double tol, int l0) {
+lsh_status scal(lsh_ctx* ctx, int mode, int ngroups, int nparts, LoadState* st, double tol, int l0, int aux) {
   Scope sc(ctx, K_SCAL);
   hipLaunchKernelGGL(k_scal, dim3(ngroups), dim3(256), 0, ctx->stream, mode,
                      ctx->ptr<double>(ctx->off.partials) + (long long)l0 * ctx->pstride, (int)ctx->pstride, nparts,
-                     st, ctx->ptr<double>(ctx->off.sums) + l0, tol);
+                     st, ctx->ptr<double>(ctx->off.sums) + l0, tol, aux);
   return check_launch(ctx, 0, "scalars");
 }
 
@@ -1014,13 +1024,16 @@ lsh_status cg_update(lsh_ctx* ctx, int nload, T* r, const T* q, LoadState* st) {
   return scal(ctx, SC_BETA, nload, nb, st, 0.0);
 }
 
-// x += alpha p for the loads whose last step is pending (end of a CG solve)
+// x += alpha p for the loads whose last step is pending (end of a CG solve);
+// with two direction buffers (fused step, pb != nullptr) the pending steps of
+// each load, one or two, from the buffers its states name
 template <typename T>
-lsh_status cg_flush(lsh_ctx* ctx, int nload, T* x, const T* p, LoadState* st) {
+lsh_status cg_flush(lsh_ctx* ctx, int nload, T* x, const T* p, const T* pb, LoadState* st) {
   const long long nvec = ctx->F / Vec16<T>::n;
   const int nb = (int)((nvec + 256 * kEwUnroll - 1) / (256 * kEwUnroll));
-  Scope sc(ctx, kcls<T>(K_CGUPD), nload * 3.0 * (double)ctx->F * sizeof(T));
-  hipLaunchKernelGGL((k_xflush<T>), dim3(nb, nload), dim3(256), 0, ctx->stream, nvec, x, p, st);
+  Scope sc(ctx, kcls<T>(K_CGUPD), nload * (pb ? 4.0 : 3.0) * (double)ctx->F * sizeof(T));
+  if (pb) hipLaunchKernelGGL((k_xflush2<T>), dim3(nb, nload), dim3(256), 0, ctx->stream, nvec, x, p, pb, st);
+  else hipLaunchKernelGGL((k_xflush<T>), dim3(nb, nload), dim3(256), 0, ctx->stream, nvec, x, p, st);
   return check_launch(ctx, 0, "cg flush");
 }
 
@@ -1074,9 +1087,11 @@ lsh_status run_iteration(lsh_ctx* ctx, int slot, long long key, F&& enqueue) {
 }
 
 // CG iterations on (x, r, p) with q held in the spectrum buffer; returns after
-// convergence of every load, or maxit iterations.
+// convergence of every load, or maxit iterations.  The fused step alternates
+// its directions between p (even iterations) and pb (odd ones), one captured
+// graph per parity; the unfused step and the persistent loop use p alone.
 template <typename T>
-lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, size_t st_off, int maxit,
+lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, T* pb, LoadState* st, size_t st_off, int maxit,
                    std::vector<LoadState>& hst) {
   const int period = check_period(ctx, nload);
   T* q = reinterpret_cast<T*>(Sel<T>::sm(ctx));
@@ -1112,8 +1127,9 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
     }
     return LSH_OK;
   }
+  int par = 0;
   auto iteration = [&]() -> lsh_status {
-    if (ctx->cg_fused) return cg_fused_step<T>(ctx, 0, nload, x, r, p, st);
+    if (ctx->cg_fused) return cg_fused_step<T>(ctx, 0, nload, x, r, par ? p : pb, par ? pb : p, par, st);
     STCHK(forward_part<T>(ctx, 0, nload, XF_CG, r, p, x, nullptr, st, true));
     int np = 0;
     STCHK(inverse_x<T>(ctx, 0, nload, XI_CG, p, q, nullptr, st, ctx->ptr<double>(ctx->off.partials), &np));
@@ -1123,7 +1139,8 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
   const long long key = (long long)nload * 4 + (st_off == ctx->off.st_in ? 1 : 0) + (ctx->cg_fused ? 2 : 0);
   for (int it = 0; it < maxit; ++it) {
     ctx->xf_first = it == 0;
-    STCHK(run_iteration(ctx, sizeof(T) == 8 ? 0 : 1, key, iteration));
+    par = ctx->cg_fused ? (it & 1) : 0;
+    STCHK(run_iteration(ctx, (sizeof(T) == 8 ? 0 : 1) + 3 * par, key, iteration));
     if ((it + 1) % period == 0 || it + 1 == maxit) {
       STCHK(read_states(ctx, st_off, nload, hst));
       any = false;
@@ -1133,7 +1150,7 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, LoadState* st, siz
     }
   }
   ctx->xf_first = false;
-  return cg_flush<T>(ctx, nload, x, p, st);
+  return cg_flush<T>(ctx, nload, x, p, ctx->cg_fused ? pb : nullptr, st);
 }
 
 // Fixed-point schemes on tau in place: basic (XI_BASIC) or Eyre--Milton (XI_EM).
@@ -1376,10 +1393,12 @@ lsh_status timing_iteration(lsh_ctx* ctx, int nload, bool fp64) {
   double* parts = ctx->ptr<double>(ctx->off.partials);
   if (!fp64 && ctx->cg_fused)
     return cg_fused_step<float>(ctx, 0, nload, ctx->ptr<float>(ctx->off.d32), ctx->ptr<float>(ctx->off.r32),
-                                ctx->ptr<float>(ctx->off.p32), ctx->ptr<LoadState>(ctx->off.st_in), false);
+                                ctx->ptr<float>(ctx->off.p32b), ctx->ptr<float>(ctx->off.p32), 0,
+                                ctx->ptr<LoadState>(ctx->off.st_in), false);
   if (fp64 && ctx->cg_fused && ctx->precision != LSH_MIXED)
     return cg_fused_step<double>(ctx, 0, nload, ctx->ptr<double>(ctx->off.x64), ctx->ptr<double>(ctx->off.r64),
-                                 ctx->ptr<double>(ctx->off.p64), ctx->ptr<LoadState>(ctx->off.st_out), false);
+                                 ctx->ptr<double>(ctx->off.p64b), ctx->ptr<double>(ctx->off.p64), 0,
+                                 ctx->ptr<LoadState>(ctx->off.st_out), false);
   if (!fp64) {
     LoadState* st = ctx->ptr<LoadState>(ctx->off.st_in);
     float* q = reinterpret_cast<float*>(Sel<float>::sm(ctx));
@@ -1941,7 +1960,7 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
     double* r = ctx->ptr<double>(ctx->off.r64);
     double* p = ctx->ptr<double>(ctx->off.p64);
     STCHK(guess_init(ctx, nload, x64, r, sto, tol));
-    STCHK(cg_loop<double>(ctx, nload, x64, r, p, sto, ctx->off.st_out, maxit, hst));
+    STCHK(cg_loop<double>(ctx, nload, x64, r, p, ctx->ptr<double>(ctx->off.p64b), sto, ctx->off.st_out, maxit, hst));
     STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
     for (int l = 0; l < nload; ++l) iters[l] = hst[l].iters, apps64 += hst[l].iters;
   } else {
@@ -1964,7 +1983,7 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
     while (true) {
       if (!refine_first) {
         // inner FP32 solve, then refresh the residual in FP64 (x64 += d inside)
-        STCHK(cg_loop<float>(ctx, nload, d, r, p, sti, ctx->off.st_in, budget, hin));
+        STCHK(cg_loop<float>(ctx, nload, d, r, p, ctx->ptr<float>(ctx->off.p32b), sti, ctx->off.st_in, budget, hin));
         STCHK(read_states(ctx, ctx->off.st_in, nload, hin));
         int used = 0;
         for (int l = 0; l < nload; ++l) {
@@ -2314,18 +2333,20 @@ lsh_status lsh_autotune(lsh_ctx* ctx, int nload, const char* cache_path, int32_t
   ctx->nact = 1 << 30;
   const int reps = 3;
   // inputs: smooth finite fields, and load states that take the full CG path
-  // (active, not the first step, a pending x update; zero steps keep the
-  // fields bounded)
+  // (active, not the first step, x updates pending: two, so that the fused x
+  // pass takes its heavier paired form; zero steps keep the fields bounded)
   {
     const long long n = (long long)nload * ctx->F;
     const unsigned nb = (unsigned)((n + 255) / 256);
     std::vector<double*> f64 = {ctx->ptr<double>(ctx->off.x64)};
     std::vector<float*> f32;
     if (ctx->precision == LSH_MIXED) {
-      f32 = {ctx->ptr<float>(ctx->off.d32), ctx->ptr<float>(ctx->off.r32), ctx->ptr<float>(ctx->off.p32)};
+      f32 = {ctx->ptr<float>(ctx->off.d32), ctx->ptr<float>(ctx->off.r32), ctx->ptr<float>(ctx->off.p32),
+             ctx->ptr<float>(ctx->off.p32b)};
     } else {
       f64.push_back(ctx->ptr<double>(ctx->off.r64));
       f64.push_back(ctx->ptr<double>(ctx->off.p64));
+      f64.push_back(ctx->ptr<double>(ctx->off.p64b));
     }
     for (double* f : f64) hipLaunchKernelGGL((k_fill<double>), dim3(nb), dim3(256), 0, ctx->stream, n, f);
     for (float* f : f32) hipLaunchKernelGGL((k_fill<float>), dim3(nb), dim3(256), 0, ctx->stream, n, f);
@@ -2333,7 +2354,7 @@ lsh_status lsh_autotune(lsh_ctx* ctx, int nload, const char* cache_path, int32_t
     LoadState s0{};
     s0.rr = s0.pq = s0.bb = s0.res2 = 1.0;
     s0.active = 1;
-    s0.pending = 1;
+    s0.pending = 2;
     std::vector<LoadState> hs((size_t)nload, s0);
     HIPCHK(hipMemcpyAsync(ctx->ws + ctx->off.st_in, hs.data(), sizeof(LoadState) * nload, hipMemcpyHostToDevice,
                           ctx->stream));

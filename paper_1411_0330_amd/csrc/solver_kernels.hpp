@@ -305,9 +305,12 @@ static __global__ __launch_bounds__(256) void k_sy_update(const long long F, dou
 
 // Deterministic final reduction of the partials of group blockIdx.x, then the
 // scalar update of the solver (one workgroup per group).
+// aux (SC_ALPHA): -1 for the unfused CG step (its x pass applies the pending
+// step every iteration); 0 or 1 for the fused step, the buffer this iteration's
+// direction went to (its x pass applies pending steps in pairs).
 static __global__ __launch_bounds__(256) void k_scal(const int mode, const double* __restrict__ partials, const int pstride,
                                               const int nparts, LoadState* __restrict__ st,
-                                              double* __restrict__ sums, const double tol) {
+                                              double* __restrict__ sums, const double tol, const int aux) {
   __shared__ double red[256];
   const int grp = blockIdx.x;
   double s = 0.0;
@@ -365,8 +368,9 @@ static __global__ __launch_bounds__(256) void k_scal(const int mode, const doubl
     // |p.Lp| <= g r.r with g = eps ||L|| from the host (tol argument): the
     // Rayleigh quotient of p (p.p >= r.r) is then below eps times the bound
     // of the operator, beyond what the field precision resolves.
-    // the previous step (if any) was applied to x by this iteration's x pass
-    L.pending = 0;
+    // pending steps this iteration's x pass applied: the previous one
+    // (unfused), or the pair when two were pending (fused)
+    if (aux < 0 || L.pending == 2) L.pending = 0;
     if (!isfinite(S)) {
       L.status = kStatusNumeric;
       L.active = 0;
@@ -374,9 +378,11 @@ static __global__ __launch_bounds__(256) void k_scal(const int mode, const doubl
       L.status = kStatusBreakdown;
       L.active = 0;
     } else {
+      if (L.pending == 1) L.alpha2 = L.alpha;
       L.alpha = L.rr / S;
       L.first = 0;
-      L.pending = 1;
+      L.pending += 1;
+      if (aux >= 0) L.pbuf = aux;
     }
   } else if (mode == SC_BETA) {
     L.iters += 1;

@@ -149,6 +149,24 @@ def test_maxit_reports_unconverged(lsh):
     assert rel_max_err(ctx.field(0).cpu().numpy(), ref["tau"]) <= 1e-10
 
 
+@pytest.mark.parametrize("graphs", [True, False])
+def test_multikernel_cg_iterates_match_oracle_at_every_stop(lsh, graphs):
+    # the fused step of the multi-kernel loop applies the solution updates of
+    # its steps in pairs; stopping after an odd or an even number of steps must
+    # give the oracle's k-th CG iterate (both loads, pending steps flushed)
+    w = I.disk_workload(32, "truncated")
+    pb = problem(w.phase, w.moduli, w.A0, "scalar", "truncated")
+    ctx = context(lsh, w.phase, w.moduli, w.A0, "scalar", "truncated", max_loads=2)
+    ctx.set_persistent(False)
+    ctx.set_graphs(graphs)
+    for k in (1, 2, 3, 4, 5, 8):
+        rep = ctx.solve(w.loads, "cg", tol=1e-14, maxit=k)
+        assert rep["iterations"] == [k, k]
+        for l in range(2):
+            ref = solvers.cg(pb, w.loads[l], tol=1e-14, maxit=k)
+            assert rel_max_err(ctx.field(l).cpu().numpy(), ref["tau"]) <= 1e-10, (k, l)
+
+
 def test_boolean_128_fp64_and_mixed_against_golden(lsh):
     gold = json.load(open(os.path.join(GOLDEN, "boolean3d_n128_filtered.json")))
     w = I.boolean_workload(128)
