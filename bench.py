@@ -120,13 +120,12 @@ def measured_traffic(kernel):
 
 
 # Algorithmic bytes per voxel of one load (FP32 elastic path, c = 6, s = 4,
-# one phase byte): a CG voxel-iteration 14.5 c s + 1 (the three read+write
-# passes of the operator plus the CG vector sweeps: r and p_{k-1} in, p_k
-# out, and x += alpha2 p_{k-2} + alpha p_{k-1} every second iteration, i.e.
-# 4.5 fields on average in the x pass), an FP64 refinement
+# one phase byte): a CG voxel-iteration B_alg = 15 c s + 1 (the three
+# read+write passes of the operator plus the CG vector sweeps; the fused step
+# with paired solution updates moves 15.5 c s + 2 on average), an FP64 refinement
 # application 11 c 8 (x64 += d, r = b - L x64 in FP64, r to FP32), a strain
 # pass 6 c 8 (three FP64 read+write passes) and the tau copy-out c (8 + 4).
-B_CG32, B_IR64, B_STRAIN, B_TAUOUT = 29 * 6 * 2 + 1, 11 * 6 * 8, 6 * 6 * 8, 6 * 12
+B_CG32, B_IR64, B_STRAIN, B_TAUOUT = 15 * 6 * 4 + 1, 11 * 6 * 8, 6 * 6 * 8, 6 * 12
 
 
 def copy_bandwidth(dev, nbytes=1 << 30, reps=10):
