@@ -360,8 +360,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(xfwdc_waves
   const int l = blockIdx.y;
   if (!a.st[l].active) return;
   const int tid = threadIdx.x;
-  for (int i = tid; i < a.nphase * TABW; i += 256) tab[i] = a.ptab[i];
-  for (int i = tid; i < 2 * MX; i += 256) twl[i] = a.twx[i];
   const int slot = tid / TR, t = tid % TR;
   const long long vrows = (long long)g.nz * g.ny;
   const long long vr = (long long)blockIdx.x * RPW + slot;
@@ -405,7 +403,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(xfwdc_waves
     // one component's rows at a time: bounds the registers the loads occupy
     __builtin_amdgcn_sched_barrier(0);
   }
-  __syncthreads();   // material table and twiddles staged
+  // material table and twiddles, staged after the row reads (a wait on them
+  // first would hold the reads back)
+  for (int i = tid; i < a.nphase * TABW; i += 256) tab[i] = a.ptab[i];
+  for (int i = tid; i < 2 * MX; i += 256) twl[i] = a.twx[i];
+  __syncthreads();
   // local quadratic form on the voxel pairs this thread holds
   double part = 0.0;
   const bool iso = a.iso != 0;
@@ -484,7 +486,6 @@ __global__ __launch_bounds__(TX*(NY / P)) void k_y(const Geo g, cpx<T>* __restri
   const int l = blockIdx.y;
   if (st != nullptr && !st[l].active) return;
   const int tid = threadIdx.x;
-  for (int i = tid; i < NY; i += TX * TY) twl[i] = twy[i];
   cpx<T>* base;
   long long es_g;
   cpx<T>* lp;
@@ -516,6 +517,8 @@ __global__ __launch_bounds__(TX*(NY / P)) void k_y(const Geo g, cpx<T>* __restri
   cpx<T> v[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) v[i] = valid ? ld_seg<SEG>(base + (long long)(t + TY * i) * es_g) : cpx<T>{0, 0};
+  // twiddles staged after the pencil reads are issued (their wait would hold the reads back)
+  for (int i = tid; i < NY; i += TX * TY) twl[i] = twy[i];
   __syncthreads();
   fft_pencil<NY, P, DIR, T>(v, t, lp, es_l, twl, 1);
   if (valid) {
@@ -589,7 +592,6 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
   }
   if (st != nullptr && !st[l].active) return;
   const int tid = threadIdx.x;
-  for (int i = tid; i < NZ; i += TX * TZ) twl[i] = twz[i];
   const int xl = tid % TX, t = tid / TX;
   cpx<T>* base;
   long long es_g, cstride;
@@ -616,13 +618,15 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
   cpx<T>* lp = lds + xl;
 
   // all components' loads are issued before the first transform (guarded
-  // reads: unguarded ones let the scheduler raise this kernel past 256 VGPRs)
+  // reads: unguarded ones let the scheduler raise this kernel past 256 VGPRs),
+  // and before the twiddles are staged, whose wait would otherwise hold them back
   cpx<T> v[C][P];
 #pragma unroll
   for (int j = 0; j < C; ++j)
 #pragma unroll
     for (int i = 0; i < P; ++i)
       v[j][i] = valid ? z_load<T, SEG>(base + j * cstride + (long long)(t + TZ * i) * es_g) : cpx<T>{0, 0};
+  for (int i = tid; i < NZ; i += TX * TZ) twl[i] = twz[i];
   __syncthreads();
   fft_pencil_multi<NZ, P, -1, T, C, CG>(v, t, lp, TX, twl, 1, TX * NZ);
   if (zmode == Z_GAMMA) {
@@ -646,6 +650,11 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
           skz = (long long)TZ * NG * g.ny;
         }
       }
+      // stored operator: the entries of the next wave-vector are read while
+      // the current one is applied (one round trip per wave-vector otherwise)
+      constexpr int NE = C * (C + 1) / 2;
+      T Gn[NE];
+      if constexpr (GS) stored_matrix<T, C>(sq, sgs, Gn);
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         const int kz = t + TZ * i;
@@ -653,8 +662,11 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
 #pragma unroll
         for (int j = 0; j < C; ++j) w[j] = v[j][i];
         if constexpr (GS) {
-          T Gm[C * (C + 1) / 2];
-          stored_matrix<T, C>(sq + i * skz, sgs, Gm);
+          T Gm[NE];
+#pragma unroll
+          for (int e = 0; e < NE; ++e) Gm[e] = Gn[e];
+          if (i + 1 < P) stored_matrix<T, C>(sq + (i + 1) * skz, sgs, Gn);
+          __builtin_amdgcn_sched_barrier(0);
           sym_apply<T, C>(Gm, w);
         } else {
           const int k[3] = {kx, ky, kz};
