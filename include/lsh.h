@@ -329,8 +329,13 @@ lsh_status lsh_spectrum_bytes(const lsh_ctx* ctx, int dtype, size_t* bytes);
  * the FP32 (fp64 = 0) or FP64 (fp64 = 1) kernels.  The z pass has a fifth
  * shape (4): one workgroup per wave-vector tile handles every load, forming
  * the operator matrices once (FP32, truncated, filtered and consistent
- * operators; otherwise shape 0 runs).  Every shape computes the
- * same result; only speed differs.  lsh_get_variants writes the 8 current
+ * operators; otherwise shape 0 runs).  Its sixth shape (5) runs 8-pencil
+ * tiles on a component-paired copy of the spectrum that the y passes write
+ * and read back (FP32 six-component fields of a mixed context with the stored
+ * filtered operator, 128- or 256-point y and z axes; otherwise shape 0 runs;
+ * the copy lives in the FP64 spectrum buffer of the workspace, so the
+ * workspace size does not change).  Every shape computes the
+ * same result up to rounding; only speed differs.  lsh_get_variants writes the 8 current
  * choices (FP32 passes, then FP64).  The environment variable LSH_TUNE (for
  * example "zg32=1,xinv64=2") sets them when the context is created.
  */
@@ -339,7 +344,8 @@ lsh_status lsh_get_variants(const lsh_ctx* ctx, int32_t* variants);
 
 /*
  * Autotuner: times every shape of every pass that has several (the others
- * held at their current choice) with HIP events over operator applications
+ * held at their current choice; the z pass before the y passes, whose layout
+ * its shape 5 sets) with HIP events over operator applications
  * of nload loads on the context's own buffers, in the modes the solvers run
  * (the CG modes for FP32 fields of a mixed context and FP64 fields of an FP64
  * context, the refinement modes for the FP64 passes of a mixed context), and

@@ -84,8 +84,12 @@ constexpr int kVariants = 4;
 // The z pass has one more shape: 4 = all loads of a tile in one workgroup with
 // the operator matrices formed once (FP32 fields, operators other than the
 // finite-difference one, 128- and 256-point z axes; elsewhere it falls back
-// to shape 0).
-constexpr int kVariantsZ = 5;
+// to shape 0).  And 5 = 8-pencil tiles on the component-paired spectrum
+// layout, whose y passes convert the layout out of place (FP32 six-component
+// fields with the stored operator, 128- and 256-point y and z axes; elsewhere
+// shape 0).
+constexpr int kVariantsZ = 6;
+constexpr int kZPaired = 5;
 enum : int { PASS_XFWD = 0, PASS_Y = 1, PASS_ZG = 2, PASS_XINV = 3, NPASS = 4 };
 constexpr int pass_variants(int pass) { return pass == PASS_ZG ? kVariantsZ : kVariants; }
 
@@ -104,6 +108,14 @@ template <typename T> constexpr int tx_zm(int n, int p) {
 template <typename T> int launch_xfwd(hipStream_t s, const XfwdArgs<T>& a, int nload, int variant = 0);
 template <typename T> int launch_y(hipStream_t s, const Geo& g, int dir, cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw,
                                    const LoadState* st, int nload, int variant = 0);
+// y passes into (dir < 0) and out of (dir > 0) the component-paired layout
+// held in sp; -1 where the shape has no such instance
+template <typename T> int launch_y_paired(hipStream_t s, const Geo& g, int dir, cpx<T>* sm, cpx<T>* sp, cpx<T>* sn,
+                                          const cpx<T>* tw, const LoadState* st, int nload, int variant = 0);
+// the Green pass on the paired layout (stored operator); -1 where none exists
+template <typename T> int launch_zg_paired(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb,
+                                           cpx<T>* sp, cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload,
+                                           double* qpart, int pstride);
 template <typename T> int launch_zg(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb,
                                     int zmode, cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw, const LoadState* st,
                                     int nload, int variant = 0, double* qpart = nullptr, int pstride = 0);

@@ -3,15 +3,17 @@
 
 namespace lsh {
 
-template <typename T, int NY, int DIR, int TX, int P>
+template <typename T, int NY, int DIR, int TX, int P, int LAY = YL_INPLACE>
 static int y_inst(hipStream_t s, const Geo& g, cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw, const LoadState* st,
-                  int nload) {
+                  int nload, cpx<T>* sout = nullptr) {
   constexpr int NT = TX * (NY / P);
-  const int xtiles = (g.mx + TX - 1) / TX;
-  const int main_tiles = g.c * g.nz * xtiles;
+  constexpr int H = LAY == YL_INPLACE ? TX : TX / 2;
+  const int xtiles = (g.mx + H - 1) / H;
+  // paired layouts: tiles over component pairs (two components per tile)
+  const int main_tiles = (LAY == YL_INPLACE ? g.c : g.c / 2) * g.nz * xtiles;
   const int nyq_tiles = (g.c * g.nz + TX - 1) / TX;
-  hipLaunchKernelGGL((k_y<T, NY, P, TX, DIR>), dim3(main_tiles + nyq_tiles, nload), dim3(NT), 0, s, g, sm, sn, tw,
-                     st, main_tiles);
+  hipLaunchKernelGGL((k_y<T, NY, P, TX, DIR, LAY>), dim3(main_tiles + nyq_tiles, nload), dim3(NT), 0, s, g, sm, sn,
+                     tw, st, main_tiles, sout);
   return main_tiles + nyq_tiles;
 }
 
@@ -70,10 +72,43 @@ int launch_y(hipStream_t s, const Geo& g, int dir, cpx<T>* sm, cpx<T>* sn, const
   return dir < 0 ? y_dir<T, -1>(s, g, sm, sn, tw, st, nload, v) : y_dir<T, 1>(s, g, sm, sn, tw, st, nload, v);
 }
 
+// Forward y into the component-paired layout (sm plain in, sp paired out) or
+// inverse y back from it (sp paired in, sm plain out): six-component FP32
+// fields with 128 or 256 points along y.  Tiles hold at least 16
+// wave-vectors of each component (whole 128-byte lines in both layouts):
+// variant 3 takes twice the pencils of the others.  Returns -1 where no
+// instance exists.
+template <typename T>
+int launch_y_paired(hipStream_t s, const Geo& g, int dir, cpx<T>* sm, cpx<T>* sp, cpx<T>* sn, const cpx<T>* tw,
+                    const LoadState* st, int nload, int v) {
+  if constexpr (sizeof(T) == 4) {
+    if (g.c != 6 || g.nz < 2) return -1;
+    auto go = [&](auto ny_tag, auto var_tag) -> int {
+      constexpr int NY = decltype(ny_tag)::value, V = decltype(var_tag)::value;
+      constexpr int P = p_y<T>(NY);
+      constexpr int TX0 = tx_strided<T>(NY, P);
+      // at least 32 pencils (16 wave-vectors of each component); shape 3 twice shape 0's
+      constexpr int TXA = TX0 >= 32 ? TX0 : 32;
+      constexpr int TXB = sv_ok<T>(NY, 2 * TXA, P) ? 2 * TXA : TXA;
+      constexpr int TX = V == 3 ? TXB : TXA;
+      static_assert(sv_ok<T>(NY, TX, P), "paired y shape within the workgroup limits");
+      if (dir < 0) return y_inst<T, NY, -1, TX, P, YL_TO_PAIRED>(s, g, sm, sn, tw, st, nload, sp);
+      return y_inst<T, NY, 1, TX, P, YL_FROM_PAIRED>(s, g, sp, sn, tw, st, nload, sm);
+    };
+    using V0 = std::integral_constant<int, 0>;
+    using V3 = std::integral_constant<int, 3>;
+    if (g.ny == 128) return v == 3 ? go(std::integral_constant<int, 128>{}, V3{}) : go(std::integral_constant<int, 128>{}, V0{});
+    if (g.ny == 256) return v == 3 ? go(std::integral_constant<int, 256>{}, V3{}) : go(std::integral_constant<int, 256>{}, V0{});
+  }
+  return -1;
+}
+
 #ifndef LSH_Y_TYPE
 #error "define LSH_Y_TYPE"
 #endif
 template int launch_y<LSH_Y_TYPE>(hipStream_t, const Geo&, int, cpx<LSH_Y_TYPE>*, cpx<LSH_Y_TYPE>*,
                                   const cpx<LSH_Y_TYPE>*, const LoadState*, int, int);
+template int launch_y_paired<LSH_Y_TYPE>(hipStream_t, const Geo&, int, cpx<LSH_Y_TYPE>*, cpx<LSH_Y_TYPE>*,
+                                         cpx<LSH_Y_TYPE>*, const cpx<LSH_Y_TYPE>*, const LoadState*, int, int);
 
 }  // namespace lsh

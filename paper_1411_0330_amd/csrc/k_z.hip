@@ -13,7 +13,7 @@ constexpr bool kGS = true;
 constexpr bool kGS = false;
 #endif
 
-template <typename T, int NZ, int C, int TX, int P>
+template <typename T, int NZ, int C, int TX, int P, bool PR = false>
 static int z_inst(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, int zmode, cpx<T>* sm,
                   cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload, double* qp, int ps) {
   constexpr int NT = TX * (NZ / P);
@@ -22,7 +22,7 @@ static int z_inst(hipStream_t s, const Geo& g, const GreenParams& gp, const Gree
   const int nyq_tiles = (g.ny + TX - 1) / TX;
   // stored operator: one workgroup per (tile, load), the loads of a tile adjacent on one XCD
   const dim3 grid = kGS ? dim3((main_tiles + nyq_tiles) * nload, 1) : dim3(main_tiles + nyq_tiles, nload);
-  hipLaunchKernelGGL((k_zg<T, NZ, P, TX, C, kGS>), grid, dim3(NT), 0, s, g, gp, tb, zmode, sm, sn, tw, st,
+  hipLaunchKernelGGL((k_zg<T, NZ, P, TX, C, kGS, PR>), grid, dim3(NT), 0, s, g, gp, tb, zmode, sm, sn, tw, st,
                      main_tiles, qp, ps, nload);
   return main_tiles + nyq_tiles;
 }
@@ -103,6 +103,21 @@ int launch_zg_stored(hipStream_t s, const Geo& g, const GreenParams& gp, const G
   if (g.c == 6) return z_c<T, 6>(s, g, gp, tb, Z_GAMMA, sm, sn, tw, st, nload, v, qp, ps);
   return -1;
 }
+
+// 8-pencil tiles of the component-paired layout: two workgroups per compute
+// unit, every access a whole 128-byte line
+template <typename T>
+int launch_zg_paired(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, cpx<T>* sp,
+                     cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload, double* qp, int ps) {
+  if constexpr (sizeof(T) == 4) {
+    if (g.c != 6 || tb.st == nullptr) return -1;
+    if (g.nz == 128)
+      return z_inst<T, 128, 6, 8, p_z<T, 6>(128), true>(s, g, gp, tb, Z_GAMMA, sp, sn, tw, st, nload, qp, ps);
+    if (g.nz == 256)
+      return z_inst<T, 256, 6, 8, p_z<T, 6>(256), true>(s, g, gp, tb, Z_GAMMA, sp, sn, tw, st, nload, qp, ps);
+  }
+  return -1;
+}
 #else
 template <typename T>
 int launch_zg(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb, int zmode, cpx<T>* sm,
@@ -128,6 +143,9 @@ int launch_zg(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTab
 template int launch_zg_stored<LSH_Z_TYPE>(hipStream_t, const Geo&, const GreenParams&, const GreenTabs<LSH_Z_TYPE>&,
                                           cpx<LSH_Z_TYPE>*, cpx<LSH_Z_TYPE>*, const cpx<LSH_Z_TYPE>*,
                                           const LoadState*, int, int, double*, int);
+template int launch_zg_paired<LSH_Z_TYPE>(hipStream_t, const Geo&, const GreenParams&, const GreenTabs<LSH_Z_TYPE>&,
+                                          cpx<LSH_Z_TYPE>*, cpx<LSH_Z_TYPE>*, const cpx<LSH_Z_TYPE>*,
+                                          const LoadState*, int, double*, int);
 #else
 template int launch_zg<LSH_Z_TYPE>(hipStream_t, const Geo&, const GreenParams&, const GreenTabs<LSH_Z_TYPE>&, int,
                                    cpx<LSH_Z_TYPE>*, cpx<LSH_Z_TYPE>*, const cpx<LSH_Z_TYPE>*, const LoadState*,

@@ -46,6 +46,11 @@ struct Geo {
   long long nvox;  // nx*ny*nz
 };
 
+// 16-byte vector of the field type
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
+template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+
 __host__ __device__ inline long long field_elems(const Geo& g) { return (long long)g.c * g.nvox; }
 __host__ __device__ inline long long main_cpx(const Geo& g) { return (long long)g.c * g.nz * g.ny * g.mx; }
 __host__ __device__ inline long long nyq_cpx(const Geo& g) { return (long long)g.c * g.nz * g.ny; }
@@ -475,33 +480,64 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(xfwdc_waves
 // ----------------------------------------------------------------------------
 // y pass: strided pencils of the main spectrum, contiguous rows of the Nyquist plane
 // ----------------------------------------------------------------------------
-template <typename T, int NY, int P, int TX, int DIR>
+// Spectrum layouts of the y pass (LAY): 0 in place in the plain layout
+// (component-major rows of mx wave-vectors); 1 reads the plain layout and
+// writes the component-paired one; 2 reads the paired layout and writes the
+// plain one.  In the paired layout (six-component FP32 fields, the z pass of
+// 8-pencil tiles) components 2m and 2m+1 of a wave-vector are adjacent:
+//   ((m nz + kz) ny + ky) 2 mx + 2 kx + (j & 1),   j = 2m or 2m + 1,
+// so an 8-pencil z tile reads whole 128-byte lines for every component pair.
+// A paired-layout tile holds TX/2 wave-vectors of two components (columns
+// xl < TX/2 the even one); the Nyquist rows stay in place in every layout.
+enum : int { YL_INPLACE = 0, YL_TO_PAIRED = 1, YL_FROM_PAIRED = 2 };
+
+template <typename T, int NY, int P, int TX, int DIR, int LAY>
 __global__ __launch_bounds__(TX*(NY / P)) void k_y(const Geo g, cpx<T>* __restrict__ smain,
                                                   cpx<T>* __restrict__ snyq, const cpx<T>* __restrict__ twy,
-                                                  const LoadState* __restrict__ st, const int main_tiles) {
+                                                  const LoadState* __restrict__ st, const int main_tiles,
+                                                  cpx<T>* __restrict__ sout) {
   constexpr int TY = NY / P;
-  constexpr int SEG = TX * (int)sizeof(cpx<T>);   // contiguous bytes per access instruction
+  constexpr int H = LAY == YL_INPLACE ? TX : TX / 2;   // wave-vectors per component in a main tile
+  constexpr int SEG = H * (int)sizeof(cpx<T>);       // contiguous bytes per plain-layout access
+  constexpr int SEGP = TX * (int)sizeof(cpx<T>);     // contiguous bytes per paired-layout access
   __shared__ cpx<T> lds[TX * NY];
   __shared__ cpx<T> twl[NY];
   const int l = blockIdx.y;
   if (st != nullptr && !st[l].active) return;
   const int tid = threadIdx.x;
   cpx<T>* base;
-  long long es_g;
+  cpx<T>* obase;
+  long long es_g, es_o;
   cpx<T>* lp;
   int es_l, t;
-  bool valid;
+  bool valid, main = false;
   if ((int)blockIdx.x < main_tiles) {
-    const int xtiles = (g.mx + TX - 1) / TX;
-    const int tile = xcd_tile<line_share<T, TX>()>(blockIdx.x, main_tiles);
+    main = true;
+    const int xtiles = (g.mx + H - 1) / H;
+    const int tile = LAY == YL_INPLACE ? xcd_tile<line_share<T, TX>()>(blockIdx.x, main_tiles) : (int)blockIdx.x;
     const int xc = tile % xtiles;
     const long long jz = tile / xtiles;
     const int xl = tid % TX;
     t = tid / TX;
-    const int kx = xc * TX + xl;
+    const int kx = xc * H + xl % H;
     valid = kx < g.mx;
-    base = smain + (long long)l * main_cpx(g) + jz * g.ny * g.mx + (valid ? kx : 0);
-    es_g = g.mx;
+    const int kxc = valid ? kx : 0;
+    const long long lo = (long long)l * main_cpx(g);
+    if constexpr (LAY == YL_INPLACE) {
+      base = smain + lo + jz * g.ny * g.mx + kxc;
+      obase = base;
+      es_g = es_o = g.mx;
+    } else {
+      // jz = m nz + kz over component pairs; this column's component j = 2m + xl / H
+      const long long m = jz / g.nz, kz = jz % g.nz;
+      const int s = xl / H;
+      cpx<T>* plain = (LAY == YL_TO_PAIRED ? smain : sout) + lo + ((2 * m + s) * g.nz + kz) * g.ny * g.mx + kxc;
+      cpx<T>* paired = (LAY == YL_TO_PAIRED ? sout : smain) + lo + (m * g.nz + kz) * g.ny * 2 * g.mx + 2 * kxc + s;
+      base = LAY == YL_TO_PAIRED ? plain : paired;
+      obase = LAY == YL_TO_PAIRED ? paired : plain;
+      es_g = LAY == YL_TO_PAIRED ? g.mx : 2 * g.mx;
+      es_o = LAY == YL_TO_PAIRED ? 2 * g.mx : g.mx;
+    }
     lp = lds + xl;
     es_l = TX;
   } else {
@@ -510,20 +546,31 @@ __global__ __launch_bounds__(TX*(NY / P)) void k_y(const Geo g, cpx<T>* __restri
     const long long row = (long long)(blockIdx.x - main_tiles) * TX + slot;
     valid = row < (long long)g.c * g.nz;
     base = snyq + (long long)l * nyq_cpx(g) + (valid ? row : 0) * g.ny;
-    es_g = 1;
+    obase = base;
+    es_g = es_o = 1;
     lp = lds + slot * NY;
     es_l = 1;
   }
   cpx<T> v[P];
+  if (!main || LAY != YL_FROM_PAIRED) {
 #pragma unroll
-  for (int i = 0; i < P; ++i) v[i] = valid ? ld_seg<SEG>(base + (long long)(t + TY * i) * es_g) : cpx<T>{0, 0};
+    for (int i = 0; i < P; ++i) v[i] = valid ? ld_seg<SEG>(base + (long long)(t + TY * i) * es_g) : cpx<T>{0, 0};
+  } else {
+#pragma unroll
+    for (int i = 0; i < P; ++i) v[i] = valid ? ld_seg<SEGP>(base + (long long)(t + TY * i) * es_g) : cpx<T>{0, 0};
+  }
   // twiddles staged after the pencil reads are issued (their wait would hold the reads back)
   for (int i = tid; i < NY; i += TX * TY) twl[i] = twy[i];
   __syncthreads();
   fft_pencil<NY, P, DIR, T>(v, t, lp, es_l, twl, 1);
   if (valid) {
+    if (!main || LAY != YL_TO_PAIRED) {
 #pragma unroll
-    for (int i = 0; i < P; ++i) st_seg<SEG>(base + (long long)(t + TY * i) * es_g, v[i]);
+      for (int i = 0; i < P; ++i) st_seg<SEG>(obase + (long long)(t + TY * i) * es_o, v[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < P; ++i) st_seg<SEGP>(obase + (long long)(t + TY * i) * es_o, v[i]);
+    }
   }
 }
 
@@ -568,7 +615,10 @@ __device__ __forceinline__ void xcd_load_tile(const int id, const int ntile, con
   }
 }
 
-template <typename T, int NZ, int P, int TX, int C, bool GS>
+// PR: the main spectrum is in the component-paired layout of the y pass
+// (YL_TO_PAIRED), each pair of components read and written as one 16-byte
+// access; the Nyquist rows keep the plain layout.
+template <typename T, int NZ, int P, int TX, int C, bool GS, bool PR = false>
 __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenParams gp, const GreenTabs<T> tb,
                                                    const int zmode, cpx<T>* __restrict__ smain,
                                                    cpx<T>* __restrict__ snyq, const cpx<T>* __restrict__ twz,
@@ -616,16 +666,41 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
     cstride = (long long)g.nz * g.ny;
   }
   cpx<T>* lp = lds + xl;
+  // paired layout (main tiles): pair m of wave-vector (kx, ky, kz) at
+  // pbase + 2 m cstride + kz pes, 16-byte aligned
+  static_assert(!PR || (GS && C % 2 == 0 && sizeof(T) == 4), "paired z pass: stored operator, FP32 component pairs");
+  using Q4 = float4;
+  const bool pm = PR && tid_tile < main_tiles;
+  cpx<T>* pbase = nullptr;
+  long long pes = 0;
+  if (pm) {
+    pbase = smain + (long long)l * main_cpx(g) + (long long)ky * 2 * g.mx + 2 * (valid ? kx : 0);
+    pes = (long long)g.ny * 2 * g.mx;
+  }
 
   // all components' loads are issued before the first transform (guarded
   // reads: unguarded ones let the scheduler raise this kernel past 256 VGPRs),
   // and before the twiddles are staged, whose wait would otherwise hold them back
   cpx<T> v[C][P];
+  if (pm) {
+    if constexpr (PR) {
 #pragma unroll
-  for (int j = 0; j < C; ++j)
+      for (int j = 0; j < C; j += 2)
 #pragma unroll
-    for (int i = 0; i < P; ++i)
-      v[j][i] = valid ? z_load<T, SEG>(base + j * cstride + (long long)(t + TZ * i) * es_g) : cpx<T>{0, 0};
+        for (int i = 0; i < P; ++i) {
+          const Q4 q = valid ? *reinterpret_cast<const Q4*>(pbase + (long long)j * cstride + (long long)(t + TZ * i) * pes)
+                             : Q4{0, 0, 0, 0};
+          v[j][i] = cpx<T>{q.x, q.y};
+          v[j + 1][i] = cpx<T>{q.z, q.w};
+        }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        v[j][i] = valid ? z_load<T, SEG>(base + j * cstride + (long long)(t + TZ * i) * es_g) : cpx<T>{0, 0};
+  }
   for (int i = tid; i < NZ; i += TX * TZ) twl[i] = twz[i];
   __syncthreads();
   fft_pencil_multi<NZ, P, -1, T, C, CG>(v, t, lp, TX, twl, 1, TX * NZ);
@@ -695,7 +770,16 @@ __global__ __launch_bounds__(TX*(NZ / P)) void k_zg(const Geo g, const GreenPara
     }
     fft_pencil_multi<NZ, P, 1, T, C, CG>(v, t, lp, TX, twl, 1, TX * NZ);
   }
-  if (valid) {
+  if (valid && pm) {
+    if constexpr (PR) {
+#pragma unroll
+      for (int j = 0; j < C; j += 2)
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+          *reinterpret_cast<Q4*>(pbase + (long long)j * cstride + (long long)(t + TZ * i) * pes) =
+              Q4{v[j][i].x, v[j][i].y, v[j + 1][i].x, v[j + 1][i].y};
+    }
+  } else if (valid) {
 #pragma unroll
     for (int j = 0; j < C; ++j)
 #pragma unroll
@@ -1188,9 +1272,6 @@ __global__ __launch_bounds__(256) void k_consistent_table(const Geo g, const Gre
 // ----------------------------------------------------------------------------
 // elementwise kernels
 // ----------------------------------------------------------------------------
-template <typename T> struct Vec16;
-template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
-template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
 
 template <typename V> __device__ __forceinline__ double vdot(const V& a, const V& b);
 template <> __device__ __forceinline__ double vdot<float4>(const float4& a, const float4& b) {

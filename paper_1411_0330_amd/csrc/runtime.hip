@@ -801,6 +801,26 @@ void tune_from_env(lsh_ctx* ctx) {
   }
 }
 
+// The component-paired spectrum of the Green pass's 8-pencil shape (z
+// variant kZPaired): FP32 six-component fields of a mixed context with the
+// stored operator and 128- or 256-point y and z axes.  The y forward pass
+// writes it and the y inverse pass reads it back, out of place; it lives in
+// the FP64 spectrum buffer (4F of its 8F bytes per load), which holds nothing
+// between FP64 applications.  Null where the shape does not apply: the passes
+// then run in place on the plain layout.
+template <typename T>
+cpx<T>* paired_spectrum(lsh_ctx* ctx, int l0) {
+  if constexpr (sizeof(T) == 4) {
+    const Geo& g = ctx->geo;
+    auto ax = [](int n) { return n == 128 || n == 256; };
+    if (ctx->precision != LSH_MIXED || ctx->ovr_sm || ctx->tune[0][PASS_ZG] != kZPaired || g.c != 6 ||
+        !ax(g.ny) || !ax(g.nz) || Sel<float>::gst(ctx) == nullptr)
+      return nullptr;
+    return ctx->ptr<cpx<float>>(ctx->off.s64m) + (long long)l0 * main_cpx(g);
+  }
+  return nullptr;
+}
+
 // Forward passes on load slots [l0, l0+nload): x (mode), y, z (+Gamma and inverse z), y inverse.
 template <typename T>
 lsh_status forward_part(lsh_ctx* ctx, int l0, int nload, int xmode, const T* src, T* pdir, T* xacc,
@@ -820,24 +840,30 @@ lsh_status forward_part(lsh_ctx* ctx, int l0, int nload, int xmode, const T* src
     Scope sc(ctx, kcls<T>(K_XFWD), nl * (xin + spec));
     STCHK(check_launch(ctx, launch_xfwd<T>(ctx->stream, xa, nload, tv<T>(ctx, PASS_XFWD)), "x forward"));
   }
+  cpx<T>* sp = gamma ? paired_spectrum<T>(ctx, l0) : nullptr;
   {
     Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
-    STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, -1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y)),
-                       "y forward"));
+    const int nb = sp ? launch_y_paired<T>(ctx->stream, g, -1, sm, sp, sn, Sel<T>::tw(ctx, 1), st, nload,
+                                           tv<T>(ctx, PASS_Y))
+                      : launch_y<T>(ctx->stream, g, -1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y));
+    STCHK(check_launch(ctx, nb, "y forward"));
   }
   {
     Scope sc(ctx, kcls<T>(K_ZG), nl * 2.0 * spec);
     GreenTabs<T> tb{Sel<T>::wt(ctx), ctx->wstride, {Sel<T>::tw(ctx, 0), Sel<T>::tw(ctx, 1), Sel<T>::tw(ctx, 2)},
                     Sel<T>::gtab(ctx), Sel<T>::gst(ctx)};
-    STCHK(check_launch(ctx,
-                       launch_zg<T>(ctx->stream, g, ctx->gp, tb, gamma ? Z_GAMMA : Z_FWD, sm, sn, Sel<T>::tw(ctx, 2),
-                                    st, nload, tv<T>(ctx, PASS_ZG)),
-                       "z/Green"));
+    const int nb = sp ? launch_zg_paired<T>(ctx->stream, g, ctx->gp, tb, sp, sn, Sel<T>::tw(ctx, 2), st, nload,
+                                            nullptr, 0)
+                      : launch_zg<T>(ctx->stream, g, ctx->gp, tb, gamma ? Z_GAMMA : Z_FWD, sm, sn, Sel<T>::tw(ctx, 2),
+                                     st, nload, tv<T>(ctx, PASS_ZG));
+    STCHK(check_launch(ctx, nb, "z/Green"));
   }
   if (gamma) {
     Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
-    STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, 1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y)),
-                       "y inverse"));
+    const int nb = sp ? launch_y_paired<T>(ctx->stream, g, 1, sm, sp, sn, Sel<T>::tw(ctx, 1), st, nload,
+                                           tv<T>(ctx, PASS_Y))
+                      : launch_y<T>(ctx->stream, g, 1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y));
+    STCHK(check_launch(ctx, nb, "y inverse"));
   }
   return LSH_OK;
 }
@@ -925,24 +951,31 @@ lsh_status cg_fused_step(lsh_ctx* ctx, int l0, int nload, T* x, T* r, const T* p
     nbx = launch_xfwdc<T>(ctx->stream, xa, nload);
     STCHK(check_launch(ctx, nbx, "x forward (CG)"));
   }
+  cpx<T>* sp = paired_spectrum<T>(ctx, l0);
   {
     Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
-    STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, -1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y)),
-                       "y forward"));
+    const int nb = sp ? launch_y_paired<T>(ctx->stream, g, -1, sm, sp, sn, Sel<T>::tw(ctx, 1), st, nload,
+                                           tv<T>(ctx, PASS_Y))
+                      : launch_y<T>(ctx->stream, g, -1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y));
+    STCHK(check_launch(ctx, nb, "y forward"));
   }
   {
     Scope sc(ctx, kcls<T>(K_ZG), nl * 2.0 * spec);
     GreenTabs<T> tb{Sel<T>::wt(ctx), ctx->wstride, {Sel<T>::tw(ctx, 0), Sel<T>::tw(ctx, 1), Sel<T>::tw(ctx, 2)},
                     Sel<T>::gtab(ctx), Sel<T>::gst(ctx)};
-    nbz = launch_zg<T>(ctx->stream, g, ctx->gp, tb, Z_GAMMA, sm, sn, Sel<T>::tw(ctx, 2), st, nload,
-                       tv<T>(ctx, PASS_ZG), parts + nbx, (int)ctx->pstride);
+    nbz = sp ? launch_zg_paired<T>(ctx->stream, g, ctx->gp, tb, sp, sn, Sel<T>::tw(ctx, 2), st, nload, parts + nbx,
+                                   (int)ctx->pstride)
+             : launch_zg<T>(ctx->stream, g, ctx->gp, tb, Z_GAMMA, sm, sn, Sel<T>::tw(ctx, 2), st, nload,
+                            tv<T>(ctx, PASS_ZG), parts + nbx, (int)ctx->pstride);
     STCHK(check_launch(ctx, nbz, "z/Green"));
   }
   if (scalars) STCHK(scal(ctx, SC_ALPHA, nload, nbx + nbz, st, ctx->bd_guard[sizeof(T) == 8 ? 1 : 0], l0, par));
   {
     Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
-    STCHK(check_launch(ctx, launch_y<T>(ctx->stream, g, 1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y)),
-                       "y inverse"));
+    const int nb = sp ? launch_y_paired<T>(ctx->stream, g, 1, sm, sp, sn, Sel<T>::tw(ctx, 1), st, nload,
+                                           tv<T>(ctx, PASS_Y))
+                      : launch_y<T>(ctx->stream, g, 1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y));
+    STCHK(check_launch(ctx, nb, "y inverse"));
   }
   STCHK(inverse_x<T>(ctx, l0, nload, XI_CGR, pout, r, nullptr, st, parts, &nbi, r));
   return scalars ? scal(ctx, SC_BETA, nload, nbi, st, 0.0, l0) : LSH_OK;
@@ -2364,7 +2397,11 @@ lsh_status lsh_autotune(lsh_ctx* ctx, int nload, const char* cache_path, int32_t
   }
   for (int prec = ctx->precision == LSH_MIXED ? 0 : 1; prec < 2; ++prec) {
     const bool fp64 = prec == 1;
-    for (int pass = 0; pass < NPASS; ++pass) {
+    // the z pass before the y passes: its shape 5 sets the spectrum layout the
+    // y passes convert, so they are timed in the layout they will run in
+    const int order[NPASS] = {PASS_XFWD, PASS_ZG, PASS_Y, PASS_XINV};
+    for (int pi = 0; pi < NPASS; ++pi) {
+      const int pass = order[pi];
       if (!pass_has_variants(ctx, pass)) continue;
       // the fused CG x pass has one shape (CG fields: FP32 of a mixed context, FP64 of an FP64 one)
       if (pass == PASS_XFWD && ctx->cg_fused && (!fp64 || ctx->precision != LSH_MIXED)) continue;

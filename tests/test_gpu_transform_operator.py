@@ -276,3 +276,43 @@ def test_multi_load_z_pass_in_a_batched_solve(lsh, monkeypatch, physics):
     A4, it4 = res["zg32=4"]
     assert rel_max_err(A4, A0_) <= 1e-7
     assert all(abs(a - b) <= 3 for a, b in zip(it0, it4))
+
+
+@pytest.mark.parametrize("shape,nload,ytune", [((128, 128, 16), 2, "0"), ((128, 128, 48), 3, "3"),
+                                               ((128, 256, 8), 1, "3"), ((256, 256, 16), 2, "1")])
+def test_paired_z_pass_matches_oracle(lsh, monkeypatch, shape, nload, ytune):
+    # z pass shape 5: the y forward pass writes the component-paired layout
+    # (16 or 32 wave-vectors of two components per tile), the z pass reads and
+    # writes it in 8-pencil tiles, the y inverse pass writes the plain layout
+    # back; ragged tiles (mx = 24 of 32 wave-vectors in a y tile of shape 3,
+    # mx = 4 of 8 pencils in a z tile), a masked phase, and y shape 1 (too
+    # narrow for paired rows) falling back to shape 0
+    monkeypatch.setenv("LSH_TUNE", f"zg32=5,y32={ytune}")
+    ph, moduli, A0 = _op_setup("elastic", shape, "filtered", "masked")
+    pb = problem(ph, moduli, A0, "elastic", "filtered")
+    ctx = context(lsh, ph, moduli, A0, "elastic", "filtered", precision="mixed", max_loads=nload)
+    assert ctx.variants()["fp32"][2] == 5
+    m = op.mask(pb)
+    tau = I.random_field(shape, pb.c, nload, seed=23) * m
+    out = ctx.apply(to_dev(tau, "f32")).cpu().numpy()
+    ref = np.stack([op.apply(pb, tau[l]) for l in range(nload)])
+    assert rel_max_err(out, ref) <= 1e-5
+
+
+def test_paired_z_pass_in_a_batched_solve(lsh, monkeypatch):
+    # the fused CG step on the paired layout, loads converging at different
+    # steps (frozen loads skipped), against the plain layout's solve
+    ph = I.random_phases((128, 128, 16), 2, seed=5)
+    moduli, A0 = np.stack([ELAS[0], ELAS[1]]), C0
+    loads = np.eye(6)[[0, 3, 5]] * np.array([[1.0], [1e-3], [5.0]])
+    res = {}
+    for tune in ("zg32=0", "zg32=5"):
+        monkeypatch.setenv("LSH_TUNE", tune)
+        ctx = context(lsh, ph, moduli, A0, "elastic", "filtered", precision="mixed", max_loads=3)
+        rep = ctx.solve(loads, "cg", tol=1e-8, maxit=2000)
+        assert rep["status"] == lsh.OK
+        res[tune] = (ctx.effective().copy(), rep["iterations"])
+    A0_, it0 = res["zg32=0"]
+    A5, it5 = res["zg32=5"]
+    assert rel_max_err(A5, A0_) <= 1e-7
+    assert all(abs(a - b) <= 3 for a, b in zip(it0, it5))
