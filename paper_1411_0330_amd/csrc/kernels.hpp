@@ -444,32 +444,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(xfwdc_waves
     __builtin_amdgcn_sched_barrier(0);
   }
   if (!valid) part = 0.0;
-  // R2C of every component: half-length transforms, then the unpacking
+  // R2C of every component: half-length transforms, then the unpacking (CG
+  // components per exchange, in the exchange buffers of the transforms)
   cpx<T>* lrow = lds + slot * MX;
   fft_pencil_multi<MX, P, -1, T, C, CG>(v, t, lrow, 1, twl, 2, RPW * MX);
 #pragma unroll
-  for (int j = 0; j < C; ++j) {
+  for (int j0 = 0; j0 < C; j0 += CG) {
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < P; ++i) lrow[t + TR * i] = v[j][i];
-    __syncthreads();
-    const long long row = (long long)j * vrows + vrc;
-    const long long so = (long long)l * main_cpx(g) + row * MX;
+    for (int jj = 0; jj < CG; ++jj)
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const int k = t + TR * i;
-      const cpx<T> z = v[j][i];
-      if (k == 0) {
-        if (valid) {
-          st_seg<SEG>(a.smain + so, cpx<T>{z.x + z.y, T(0)});
-          a.snyq[(long long)l * nyq_cpx(g) + row] = cpx<T>{z.x - z.y, T(0)};
+      for (int i = 0; i < P; ++i) lrow[jj * RPW * MX + t + TR * i] = v[j0 + jj][i];
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < CG; ++jj) {
+      const int j = j0 + jj;
+      const long long row = (long long)j * vrows + vrc;
+      const long long so = (long long)l * main_cpx(g) + row * MX;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int k = t + TR * i;
+        const cpx<T> z = v[j][i];
+        if (k == 0) {
+          if (valid) {
+            st_seg<SEG>(a.smain + so, cpx<T>{z.x + z.y, T(0)});
+            a.snyq[(long long)l * nyq_cpx(g) + row] = cpx<T>{z.x - z.y, T(0)};
+          }
+        } else {
+          const cpx<T> zm = lrow[jj * RPW * MX + MX - k];
+          const cpx<T> s1 = cpx<T>{z.x + zm.x, z.y - zm.y};   // Z + conj(Zm)
+          const cpx<T> d1 = cpx<T>{z.x - zm.x, z.y + zm.y};   // Z - conj(Zm)
+          const cpx<T> wo = cmul(twl[k], mul_neg_i(d1));
+          if (valid) st_seg<SEG>(a.smain + so + k, cpx<T>{T(0.5) * (s1.x + wo.x), T(0.5) * (s1.y + wo.y)});
         }
-      } else {
-        const cpx<T> zm = lrow[MX - k];
-        const cpx<T> s1 = cpx<T>{z.x + zm.x, z.y - zm.y};   // Z + conj(Zm)
-        const cpx<T> d1 = cpx<T>{z.x - zm.x, z.y + zm.y};   // Z - conj(Zm)
-        const cpx<T> wo = cmul(twl[k], mul_neg_i(d1));
-        if (valid) st_seg<SEG>(a.smain + so + k, cpx<T>{T(0.5) * (s1.x + wo.x), T(0.5) * (s1.y + wo.y)});
       }
     }
   }
@@ -978,23 +985,30 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
     nqs[j] = a.snyq[(long long)l * nyq_cpx(g) + srow];
   }
   // repack each component's half spectrum as the half-length complex
-  // transform 2Z = 2E + i 2O, then the inverse transforms of all components
+  // transform 2Z = 2E + i 2O (CG components per exchange, in the exchange
+  // buffers of the transforms), then the inverse transforms of all components
 #pragma unroll
-  for (int j = 0; j < C; ++j) {
-    const cpx<T> nq = nqs[j];
+  for (int j0 = 0; j0 < C; j0 += CG) {
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < P; ++i) lrow[t + TR * i] = gam[j][i];
+    for (int jj = 0; jj < CG; ++jj)
+#pragma unroll
+      for (int i = 0; i < P; ++i) lrow[jj * RPW * MX + t + TR * i] = gam[j0 + jj][i];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const int k = t + TR * i;
-      const cpx<T> xk = gam[j][i];
-      const cpx<T> xm = (k == 0) ? nq : lrow[MX - k];
-      const cpx<T> e = cpx<T>{xk.x + xm.x, xk.y - xm.y};          // 2E = X + conj(Xm)
-      const cpx<T> d = cpx<T>{xk.x - xm.x, xk.y + xm.y};          // X - conj(Xm)
-      const cpx<T> o = cmulc(d, twl[k]);                          // 2O = (X - conj Xm) W^{-k}
-      gam[j][i] = cadd(e, mul_i(o));
+    for (int jj = 0; jj < CG; ++jj) {
+      const int j = j0 + jj;
+      const cpx<T> nq = nqs[j];
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int k = t + TR * i;
+        const cpx<T> xk = gam[j][i];
+        const cpx<T> xm = (k == 0) ? nq : lrow[jj * RPW * MX + MX - k];
+        const cpx<T> e = cpx<T>{xk.x + xm.x, xk.y - xm.y};          // 2E = X + conj(Xm)
+        const cpx<T> d = cpx<T>{xk.x - xm.x, xk.y + xm.y};          // X - conj(Xm)
+        const cpx<T> o = cmulc(d, twl[k]);                          // 2O = (X - conj Xm) W^{-k}
+        gam[j][i] = cadd(e, mul_i(o));
+      }
     }
   }
   __syncthreads();
