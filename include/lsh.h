@@ -264,6 +264,24 @@ lsh_status lsh_get_field(lsh_ctx* ctx, int load, int which, void* dst, int dtype
 lsh_status lsh_get_effective(lsh_ctx* ctx, double* sigma_mean);
 
 /*
+ * Residual history of load `load` in the last solve: the relative residual
+ * ||r_k|| / ||b|| after every iteration, in order, as the solver's own
+ * recurrences give it (CG: the recursive residual of Section 5's CG setting;
+ * the fixed-point schemes of Section 3: the residual of the iterate; MINRES:
+ * |phi_k|; SYMMLQ: the residual of the CG point, +inf where it has none),
+ * with a level per entry: 0 for an FP64 iteration (and the FP64 residual
+ * b - L tau that a mixed solve refreshes after each inner solve), 1 for an
+ * iteration of the FP32 inner CG of a mixed solve, relative to its own
+ * right-hand side (the FP64 residual it started from).  The device keeps the
+ * last 4096 entries per load.  Copies the last min(cap, total, 4096) entries
+ * into rel and level (host arrays of cap entries; both may be NULL when cap
+ * is 0) and the number of entries the solve made into *total (may be NULL).
+ * Synchronises the context's stream.  LSH_EINVAL for a load beyond the last
+ * solve's or cap < 0.
+ */
+lsh_status lsh_get_residual_history(lsh_ctx* ctx, int load, int cap, double* rel, int32_t* level, int64_t* total);
+
+/*
  * Derivative of J = sum_lm W_lm p_l . A*_h p_m over the loads of the last solve
  * (W: host FP64 nload x nload, symmetrised as (W + W^T)/2) with respect to the
  * isotropic coefficients of every voxel.  The operator M of eq. (13) is

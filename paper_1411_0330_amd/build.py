@@ -25,6 +25,9 @@ FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", CSRC, "-I", INCLUDE]
 
+# roctx ranges (rocprofiler-sdk) for profiler timelines
+LINK = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
+
 UNITS = [
     ("k_x.hip", "k_x_f32.o", ["-DLSH_X_TYPE=float", "-DLSH_X_PART=0"]),
     ("k_x.hip", "k_x_f64.o", ["-DLSH_X_TYPE=double", "-DLSH_X_PART=0"]),
@@ -77,7 +80,7 @@ def build(verbose: bool = True, jobs: int | None = None) -> str:
                 print(f"[build] compiled {obj}", flush=True)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC",
-           *[os.path.join(OBJDIR, u[1]) for u in UNITS], "-o", tmp]
+           *[os.path.join(OBJDIR, u[1]) for u in UNITS], *LINK, "-o", tmp]
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
         raise RuntimeError(f"link failed:\n{proc.stderr[-6000:]}")
@@ -85,6 +88,46 @@ def build(verbose: bool = True, jobs: int | None = None) -> str:
     if verbose:
         print(f"[build] wrote {LIB}", flush=True)
     return LIB
+
+
+SAN_DIR = os.path.join(ROOT, "_build", "hostsan")
+
+
+def sanitizer_runtime() -> str:
+    """Path of the compiler's AddressSanitizer runtime (preloaded into the
+    process that loads the host-sanitizer build)."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "lib", "llvm", "bin", "clang")
+    if not os.path.exists(clang):
+        clang = shutil.which("amdclang") or "/opt/rocm/llvm/bin/clang"
+    out = subprocess.run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    return out.stdout.strip()
+
+
+def build_host_sanitized() -> str:
+    """Host-side AddressSanitizer + UndefinedBehaviorSanitizer build of the
+    library: runtime.hip (every host line of the C ABI, the solvers' control
+    flow, the scheduler) compiled with both sanitizers on its host pass only,
+    linked with the device units of the last build().  Device code is
+    unchanged (GPU sanitizers are not used).  Returns the library path."""
+    objs = [os.path.join(OBJDIR, u[1]) for u in UNITS if u[0] != "runtime.hip"]
+    missing = [o for o in objs if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError(f"device units not built (run build() first): {missing[:3]}")
+    os.makedirs(SAN_DIR, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+    obj = os.path.join(SAN_DIR, "runtime_san.o")
+    flags = [f if f != "-O3" else "-O1" for f in FLAGS]
+    proc = subprocess.run([hipcc(), *flags, *san, "-c", os.path.join(CSRC, "runtime.hip"), "-o", obj],
+                          capture_output=True, text=True)
+    if proc.returncode != 0:
+        raise RuntimeError(f"sanitized compile failed:\n{proc.stderr[-4000:]}")
+    lib = os.path.join(SAN_DIR, "liblsh_hostsan.so")
+    proc = subprocess.run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *san[:4], "-shared-libsan",
+                           *objs, obj, *LINK, "-o", lib], capture_output=True, text=True)
+    if proc.returncode != 0:
+        raise RuntimeError(f"sanitized link failed:\n{proc.stderr[-4000:]}")
+    return lib
 
 
 if __name__ == "__main__":

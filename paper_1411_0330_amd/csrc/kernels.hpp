@@ -41,6 +41,28 @@ struct LoadState {
   int pbuf;      // fused step: direction buffer (0/1) holding the newest pending direction
 };
 
+// Residual history: per load a ring of kHistCap entries, each the squared
+// relative residual ||r||^2 / ||b||^2 of the iterated state after one
+// iteration and its level (0: FP64 solve or the FP64 refinement residual of a
+// mixed solve, 1: the FP32 inner CG of a mixed solve, relative to its own
+// right-hand side, the FP64 residual it started from), and per load the
+// number of entries written since the solve began.  One writer per load at a
+// time (thread 0 of the load's scalar workgroup).
+constexpr int kHistCap = 4096;
+struct HistRef {
+  double* ring;                 // [load][kHistCap][2], null: no history
+  unsigned long long* count;    // [load]
+  int level;
+};
+__device__ __forceinline__ void hist_push(const HistRef& h, const int load, const double rel2) {
+  if (h.ring == nullptr) return;
+  const unsigned long long i = h.count[load];
+  h.count[load] = i + 1;
+  double* e = h.ring + ((long long)load * kHistCap + (long long)(i % kHistCap)) * 2;
+  e[0] = rel2;
+  e[1] = (double)h.level;
+}
+
 struct Geo {
   int nx, ny, nz, mx, c, pad;
   long long nvox;  // nx*ny*nz

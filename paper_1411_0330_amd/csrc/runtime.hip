@@ -22,10 +22,24 @@
 #include <sys/mman.h>
 #include <ucontext.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "dispatch.hpp"
 #include "solver_kernels.hpp"
 #include "tiny.hpp"
 #include "lsh.h"
+
+// Named host ranges for profilers (rocprofv3 --marker-trace): setup, solves,
+// the inner solves and refinement residuals of the mixed path, tuning and
+// ensembles.  Started and stopped by id (not a per-thread stack), since the
+// members of an ensemble interleave on one thread as fibers.
+struct TraceRange {
+  roctx_range_id_t id;
+  explicit TraceRange(const char* name) : id(roctxRangeStartA(name)) {}
+  ~TraceRange() { roctxRangeStop(id); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 using namespace lsh;
 
@@ -188,9 +202,10 @@ struct lsh_ctx {
   // plane in the per-device scratch array)
   void* ovr_sm = nullptr;
   void* ovr_sn = nullptr;
+  int hist_loads = 0;   // loads of the last solve (their residual histories are valid)
   struct {
     size_t x64, r64, p64, p64b, d32, r32, p32, p32b, s64m, s64n, s32m, s32n, phase, i0, ptab64, ptab32, vc64, vc32, tw64, tw32,
-        wt64, wt32, loads, wgrad, st_out, st_in, mstate, guess, partials, sums, gst, end;
+        wt64, wt32, loads, wgrad, st_out, st_in, mstate, guess, partials, sums, gst, hist, hcnt, end;
   } off{};
   long long pstride = 0, nsums = 0;
   int twoff[3] = {0, 0, 0};
@@ -455,6 +470,9 @@ void compute_layout(lsh_ctx* ctx) {
     const int ng = c == 6 ? store_groups<6>() : store_groups<3>();
     ctx->off.gst = take((mixed ? sizeof(float) : sizeof(double)) * 4 * ng * nk);
   }
+  // residual history: a ring of kHistCap (value, level) pairs and a count per load
+  ctx->off.hist = take(sizeof(double) * 2 * kHistCap * L);
+  ctx->off.hcnt = take(sizeof(unsigned long long) * L);
   ctx->off.end = o;
   ctx->ws_need = o;
 }
@@ -513,6 +531,7 @@ lsh_status upload_consts(lsh_ctx* ctx) {
 
 // Phase tables against the current A0: (A-A0)^{-1}, (A-A0), I0 flag; checks hypothesis (2).
 lsh_status build_tables(lsh_ctx* ctx) {
+  TraceRange tr("lsh setup: material tables");
   const int c = ctx->c;
   const int tabw = 2 * c * c + 5;
   ctx->h_ptab64.assign((size_t)kMaxPhases * tabw, 0.0);
@@ -982,11 +1001,20 @@ lsh_status cg_fused_step(lsh_ctx* ctx, int l0, int nload, T* x, T* r, const T* p
 }
 
 // groups [l0, l0 + ngroups): the partials of group l at (l0 + l) pstride; st is already offset
+// Residual history of loads [l0, ...) at `level` (see hist_push).
+HistRef hist_ref(lsh_ctx* ctx, int l0, int level) {
+  return HistRef{ctx->ptr<double>(ctx->off.hist) + (long long)l0 * 2 * kHistCap,
+                 ctx->ptr<unsigned long long>(ctx->off.hcnt) + l0, level};
+}
+
 lsh_status scal(lsh_ctx* ctx, int mode, int ngroups, int nparts, LoadState* st, double tol, int l0, int aux) {
   Scope sc(ctx, K_SCAL);
+  // the inner FP32 states of a mixed solve record at level 1, every other state at 0
+  const LoadState* sin = ctx->ptr<LoadState>(ctx->off.st_in);
+  const int level = (st >= sin && st < sin + ctx->max_loads) ? 1 : 0;
   hipLaunchKernelGGL(k_scal, dim3(ngroups), dim3(256), 0, ctx->stream, mode,
                      ctx->ptr<double>(ctx->off.partials) + (long long)l0 * ctx->pstride, (int)ctx->pstride, nparts,
-                     st, ctx->ptr<double>(ctx->off.sums) + l0, tol, aux);
+                     st, ctx->ptr<double>(ctx->off.sums) + l0, tol, aux, hist_ref(ctx, l0, level));
   return check_launch(ctx, 0, "scalars");
 }
 
@@ -1140,6 +1168,7 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, T* pb, LoadState* 
     ta.gp = ctx->gp;
     ta.tb = GreenTabs<T>{Sel<T>::wt(ctx), ctx->wstride, {Sel<T>::tw(ctx, 0), Sel<T>::tw(ctx, 1), Sel<T>::tw(ctx, 2)},
                          Sel<T>::gtab(ctx), nullptr};
+    ta.hist = hist_ref(ctx, 0, (sizeof(T) == 4 && ctx->precision == LSH_MIXED) ? 1 : 0);
     ta.x = x;
     ta.r = r;
     ta.p = p;
@@ -1242,7 +1271,7 @@ lsh_status mr_loop(lsh_ctx* ctx, int nload, double tol, int maxit, std::vector<L
   {
     Scope sc(ctx, K_SCAL);
     hipLaunchKernelGGL(k_mr_scal, dim3(nload), dim3(256), 0, ctx->stream, (int)MR_INIT, parts, (int)ctx->pstride, 0,
-                       st, ms);
+                       st, ms, hist_ref(ctx, 0, 0));
     STCHK(check_launch(ctx, 0, "minres init"));
   }
   const int period = check_period(ctx, nload);
@@ -1260,7 +1289,7 @@ lsh_status mr_loop(lsh_ctx* ctx, int nload, double tol, int maxit, std::vector<L
     {
       Scope sc(ctx, K_SCAL);
       hipLaunchKernelGGL(k_mr_scal, dim3(nload), dim3(256), 0, ctx->stream, (int)MR_ALPHA, parts, (int)ctx->pstride,
-                         np, st, ms);
+                         np, st, ms, hist_ref(ctx, 0, 0));
       STCHK(check_launch(ctx, 0, "minres alpha"));
     }
     {
@@ -1272,7 +1301,7 @@ lsh_status mr_loop(lsh_ctx* ctx, int nload, double tol, int maxit, std::vector<L
     {
       Scope sc(ctx, K_SCAL);
       hipLaunchKernelGGL(k_mr_scal, dim3(nload), dim3(256), 0, ctx->stream, (int)MR_ROT, parts, (int)ctx->pstride,
-                         nbe, st, ms);
+                         nbe, st, ms, hist_ref(ctx, 0, 0));
       STCHK(check_launch(ctx, 0, "minres rotation"));
     }
     {
@@ -1316,7 +1345,7 @@ lsh_status sy_loop(lsh_ctx* ctx, int nload, double tol, int maxit, std::vector<L
   {
     Scope sc(ctx, K_SCAL);
     hipLaunchKernelGGL(k_sy_scal, dim3(nload), dim3(256), 0, ctx->stream, (int)SY_INIT, parts, (int)ctx->pstride, 0,
-                       0, st, ms);
+                       0, st, ms, hist_ref(ctx, 0, 0));
     STCHK(check_launch(ctx, 0, "symmlq init"));
   }
   const int period = check_period(ctx, nload);
@@ -1334,7 +1363,7 @@ lsh_status sy_loop(lsh_ctx* ctx, int nload, double tol, int maxit, std::vector<L
     {
       Scope sc(ctx, K_SCAL);
       hipLaunchKernelGGL(k_mr_scal, dim3(nload), dim3(256), 0, ctx->stream, (int)MR_ALPHA, parts, (int)ctx->pstride,
-                         np, st, ms);
+                         np, st, ms, hist_ref(ctx, 0, 0));
       STCHK(check_launch(ctx, 0, "symmlq alpha"));
     }
     {
@@ -1346,7 +1375,7 @@ lsh_status sy_loop(lsh_ctx* ctx, int nload, double tol, int maxit, std::vector<L
     {
       Scope sc(ctx, K_SCAL);
       hipLaunchKernelGGL(k_sy_scal, dim3(nload), dim3(256), 0, ctx->stream, (int)SY_ROT, parts, (int)ctx->pstride,
-                         nbe, it + 1 == maxit ? 1 : 0, st, ms);
+                         nbe, it + 1 == maxit ? 1 : 0, st, ms, hist_ref(ctx, 0, 0));
       STCHK(check_launch(ctx, 0, "symmlq rotation"));
     }
     {
@@ -1827,6 +1856,7 @@ lsh_status lsh_set_voxel_moduli(lsh_ctx* ctx, const void* m, int dtype, int mem,
 
 lsh_status lsh_gradient(lsh_ctx* ctx, const double* W, void* grad, int dtype) {
   if (!ctx) return LSH_EINVAL;
+  TraceRange tr("lsh_gradient");
   if (!W || !grad) return fail(ctx, LSH_EINVAL, "null weights or gradient buffer");
   if (dtype != LSH_F64 && dtype != LSH_F32) return fail(ctx, LSH_EINVAL, "bad dtype");
   if (!ctx->have_solution) return fail(ctx, LSH_ESTATE, "no solution");
@@ -1954,10 +1984,14 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
       ctx->tables_dirty = true;
     }
   }
+  TraceRange tr("lsh_solve");
   STCHK(prepare(ctx));
   ctx->nact = 1 << 30;
   const auto t0 = std::chrono::steady_clock::now();
   ctx->have_solution = false;
+  // residual histories start empty (outside any captured graph)
+  HIPCHK(hipMemsetAsync(ctx->ws + ctx->off.hcnt, 0, sizeof(unsigned long long) * nload, ctx->stream));
+  ctx->hist_loads = nload;
   ctx->last_nload = nload;
   ctx->last_loads.assign(loads, loads + (size_t)nload * c);
   ctx->h_loads = ctx->last_loads;
@@ -2016,7 +2050,10 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
     while (true) {
       if (!refine_first) {
         // inner FP32 solve, then refresh the residual in FP64 (x64 += d inside)
-        STCHK(cg_loop<float>(ctx, nload, d, r, p, ctx->ptr<float>(ctx->off.p32b), sti, ctx->off.st_in, budget, hin));
+        {
+          TraceRange tr_in("lsh_solve: inner FP32 CG");
+          STCHK(cg_loop<float>(ctx, nload, d, r, p, ctx->ptr<float>(ctx->off.p32b), sti, ctx->off.st_in, budget, hin));
+        }
         STCHK(read_states(ctx, ctx->off.st_in, nload, hin));
         int used = 0;
         for (int l = 0; l < nload; ++l) {
@@ -2034,11 +2071,14 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
       refine_first = false;
       ctx->nact = 0;
       for (auto& sv : hst) ctx->nact += sv.active != 0;
-      STCHK(forward_part<double>(ctx, 0, nload, XF_IRX, nullptr, x64, nullptr, d, sto, true));
-      int np = 0;
-      STCHK(inverse_x<double>(ctx, 0, nload, XI_IRRES, x64, nullptr, r, sto, ctx->ptr<double>(ctx->off.partials),
-                              &np));
-      STCHK(scal(ctx, SC_OUTER, nload, np, sto, 0.0));
+      {
+        TraceRange tr_ref("lsh_solve: FP64 refinement residual");
+        STCHK(forward_part<double>(ctx, 0, nload, XF_IRX, nullptr, x64, nullptr, d, sto, true));
+        int np = 0;
+        STCHK(inverse_x<double>(ctx, 0, nload, XI_IRRES, x64, nullptr, r, sto, ctx->ptr<double>(ctx->off.partials),
+                                &np));
+        STCHK(scal(ctx, SC_OUTER, nload, np, sto, 0.0));
+      }
       ++outer;
       STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
       bool ended = false;
@@ -2228,6 +2268,7 @@ lsh_status lsh_get_field(lsh_ctx* ctx, int load, int which, void* dst, int dtype
 
 lsh_status lsh_apply(lsh_ctx* ctx, int nload, const void* tau, void* out, int dtype) {
   if (!ctx) return LSH_EINVAL;
+  TraceRange tr("lsh_apply");
   if (nload < 1 || nload > ctx->max_loads) return fail(ctx, LSH_EINVAL, "nload out of range");
   if (!tau || !out || tau == out) return fail(ctx, LSH_EINVAL, "bad buffers");
   if (dtype != LSH_F64 && dtype != LSH_F32) return fail(ctx, LSH_EINVAL, "bad dtype");
@@ -2333,6 +2374,28 @@ lsh_status lsh_set_variant(lsh_ctx* ctx, int pass, int fp64, int variant) {
   return LSH_OK;
 }
 
+lsh_status lsh_get_residual_history(lsh_ctx* ctx, int load, int cap, double* rel, int32_t* level, int64_t* total) {
+  if (!ctx) return LSH_EINVAL;
+  if (load < 0 || load >= ctx->hist_loads) return fail(ctx, LSH_EINVAL, "no residual history for that load");
+  if (cap < 0 || (cap > 0 && (!rel || !level))) return fail(ctx, LSH_EINVAL, "bad history buffers");
+  unsigned long long cnt = 0;
+  std::vector<double> ring((size_t)2 * kHistCap);
+  HIPCHK(hipMemcpyAsync(&cnt, ctx->ws + ctx->off.hcnt + sizeof(unsigned long long) * load, sizeof(cnt),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ring.data(), ctx->ws + ctx->off.hist + sizeof(double) * 2 * kHistCap * load,
+                        sizeof(double) * ring.size(), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (total) *total = (int64_t)cnt;
+  // the last n entries in order (the ring keeps the last kHistCap)
+  const unsigned long long n = std::min<unsigned long long>({cnt, (unsigned long long)kHistCap, (unsigned long long)cap});
+  for (unsigned long long i = 0; i < n; ++i) {
+    const unsigned long long k = (cnt - n + i) % kHistCap;
+    rel[i] = std::sqrt(ring[2 * k]);
+    level[i] = (int32_t)ring[2 * k + 1];
+  }
+  return LSH_OK;
+}
+
 lsh_status lsh_get_variants(const lsh_ctx* ctx, int32_t* variants) {
   if (!ctx || !variants) return LSH_EINVAL;
   for (int p = 0; p < 2; ++p)
@@ -2342,6 +2405,7 @@ lsh_status lsh_get_variants(const lsh_ctx* ctx, int32_t* variants) {
 
 lsh_status lsh_autotune(lsh_ctx* ctx, int nload, const char* cache_path, int32_t* variants, int* from_cache) {
   if (!ctx) return LSH_EINVAL;
+  TraceRange tr("lsh_autotune");
   if (nload < 1 || nload > ctx->max_loads) return fail(ctx, LSH_EINVAL, "nload out of range");
   STCHK(prepare(ctx));
   const std::string key = tune_key(ctx, nload);
@@ -2453,6 +2517,7 @@ lsh_status lsh_solve_many(int n, lsh_ctx* const* ctxs, int solver, const int32_t
                           double tol, int maxit, lsh_load_report* const* reports, lsh_solve_report* summaries,
                           int32_t* statuses, int nthreads) {
   if (n < 1 || !ctxs || !nloads || !loads) return LSH_EINVAL;
+  TraceRange tr("lsh_solve_many");
   for (int i = 0; i < n; ++i) {
     if (!ctxs[i] || !loads[i]) return LSH_EINVAL;
     for (int j = 0; j < i; ++j)

@@ -108,7 +108,8 @@ __device__ __forceinline__ double group_sum(const double* __restrict__ partials,
 // at beta_{k+1} = 0 (exact solution) or, with gamma2 = 0, on breakdown.
 static __global__ __launch_bounds__(256) void k_mr_scal(const int mode, const double* __restrict__ partials,
                                                         const int pstride, const int nparts,
-                                                        LoadState* __restrict__ st, MinresState* __restrict__ ms) {
+                                                        LoadState* __restrict__ st, MinresState* __restrict__ ms,
+                                                        const HistRef hist) {
   __shared__ double red[256];
   const int l = blockIdx.x;
   const double S = mode == MR_INIT ? 0.0 : group_sum(partials, pstride, nparts, l, red);
@@ -162,6 +163,7 @@ static __global__ __launch_bounds__(256) void k_mr_scal(const int mode, const do
   M.c = c;
   M.s = s;
   L.res2 = M.phi * M.phi;
+  hist_push(hist, l, L.res2 / L.bb);
   if (L.res2 <= L.tol2 || bn == 0.0) L.active = 0;
 }
 
@@ -199,7 +201,8 @@ static __global__ __launch_bounds__(256) void k_sy_start(const long long F, doub
 // system singular on the Krylov space) is a breakdown.
 static __global__ __launch_bounds__(256) void k_sy_scal(const int mode, const double* __restrict__ partials,
                                                         const int pstride, const int nparts, const int last,
-                                                        LoadState* __restrict__ st, MinresState* __restrict__ ms) {
+                                                        LoadState* __restrict__ st, MinresState* __restrict__ ms,
+                                                        const HistRef hist) {
   __shared__ double red[256];
   const int l = blockIdx.x;
   const double S = mode == SY_INIT ? 0.0 : group_sum(partials, pstride, nparts, l, red);
@@ -229,10 +232,14 @@ static __global__ __launch_bounds__(256) void k_sy_scal(const int mode, const do
   const double dbar_next = -M.c * bn;
   const double num = M.first - delta * M.z1 - M.eps * M.z2;
   L.iters += 1;
-  double zbar = 0.0;
+  // the CG point and its residual (none, an infinite residual, when gbar = 0)
+  double zbar = 0.0, rc = (double)INFINITY;
   if (gbar != 0.0) {
     zbar = num / gbar;
-    const double rc = bn * fabs(M.s * M.z1 - M.c * zbar);
+    rc = bn * fabs(M.s * M.z1 - M.c * zbar);
+  }
+  hist_push(hist, l, rc * rc / L.bb);
+  if (gbar != 0.0) {
     L.res2 = rc * rc;
     if (L.res2 <= L.tol2) {
       M.zbar = zbar;
@@ -310,7 +317,8 @@ static __global__ __launch_bounds__(256) void k_sy_update(const long long F, dou
 // direction went to (its x pass applies pending steps in pairs).
 static __global__ __launch_bounds__(256) void k_scal(const int mode, const double* __restrict__ partials, const int pstride,
                                               const int nparts, LoadState* __restrict__ st,
-                                              double* __restrict__ sums, const double tol, const int aux) {
+                                              double* __restrict__ sums, const double tol, const int aux,
+                                              const HistRef hist) {
   __shared__ double red[256];
   const int grp = blockIdx.x;
   double s = 0.0;
@@ -394,10 +402,12 @@ static __global__ __launch_bounds__(256) void k_scal(const int mode, const doubl
     L.beta = S / L.rr;
     L.rr = S;
     L.res2 = S;
+    hist_push(hist, grp, S / L.bb);
     if (S <= L.tol2) L.active = 0;
   } else if (mode == SC_BASIC || mode == SC_OUTER) {
     L.iters += 1;
     L.res2 = S;
+    hist_push(hist, grp, S / L.bb);
     if (!isfinite(S)) {
       L.status = kStatusNumeric;
       L.active = 0;

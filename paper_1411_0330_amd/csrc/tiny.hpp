@@ -33,6 +33,7 @@ struct TinyArgs {
   LoadState* st;
   int maxit;
   double guard;   // CG breakdown when |p.Lp| <= guard r.r (see k_scal)
+  HistRef hist;   // residual history (see hist_push)
 };
 
 // workgroup sum of one double, returned to every thread (fixed order)
@@ -413,6 +414,7 @@ __global__ __launch_bounds__(NT) void k_tiny_cg(const TinyArgs<T> a) {
     }
     beta = rr_new / rr;
     rr = rr_new;
+    if (tid == 0) hist_push(a.hist, l, rr / st->bb);
     if (rr <= tol2) {
       done = true;
       break;

@@ -15,7 +15,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_lib", "liblsh.so")
+# LSH_LIB_PATH selects another build of the same library (the host-sanitizer
+# build of build.build_host_sanitized)
+LIB_PATH = os.environ.get("LSH_LIB_PATH") or os.path.join(HERE, "_lib", "liblsh.so")
 
 OK, MAXIT, EINVAL, ENOMEM, EHIP, EHYP2, EBREAKDOWN, ENUMERIC, ESTATE = 0, 1, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "OK", 1: "MAXIT", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EHYP2",
@@ -66,6 +68,8 @@ _SIGS = {
     "lsh_get_field": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int]),
     "lsh_set_initial_guess": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_int]),
     "lsh_get_effective": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "lsh_get_residual_history": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double),
+                                           C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "lsh_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "lsh_apply_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "lsh_forward_dft": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
@@ -319,6 +323,18 @@ class Context:
         out = np.zeros((self.nload, self.c))
         self._check(self.lib.lsh_get_effective(self.h, _dptr(out)))
         return out
+
+    def residual_history(self, load=0, cap=4096):
+        """Relative residual after every iteration of the last solve of `load`
+        (the last `cap` entries, at most 4096): dict with "rel" (float64),
+        "level" (int32: 0 FP64, 1 FP32 inner CG of a mixed solve) and "total"."""
+        rel = np.zeros(cap)
+        lev = np.zeros(cap, dtype=np.int32)
+        tot = C.c_int64(0)
+        self._check(self.lib.lsh_get_residual_history(self.h, int(load), int(cap), _dptr(rel),
+                                                      lev.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(tot)))
+        n = min(cap, tot.value, 4096)
+        return {"rel": rel[:n].copy(), "level": lev[:n].copy(), "total": int(tot.value)}
 
     def field(self, load=0, which="tau", dtype="f64", device=True):
         import torch

@@ -90,6 +90,7 @@ def test_reference_and_phase_validation_and_hypothesis2():
     assert lib.lsh_solve(h, L.CG, 1, dp([np.nan, 0.0]), 1e-8, 10, None, None) == L.EINVAL
     assert lib.lsh_set_green(h, 9) == L.EINVAL
     assert lib.lsh_get_effective(h, dp(np.zeros(4))) == L.ESTATE
+    assert lib.lsh_get_residual_history(h, 0, 0, None, None, None) == L.EINVAL   # no solve yet
     lib.lsh_destroy(h)
 
 

@@ -237,3 +237,56 @@ def test_switching_between_basic_and_eyre_milton(lsh):
     assert np.array_equal(out[1][0], out[3][0]) and out[1][1] == out[3][1]
     for A, _ in out[1:]:
         assert rel_max_err(A, out[0][0]) <= 1e-10
+
+
+@pytest.mark.parametrize("solver", ["cg", "basic", "minres", "symmlq", "eyre_milton"])
+def test_residual_history_matches_oracle(lsh, solver):
+    # the device ring holds the solver's relative residual after every
+    # iteration; FP64 solves give the oracle's history entry by entry
+    from oracle import solvers as S
+    from paper_1411_0330_amd import inputs as I
+    shape = (8, 16, 16)
+    ph = I.random_phases(shape, 2, seed=11)
+    mod = np.stack([np.eye(3), 8.0 * np.eye(3)])
+    A0 = 0.5 * np.eye(3) if solver in ("cg", "minres", "symmlq") else 4.5 * np.eye(3)
+    ctx = lsh.Context(shape, "scalar", "fp64", max_loads=2)
+    ctx.set_reference(A0)
+    ctx.set_phases(ph, mod)
+    ctx.set_green("filtered")
+    loads = np.array([[1.0, 0.0, 0.0], [0.0, 0.3, 1.0]])
+    tol = 1e-9
+    rep = ctx.solve(loads, solver, tol=tol, maxit=400)
+    pb = op.Problem(ph, mod, A0, "scalar", "filtered")
+    fn = {"cg": S.cg, "basic": S.basic, "minres": S.minres, "symmlq": S.symmlq, "eyre_milton": S.eyre_milton}[solver]
+    for l in range(2):
+        hist = []
+        fn(pb, loads[l], tol=tol, maxit=400, history=hist)
+        h = ctx.residual_history(l)
+        assert h["total"] == len(hist) == rep["iterations"][l]
+        assert np.all(h["level"] == 0)
+        ref = np.array(hist)
+        fin = np.isfinite(ref)
+        assert np.array_equal(np.isfinite(h["rel"]), fin)
+        np.testing.assert_allclose(h["rel"][fin], ref[fin], rtol=1e-6, atol=1e-13)
+
+
+def test_residual_history_of_a_mixed_solve(lsh):
+    # levels: FP32 inner CG entries (1) relative to their own right-hand side,
+    # each inner solve followed by one FP64 refinement entry (0); the last
+    # FP64 entry is the reported true residual
+    from paper_1411_0330_amd import inputs as I
+    shape = (8, 16, 16)
+    ph = I.random_phases(shape, 2, seed=12)
+    ctx = lsh.Context(shape, "scalar", "mixed", max_loads=1)
+    ctx.set_reference(0.5 * np.eye(3))
+    ctx.set_phases(ph, np.stack([np.eye(3), 10.0 * np.eye(3)]))
+    ctx.set_green("filtered")
+    rep = ctx.solve(np.eye(3)[:1], "cg", tol=1e-9, maxit=500)
+    h = ctx.residual_history(0)
+    lev, rel = h["level"], h["rel"]
+    assert h["total"] == len(rel) == rep["applications_fp32"] + rep["outer_iterations"]
+    assert np.sum(lev == 0) == rep["outer_iterations"] and np.sum(lev == 1) == rep["applications_fp32"]
+    assert lev[-1] == 0
+    np.testing.assert_allclose(rel[-1], rep["rel_residual"][0], rtol=1e-12)
+    outer = rel[lev == 0]
+    assert np.all(np.diff(outer) < 0)            # every refinement lowers the FP64 residual
