@@ -112,6 +112,9 @@ template <typename T> int launch_y(hipStream_t s, const Geo& g, int dir, cpx<T>*
 // held in sp; -1 where the shape has no such instance
 template <typename T> int launch_y_paired(hipStream_t s, const Geo& g, int dir, cpx<T>* sm, cpx<T>* sp, cpx<T>* sn,
                                           const cpx<T>* tw, const LoadState* st, int nload, int variant = 0);
+// both y passes in place on the paired layout (the fused CG step's); -1 where none exists
+template <typename T> int launch_y_paired_inplace(hipStream_t s, const Geo& g, int dir, cpx<T>* sm, cpx<T>* sn,
+                                                  const cpx<T>* tw, const LoadState* st, int nload, int variant = 0);
 // the Green pass on the paired layout (stored operator); -1 where none exists
 template <typename T> int launch_zg_paired(hipStream_t s, const Geo& g, const GreenParams& gp, const GreenTabs<T>& tb,
                                            cpx<T>* sp, cpx<T>* sn, const cpx<T>* tw, const LoadState* st, int nload,

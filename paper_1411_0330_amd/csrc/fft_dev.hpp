@@ -37,6 +37,18 @@ __device__ __forceinline__ void st_stream(V* p, const V& v) {
   __builtin_nontemporal_store(w, reinterpret_cast<N*>(p));
 }
 
+// 16-byte (four-float) forms, for component pairs of the paired spectrum layout
+__device__ __forceinline__ float4 ld_stream4(const float4* p) {
+  typedef float N __attribute__((ext_vector_type(4)));
+  const N v = __builtin_nontemporal_load(reinterpret_cast<const N*>(p));
+  return float4{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ void st_stream4(float4* p, const float4& v) {
+  typedef float N __attribute__((ext_vector_type(4)));
+  const N w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<N*>(p));
+}
+
 // Streaming access only where one access instruction covers whole 128-byte
 // lines (W contiguous bytes per row segment).  Narrower segments read each
 // line in two halves by consecutive instructions, and a streaming hint lets

@@ -7,9 +7,11 @@ template <typename T, int NY, int DIR, int TX, int P, int LAY = YL_INPLACE>
 static int y_inst(hipStream_t s, const Geo& g, cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw, const LoadState* st,
                   int nload, cpx<T>* sout = nullptr) {
   constexpr int NT = TX * (NY / P);
-  constexpr int H = LAY == YL_INPLACE ? TX : TX / 2;
-  const int xtiles = (g.mx + H - 1) / H;
-  // paired layouts: tiles over component pairs (two components per tile)
+  constexpr bool INPL = LAY == YL_INPLACE || LAY == YL_PAIRED;
+  constexpr int H = INPL ? TX : TX / 2;
+  const int mrow = LAY == YL_PAIRED ? 2 * g.mx : g.mx;
+  const int xtiles = (mrow + H - 1) / H;
+  // paired layouts: tiles over component pairs
   const int main_tiles = (LAY == YL_INPLACE ? g.c : g.c / 2) * g.nz * xtiles;
   const int nyq_tiles = (g.c * g.nz + TX - 1) / TX;
   hipLaunchKernelGGL((k_y<T, NY, P, TX, DIR, LAY>), dim3(main_tiles + nyq_tiles, nload), dim3(NT), 0, s, g, sm, sn,
@@ -17,30 +19,30 @@ static int y_inst(hipStream_t s, const Geo& g, cpx<T>* sm, cpx<T>* sn, const cpx
   return main_tiles + nyq_tiles;
 }
 
-template <typename T, int NY, int DIR, int V>
+template <typename T, int NY, int DIR, int V, int LAY = YL_INPLACE>
 static int y_var(hipStream_t s, const Geo& g, cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw, const LoadState* st,
                  int nload) {
   constexpr int P0 = p_y<T>(NY);
   constexpr int TX0 = tx_strided<T>(NY, P0);
   constexpr int TXV = sv_tx<T>(NY, P0, V), PV = sv_p(P0, V);
   if constexpr (V != 0 && sv_ok<T>(NY, TXV, PV))
-    return y_inst<T, NY, DIR, TXV, PV>(s, g, sm, sn, tw, st, nload);
+    return y_inst<T, NY, DIR, TXV, PV, LAY>(s, g, sm, sn, tw, st, nload);
   else
-    return y_inst<T, NY, DIR, TX0, P0>(s, g, sm, sn, tw, st, nload);
+    return y_inst<T, NY, DIR, TX0, P0, LAY>(s, g, sm, sn, tw, st, nload);
 }
 
-template <typename T, int NY, int DIR>
+template <typename T, int NY, int DIR, int LAY = YL_INPLACE>
 static int y_one(hipStream_t s, const Geo& g, cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw, const LoadState* st,
                  int nload, int v = 0) {
   if constexpr (NY == 128 || NY == 256) {
     switch (v) {
-      case 1: return y_var<T, NY, DIR, 1>(s, g, sm, sn, tw, st, nload);
-      case 2: return y_var<T, NY, DIR, 2>(s, g, sm, sn, tw, st, nload);
-      case 3: return y_var<T, NY, DIR, 3>(s, g, sm, sn, tw, st, nload);
+      case 1: return y_var<T, NY, DIR, 1, LAY>(s, g, sm, sn, tw, st, nload);
+      case 2: return y_var<T, NY, DIR, 2, LAY>(s, g, sm, sn, tw, st, nload);
+      case 3: return y_var<T, NY, DIR, 3, LAY>(s, g, sm, sn, tw, st, nload);
       default: break;
     }
   }
-  return y_var<T, NY, DIR, 0>(s, g, sm, sn, tw, st, nload);
+  return y_var<T, NY, DIR, 0, LAY>(s, g, sm, sn, tw, st, nload);
 }
 
 template <typename T, int DIR>
@@ -103,6 +105,24 @@ int launch_y_paired(hipStream_t s, const Geo& g, int dir, cpx<T>* sm, cpx<T>* sp
   return -1;
 }
 
+// Both y passes in place on the component-paired layout (written by the
+// fused CG x pass, read by its x inverse pass): six-component FP32 fields,
+// 128 or 256 points along y, every shape variant; -1 elsewhere.
+template <typename T>
+int launch_y_paired_inplace(hipStream_t s, const Geo& g, int dir, cpx<T>* sm, cpx<T>* sn, const cpx<T>* tw,
+                            const LoadState* st, int nload, int v) {
+  if constexpr (sizeof(T) == 4) {
+    if (g.c != 6 || g.nz < 2) return -1;
+    if (g.ny == 128)
+      return dir < 0 ? y_one<T, 128, -1, YL_PAIRED>(s, g, sm, sn, tw, st, nload, v)
+                     : y_one<T, 128, 1, YL_PAIRED>(s, g, sm, sn, tw, st, nload, v);
+    if (g.ny == 256)
+      return dir < 0 ? y_one<T, 256, -1, YL_PAIRED>(s, g, sm, sn, tw, st, nload, v)
+                     : y_one<T, 256, 1, YL_PAIRED>(s, g, sm, sn, tw, st, nload, v);
+  }
+  return -1;
+}
+
 #ifndef LSH_Y_TYPE
 #error "define LSH_Y_TYPE"
 #endif
@@ -110,5 +130,7 @@ template int launch_y<LSH_Y_TYPE>(hipStream_t, const Geo&, int, cpx<LSH_Y_TYPE>*
                                   const cpx<LSH_Y_TYPE>*, const LoadState*, int, int);
 template int launch_y_paired<LSH_Y_TYPE>(hipStream_t, const Geo&, int, cpx<LSH_Y_TYPE>*, cpx<LSH_Y_TYPE>*,
                                          cpx<LSH_Y_TYPE>*, const cpx<LSH_Y_TYPE>*, const LoadState*, int, int);
+template int launch_y_paired_inplace<LSH_Y_TYPE>(hipStream_t, const Geo&, int, cpx<LSH_Y_TYPE>*, cpx<LSH_Y_TYPE>*,
+                                                 const cpx<LSH_Y_TYPE>*, const LoadState*, int, int);
 
 }  // namespace lsh

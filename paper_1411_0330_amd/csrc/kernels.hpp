@@ -368,6 +368,7 @@ struct XfwdcArgs {
   const T* vcoef;
   double* partials;
   int pstride;
+  int paired;     // write the main spectrum in the component-paired layout (FP32, even c)
 };
 
 template <typename T, int MX, int P, int C>
@@ -478,26 +479,48 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(xfwdc_waves
 #pragma unroll
       for (int i = 0; i < P; ++i) lrow[jj * RPW * MX + t + TR * i] = v[j0 + jj][i];
     __syncthreads();
+    // X[k] = (Z[k] + conj Z[M-k]) / 2 - i W^k (Z[k] - conj Z[M-k]) / 2 for k > 0;
+    // X[0] = Re Z[0] + Im Z[0] and the Nyquist value Re Z[0] - Im Z[0]
+    auto unpack = [&](const int jj, const int i) -> cpx<T> {
+      const int k = t + TR * i;
+      const cpx<T> z = v[j0 + jj][i];
+      if (k == 0) return cpx<T>{z.x + z.y, T(0)};
+      const cpx<T> zm = lrow[jj * RPW * MX + MX - k];
+      const cpx<T> s1 = cpx<T>{z.x + zm.x, z.y - zm.y};   // Z + conj(Zm)
+      const cpx<T> d1 = cpx<T>{z.x - zm.x, z.y + zm.y};   // Z - conj(Zm)
+      const cpx<T> wo = cmul(twl[k], mul_neg_i(d1));
+      return cpx<T>{T(0.5) * (s1.x + wo.x), T(0.5) * (s1.y + wo.y)};
+    };
 #pragma unroll
     for (int jj = 0; jj < CG; ++jj) {
-      const int j = j0 + jj;
-      const long long row = (long long)j * vrows + vrc;
-      const long long so = (long long)l * main_cpx(g) + row * MX;
+      const long long row = (long long)(j0 + jj) * vrows + vrc;
+      if (t == 0 && valid) {
+        const cpx<T> z = v[j0 + jj][0];
+        a.snyq[(long long)l * nyq_cpx(g) + row] = cpx<T>{z.x - z.y, T(0)};
+      }
+    }
+    bool done = false;
+    if constexpr (CG == 2 && sizeof(T) == 4) {
+      if (a.paired) {
+        // components j0 and j0 + 1 of each wave-vector side by side (16 bytes)
+        float4* pr = reinterpret_cast<float4*>(a.smain + (long long)l * main_cpx(g) +
+                                               ((long long)(j0 / 2) * vrows + vrc) * 2 * MX);
 #pragma unroll
-      for (int i = 0; i < P; ++i) {
-        const int k = t + TR * i;
-        const cpx<T> z = v[j][i];
-        if (k == 0) {
-          if (valid) {
-            st_seg<SEG>(a.smain + so, cpx<T>{z.x + z.y, T(0)});
-            a.snyq[(long long)l * nyq_cpx(g) + row] = cpx<T>{z.x - z.y, T(0)};
-          }
-        } else {
-          const cpx<T> zm = lrow[jj * RPW * MX + MX - k];
-          const cpx<T> s1 = cpx<T>{z.x + zm.x, z.y - zm.y};   // Z + conj(Zm)
-          const cpx<T> d1 = cpx<T>{z.x - zm.x, z.y + zm.y};   // Z - conj(Zm)
-          const cpx<T> wo = cmul(twl[k], mul_neg_i(d1));
-          if (valid) st_seg<SEG>(a.smain + so + k, cpx<T>{T(0.5) * (s1.x + wo.x), T(0.5) * (s1.y + wo.y)});
+        for (int i = 0; i < P; ++i) {
+          const cpx<T> e0 = unpack(0, i), e1 = unpack(1, i);
+          if (valid) st_stream4(pr + t + TR * i, float4{e0.x, e0.y, e1.x, e1.y});
+        }
+        done = true;
+      }
+    }
+    if (!done) {
+#pragma unroll
+      for (int jj = 0; jj < CG; ++jj) {
+        const long long so = (long long)l * main_cpx(g) + ((long long)(j0 + jj) * vrows + vrc) * MX;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          const cpx<T> e = unpack(jj, i);
+          if (valid) st_seg<SEG>(a.smain + so + t + TR * i, e);
         }
       }
     }
@@ -516,9 +539,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(xfwdc_waves
 // 8-pencil tiles) components 2m and 2m+1 of a wave-vector are adjacent:
 //   ((m nz + kz) ny + ky) 2 mx + 2 kx + (j & 1),   j = 2m or 2m + 1,
 // so an 8-pencil z tile reads whole 128-byte lines for every component pair.
-// A paired-layout tile holds TX/2 wave-vectors of two components (columns
-// xl < TX/2 the even one); the Nyquist rows stay in place in every layout.
-enum : int { YL_INPLACE = 0, YL_TO_PAIRED = 1, YL_FROM_PAIRED = 2 };
+// A converting tile holds TX/2 wave-vectors of two components (columns
+// xl < TX/2 the even one).  3 runs in place on the paired layout: each
+// component pair is a row of 2 mx entries, cut into tiles of TX.  The Nyquist
+// rows stay in place in every layout.
+enum : int { YL_INPLACE = 0, YL_TO_PAIRED = 1, YL_FROM_PAIRED = 2, YL_PAIRED = 3 };
 
 template <typename T, int NY, int P, int TX, int DIR, int LAY>
 __global__ __launch_bounds__(TX*(NY / P)) void k_y(const Geo g, cpx<T>* __restrict__ smain,
@@ -526,7 +551,8 @@ __global__ __launch_bounds__(TX*(NY / P)) void k_y(const Geo g, cpx<T>* __restri
                                                   const LoadState* __restrict__ st, const int main_tiles,
                                                   cpx<T>* __restrict__ sout) {
   constexpr int TY = NY / P;
-  constexpr int H = LAY == YL_INPLACE ? TX : TX / 2;   // wave-vectors per component in a main tile
+  constexpr bool INPL = LAY == YL_INPLACE || LAY == YL_PAIRED;
+  constexpr int H = INPL ? TX : TX / 2;   // row entries (wave-vectors, or pair entries) per component in a main tile
   constexpr int SEG = H * (int)sizeof(cpx<T>);       // contiguous bytes per plain-layout access
   constexpr int SEGP = TX * (int)sizeof(cpx<T>);     // contiguous bytes per paired-layout access
   __shared__ cpx<T> lds[TX * NY];
@@ -542,20 +568,21 @@ __global__ __launch_bounds__(TX*(NY / P)) void k_y(const Geo g, cpx<T>* __restri
   bool valid, main = false;
   if ((int)blockIdx.x < main_tiles) {
     main = true;
-    const int xtiles = (g.mx + H - 1) / H;
-    const int tile = LAY == YL_INPLACE ? xcd_tile<line_share<T, TX>()>(blockIdx.x, main_tiles) : (int)blockIdx.x;
+    const int mrow = LAY == YL_PAIRED ? 2 * g.mx : g.mx;   // entries per row
+    const int xtiles = (mrow + H - 1) / H;
+    const int tile = INPL ? xcd_tile<line_share<T, TX>()>(blockIdx.x, main_tiles) : (int)blockIdx.x;
     const int xc = tile % xtiles;
     const long long jz = tile / xtiles;
     const int xl = tid % TX;
     t = tid / TX;
     const int kx = xc * H + xl % H;
-    valid = kx < g.mx;
+    valid = kx < mrow;
     const int kxc = valid ? kx : 0;
     const long long lo = (long long)l * main_cpx(g);
-    if constexpr (LAY == YL_INPLACE) {
-      base = smain + lo + jz * g.ny * g.mx + kxc;
+    if constexpr (INPL) {
+      base = smain + lo + jz * g.ny * mrow + kxc;
       obase = base;
-      es_g = es_o = g.mx;
+      es_g = es_o = mrow;
     } else {
       // jz = m nz + kz over component pairs; this column's component j = 2m + xl / H
       const long long m = jz / g.nz, kz = jz % g.nz;
@@ -975,6 +1002,7 @@ struct XinvArgs {
   int pstride;
   T scale;                // 1/N^d times the factor of the half-length route
   T em2[9];               // 2 A0: c x c (scalar), or (4 mu0, 2 lambda0) of the isotropic elastic A0
+  int paired;             // main spectrum in the component-paired layout (FP32, even c)
 };
 
 template <typename T, int MX, int P, int C>
@@ -1007,14 +1035,34 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
   // all components' spectrum rows are loaded before the first transform
   cpx<T> gam[C][P];
   cpx<T> nqs[C];
+  bool loaded = false;
+  if constexpr (C % 2 == 0 && sizeof(T) == 4) {
+    if (a.paired) {
+      // component pairs side by side: one 16-byte read per pair and point
 #pragma unroll
-  for (int j = 0; j < C; ++j) {
-    const long long srow = (long long)j * vrows + vrc;
-    const cpx<T>* sm = a.smain + (long long)l * main_cpx(g) + srow * MX;
+      for (int j = 0; j < C; j += 2) {
+        const float4* pr = reinterpret_cast<const float4*>(a.smain + (long long)l * main_cpx(g) +
+                                                           ((long long)(j / 2) * vrows + vrc) * 2 * MX);
 #pragma unroll
-    for (int i = 0; i < P; ++i) gam[j][i] = ld_seg<SEG>(sm + t + TR * i);
-    nqs[j] = a.snyq[(long long)l * nyq_cpx(g) + srow];
+        for (int i = 0; i < P; ++i) {
+          const float4 q = ld_stream4(pr + t + TR * i);
+          gam[j][i] = cpx<T>{q.x, q.y};
+          gam[j + 1][i] = cpx<T>{q.z, q.w};
+        }
+      }
+      loaded = true;
+    }
   }
+  if (!loaded) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const cpx<T>* sm = a.smain + (long long)l * main_cpx(g) + ((long long)j * vrows + vrc) * MX;
+#pragma unroll
+      for (int i = 0; i < P; ++i) gam[j][i] = ld_seg<SEG>(sm + t + TR * i);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < C; ++j) nqs[j] = a.snyq[(long long)l * nyq_cpx(g) + (long long)j * vrows + vrc];
   // repack each component's half spectrum as the half-length complex
   // transform 2Z = 2E + i 2O (CG components per exchange, in the exchange
   // buffers of the transforms), then the inverse transforms of all components

@@ -820,24 +820,31 @@ void tune_from_env(lsh_ctx* ctx) {
   }
 }
 
-// The component-paired spectrum of the Green pass's 8-pencil shape (z
-// variant kZPaired): FP32 six-component fields of a mixed context with the
-// stored operator and 128- or 256-point y and z axes.  The y forward pass
-// writes it and the y inverse pass reads it back, out of place; it lives in
-// the FP64 spectrum buffer (4F of its 8F bytes per load), which holds nothing
-// between FP64 applications.  Null where the shape does not apply: the passes
-// then run in place on the plain layout.
+// The component-paired spectrum layout of the Green pass's 8-pencil shape
+// (z variant kZPaired): FP32 six-component fields of a mixed context with the
+// stored operator and 128- or 256-point y and z axes.
 template <typename T>
-cpx<T>* paired_spectrum(lsh_ctx* ctx, int l0) {
+bool paired_shape(lsh_ctx* ctx) {
   if constexpr (sizeof(T) == 4) {
     const Geo& g = ctx->geo;
     auto ax = [](int n) { return n == 128 || n == 256; };
-    if (ctx->precision != LSH_MIXED || ctx->ovr_sm || ctx->tune[0][PASS_ZG] != kZPaired || g.c != 6 ||
-        !ax(g.ny) || !ax(g.nz) || Sel<float>::gst(ctx) == nullptr)
-      return nullptr;
-    return ctx->ptr<cpx<float>>(ctx->off.s64m) + (long long)l0 * main_cpx(g);
+    return ctx->precision == LSH_MIXED && !ctx->ovr_sm && ctx->tune[0][PASS_ZG] == kZPaired && g.c == 6 &&
+           ax(g.ny) && ax(g.nz) && Sel<float>::gst(ctx) != nullptr;
   }
-  return nullptr;
+  return false;
+}
+
+// Where the x passes use the plain layout (the operator passes of
+// forward_part), the y forward pass writes the paired spectrum out of place
+// and the y inverse pass reads it back: it lives in the FP64 spectrum buffer
+// (4F of its 8F bytes per load), which holds nothing between FP64
+// applications.  Null where the shape does not apply: the passes then run in
+// place on the plain layout.  (The fused CG step writes and reads the paired
+// layout in its x passes and runs every pass in place.)
+template <typename T>
+cpx<T>* paired_spectrum(lsh_ctx* ctx, int l0) {
+  if (!paired_shape<T>(ctx)) return nullptr;
+  return reinterpret_cast<cpx<T>*>(ctx->ptr<char>(ctx->off.s64m)) + (long long)l0 * main_cpx(ctx->geo);
 }
 
 // Forward passes on load slots [l0, l0+nload): x (mode), y, z (+Gamma and inverse z), y inverse.
@@ -889,7 +896,8 @@ lsh_status forward_part(lsh_ctx* ctx, int l0, int nload, int xmode, const T* src
 
 template <typename T>
 lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T* out, float* rout,
-                     const LoadState* st, double* partials, int* nparts, const T* rin = nullptr) {
+                     const LoadState* st, double* partials, int* nparts, const T* rin = nullptr,
+                     bool paired = false) {
   const Geo& g = ctx->geo;
   XinvArgs<T> a{};
   a.g = g;
@@ -910,6 +918,7 @@ lsh_status inverse_x(lsh_ctx* ctx, int l0, int nload, int mode, const T* tau, T*
   a.st = st;
   a.partials = partials;
   a.pstride = (int)ctx->pstride;
+  a.paired = paired ? 1 : 0;
   a.scale = static_cast<T>(1.0 / (double)g.nvox);
   for (int i = 0; i < 9; ++i) a.em2[i] = T(0);
   if (ctx->physics == LSH_ELASTIC) {
@@ -959,8 +968,10 @@ lsh_status cg_fused_step(lsh_ctx* ctx, int l0, int nload, T* x, T* r, const T* p
   const double cvs = (double)ctx->F * sizeof(T);
   const double spec = cvs + 2.0 * sizeof(T) * (double)nyq_cpx(g);
   const double mat = (ctx->mat_voxel ? 2.0 * sizeof(T) : 1.0) * g.nvox;
+  // the paired z shape: every pass of the step in place on the paired layout
+  const bool pr = paired_shape<T>(ctx);
   XfwdcArgs<T> xa{g, r, pin, pout, x, sm, sn, Sel<T>::tw(ctx, 0), st, ctx->nphase, ctx->iso, Sel<T>::ptab(ctx),
-                  ctx->ptr<uint8_t>(ctx->off.phase), Sel<T>::vc(ctx), parts, (int)ctx->pstride};
+                  ctx->ptr<uint8_t>(ctx->off.phase), Sel<T>::vc(ctx), parts, (int)ctx->pstride, pr ? 1 : 0};
   int nbx = 0, nbz = 0, nbi = 0;
   {
     // fields: first step r in, p out; then r and p_{k-1} in, p_k out, and every
@@ -970,11 +981,10 @@ lsh_status cg_fused_step(lsh_ctx* ctx, int l0, int nload, T* x, T* r, const T* p
     nbx = launch_xfwdc<T>(ctx->stream, xa, nload);
     STCHK(check_launch(ctx, nbx, "x forward (CG)"));
   }
-  cpx<T>* sp = paired_spectrum<T>(ctx, l0);
   {
     Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
-    const int nb = sp ? launch_y_paired<T>(ctx->stream, g, -1, sm, sp, sn, Sel<T>::tw(ctx, 1), st, nload,
-                                           tv<T>(ctx, PASS_Y))
+    const int nb = pr ? launch_y_paired_inplace<T>(ctx->stream, g, -1, sm, sn, Sel<T>::tw(ctx, 1), st, nload,
+                                                   tv<T>(ctx, PASS_Y))
                       : launch_y<T>(ctx->stream, g, -1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y));
     STCHK(check_launch(ctx, nb, "y forward"));
   }
@@ -982,7 +992,7 @@ lsh_status cg_fused_step(lsh_ctx* ctx, int l0, int nload, T* x, T* r, const T* p
     Scope sc(ctx, kcls<T>(K_ZG), nl * 2.0 * spec);
     GreenTabs<T> tb{Sel<T>::wt(ctx), ctx->wstride, {Sel<T>::tw(ctx, 0), Sel<T>::tw(ctx, 1), Sel<T>::tw(ctx, 2)},
                     Sel<T>::gtab(ctx), Sel<T>::gst(ctx)};
-    nbz = sp ? launch_zg_paired<T>(ctx->stream, g, ctx->gp, tb, sp, sn, Sel<T>::tw(ctx, 2), st, nload, parts + nbx,
+    nbz = pr ? launch_zg_paired<T>(ctx->stream, g, ctx->gp, tb, sm, sn, Sel<T>::tw(ctx, 2), st, nload, parts + nbx,
                                    (int)ctx->pstride)
              : launch_zg<T>(ctx->stream, g, ctx->gp, tb, Z_GAMMA, sm, sn, Sel<T>::tw(ctx, 2), st, nload,
                             tv<T>(ctx, PASS_ZG), parts + nbx, (int)ctx->pstride);
@@ -991,12 +1001,12 @@ lsh_status cg_fused_step(lsh_ctx* ctx, int l0, int nload, T* x, T* r, const T* p
   if (scalars) STCHK(scal(ctx, SC_ALPHA, nload, nbx + nbz, st, ctx->bd_guard[sizeof(T) == 8 ? 1 : 0], l0, par));
   {
     Scope sc(ctx, kcls<T>(K_Y), nl * 2.0 * spec);
-    const int nb = sp ? launch_y_paired<T>(ctx->stream, g, 1, sm, sp, sn, Sel<T>::tw(ctx, 1), st, nload,
-                                           tv<T>(ctx, PASS_Y))
+    const int nb = pr ? launch_y_paired_inplace<T>(ctx->stream, g, 1, sm, sn, Sel<T>::tw(ctx, 1), st, nload,
+                                                   tv<T>(ctx, PASS_Y))
                       : launch_y<T>(ctx->stream, g, 1, sm, sn, Sel<T>::tw(ctx, 1), st, nload, tv<T>(ctx, PASS_Y));
     STCHK(check_launch(ctx, nb, "y inverse"));
   }
-  STCHK(inverse_x<T>(ctx, l0, nload, XI_CGR, pout, r, nullptr, st, parts, &nbi, r));
+  STCHK(inverse_x<T>(ctx, l0, nload, XI_CGR, pout, r, nullptr, st, parts, &nbi, r, pr));
   return scalars ? scal(ctx, SC_BETA, nload, nbi, st, 0.0, l0) : LSH_OK;
 }
 
