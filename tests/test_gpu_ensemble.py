@@ -6,8 +6,9 @@
   bitwise (A*, iteration counts).
 * The full ensemble (48 cubes of 64/96/128/160, Gaussian fields of
   correlation length 4, a = exp(g), mixed to 1e-6, 3 loads each): every member
-  converges and its A* lies between the harmonic and arithmetic means of its
-  conductivity (the Wiener bounds of the discrete problem with A0 <= A).
+  converges, its A* lies between the harmonic and arithmetic means of its
+  conductivity (the Wiener bounds of the discrete problem with A0 <= A), and
+  A* and the iteration counts equal those of each member solved alone.
 * The autotuner: chosen shapes are valid, the cache file is written and hit,
   a foreign cache line is ignored, and results with the tuned shapes equal
   the default shapes' within FP64 rounding.
@@ -77,9 +78,13 @@ def test_concurrent_equals_sequential(lsh):
 
 
 def test_full_ensemble_converges_within_wiener_bounds(lsh):
+    # the full 48-member ensemble with four members in flight: every member
+    # converges within the Wiener bounds, and gives bitwise the A* and the
+    # iteration counts of the same member solved alone afterwards
     members = I.ensemble_workload()
     ctxs = [_member_ctx(lsh, m, "mixed") for m in members]
     reps = lsh.solve_many(ctxs, [np.eye(3)] * len(ctxs), "cg", tol=1e-6, maxit=3000, threads=4)
+    got = []
     for m, ctx, rep in zip(members, ctxs, reps):
         assert rep["status"] == lsh.OK and max(rep["rel_residual"]) <= 1e-6
         A = ctx.effective()
@@ -88,7 +93,11 @@ def test_full_ensemble_converges_within_wiener_bounds(lsh):
         d = np.diag(A)
         assert np.all(d >= harm * (1 - 1e-5)) and np.all(d <= arit * (1 + 1e-5)), (m.n, d, harm, arit)
         assert np.abs(A - A.T).max() <= 1e-4 * np.abs(A).max()
-        del ctx
+        got.append((A.copy(), rep["iterations"]))
+    for m, ctx, (A, its) in zip(members, ctxs, got):
+        rep = ctx.solve(np.eye(3), "cg", tol=1e-6, maxit=3000)
+        assert np.array_equal(ctx.effective(), A), m.n
+        assert rep["iterations"] == its, m.n
 
 
 def test_autotune_cache_and_results(lsh, tmp_path):
