@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the FP64 1e-10 reference and the time-to-accuracy sweep")
     ap.add_argument("--no-small", action="store_true", help="skip the 64^2 launch-bound leg")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 48-member ensemble leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel shapes")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: the package's tune_cache.txt, written by the autotuner on MI355X)")
@@ -229,10 +230,11 @@ def cpu_baseline(n=128, reps=5):
     }
 
 
-def bench_ensemble(args):
+def run_ensemble():
     """48 lognormal members (64/96/128/160), mixed CG to 1e-6, three loads each:
     all members solved one after another (one member in flight), then with
-    four members in flight (the fiber scheduler of lsh_solve_many)."""
+    four members in flight (the fiber scheduler of lsh_solve_many).  Returns
+    the result record."""
     import numpy as np
     import torch
 
@@ -269,7 +271,8 @@ def bench_ensemble(args):
     alg = sum((184 * r["applications_fp32"] + 264 * r["applications_fp64"]) * m.n ** 3
               for r, m in zip(res_reps[4], members))
     gbs = alg / dt / 1e9
-    print(json.dumps({
+    del ctxs
+    return {
         "metric": "ensemble voxel-iterations/s (48 lognormal members, mixed CG 1e-6)",
         "value": apps / dt, "unit": "voxel-iterations/s", "n_gpus": 1, "higher_is_better": True,
         "seconds": dt, "sequential_seconds": res[1][0], "concurrency_speedup": res[1][0] / dt,
@@ -280,7 +283,12 @@ def bench_ensemble(args):
         "worst_rel_residual": worst, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "48 cubes, sizes uniform over 64/96/128/160 (seed 0), a = exp(g), g a periodic "
                                "Gaussian field of correlation length 4, a0 = min(a)/2, filtered, 3 unit loads",
-                   "voxels": int(sum(m.n ** 3 for m in members)), "members_in_flight": 4}}), flush=True)
+                   "voxels": int(sum(m.n ** 3 for m in members)), "members_in_flight": 4}}
+
+
+def bench_ensemble(args):
+    """The ensemble alone (one JSON line)."""
+    print(json.dumps(run_ensemble()), flush=True)
 
 
 def bench_boolean(args):
@@ -569,6 +577,14 @@ def main():
     if small:
         out["disk64_fp64_cg"] = small
         log(f"disk 64^2: {small}")
+
+    # ---------------- the ensemble workload (uneven grids, streams) ----------------
+    if not args.no_ensemble:
+        e = run_ensemble()
+        out["ensemble"] = {"value": e["value"], "unit": e["unit"], "seconds": round(e["seconds"], 4),
+                           "sequential_seconds": round(e["sequential_seconds"], 4),
+                           "roofline": e["roofline"], "worst_rel_residual": e["worst_rel_residual"],
+                           "workload": e["config"]["workload"]}
 
     # ---------------- CPU oracle on a bounded sample ----------------
     if not args.no_cpu:
