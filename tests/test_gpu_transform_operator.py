@@ -299,10 +299,16 @@ def test_paired_z_pass_matches_oracle(lsh, monkeypatch, shape, nload, ytune):
     assert rel_max_err(out, ref) <= 1e-5
 
 
-def test_paired_z_pass_in_a_batched_solve(lsh, monkeypatch):
-    # the fused CG step on the paired layout, loads converging at different
-    # steps (frozen loads skipped), against the plain layout's solve
-    ph = I.random_phases((128, 128, 16), 2, seed=5)
+@pytest.mark.parametrize("shape,fused", [((128, 128, 16), "1"), ((128, 256, 48), "1"), ((256, 128, 8), "1"),
+                                         ((128, 128, 16), "0")])
+def test_paired_z_pass_in_a_batched_solve(lsh, monkeypatch, shape, fused):
+    # CG on the paired layout, loads converging at different steps (frozen
+    # loads skipped), against the plain layout's solve: the fused step with
+    # every pass in place on the paired layout (ragged x tiles: mx = 24 of 32
+    # pair entries per y tile row segment, mx = 4 of 8 z pencils), and the
+    # unfused step, whose y passes convert the layout
+    monkeypatch.setenv("LSH_CG_FUSED", fused)
+    ph = I.random_phases(shape, 2, seed=5)
     moduli, A0 = np.stack([ELAS[0], ELAS[1]]), C0
     loads = np.eye(6)[[0, 3, 5]] * np.array([[1.0], [1e-3], [5.0]])
     res = {}
