@@ -1011,8 +1011,8 @@ __global__ __launch_bounds__(256) void k_xinv(const XinvArgs<T> a) {
   constexpr int RPW = 256 / TR;
   constexpr int SEG = TR * (int)sizeof(cpx<T>);   // contiguous bytes per access instruction
   constexpr int TABW = 2 * C * C + 5;
-  // FP32 six components: three components share each FFT exchange
-  constexpr int CG = (sizeof(T) == 4 && C == 6) ? 3 : 1;
+  // six components: three components share each FFT exchange
+  constexpr int CG = C == 6 ? 3 : 1;
   __shared__ cpx<T> lds[CG * RPW * MX];
   __shared__ cpx<T> twl[2 * MX];
   __shared__ T tab[kMaxPhases * TABW];
