@@ -70,6 +70,7 @@ struct XfwdArgs {
   cpx<T>* snyq;
   const cpx<T>* twx;
   const LoadState* st;
+  IrxFold fold;   // XF_IRX: the inner solve's pending steps, x starting at zero
 };
 
 // Kernel-shape variants of each pass (0 = the default shape).  For the axis

@@ -19,7 +19,7 @@ static int xfwd_inst(hipStream_t s, const XfwdArgs<T>& a, int nload) {
   const long long rows = (long long)a.g.c * a.g.nz * a.g.ny;
   const int nb = (int)((rows + RPW - 1) / RPW);
   hipLaunchKernelGGL((k_xfwd<T, MX, P>), dim3(nb, nload), dim3(256), 0, s, a.g, a.mode, a.src, a.pdir, a.xacc,
-                     a.dsrc, a.smain, a.snyq, a.twx, a.st);
+                     a.dsrc, a.smain, a.snyq, a.twx, a.st, a.fold);
   return nb;
 }
 

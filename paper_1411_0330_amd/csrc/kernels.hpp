@@ -63,6 +63,19 @@ __device__ __forceinline__ void hist_push(const HistRef& h, const int load, cons
   e[1] = (double)h.level;
 }
 
+// The FP64 refinement x pass of a mixed solve (XF_IRX, x += d) also applies
+// the x updates that the FP32 inner CG left pending (one or two steps, from
+// the direction buffers its load states name: pa, or pa and pb for the fused
+// step's alternating buffers), so that no separate flush pass reads and
+// writes d; with xzero it writes x = d (the first refinement of a solve that
+// starts at zero, which then needs no zeroing pass).
+struct IrxFold {
+  const float* pa;
+  const float* pb;
+  const LoadState* sti;   // inner states (null: nothing pending)
+  int xzero;
+};
+
 struct Geo {
   int nx, ny, nz, mx, c, pad;
   long long nvox;  // nx*ny*nz
@@ -150,21 +163,29 @@ __global__ __launch_bounds__(256) void k_xfwd(const Geo g, const int mode, const
                                               T* __restrict__ pdir, T* __restrict__ xacc,
                                               const float* __restrict__ dsrc, cpx<T>* __restrict__ smain,
                                               cpx<T>* __restrict__ snyq, const cpx<T>* __restrict__ twx,
-                                              const LoadState* __restrict__ st) {
+                                              const LoadState* __restrict__ st, const IrxFold fold) {
   constexpr int TR = MX / P;
   constexpr int RPW = 256 / TR;
   constexpr int SEG = TR * (int)sizeof(cpx<T>);   // contiguous bytes per access instruction
   __shared__ cpx<T> lds[RPW * MX];
   __shared__ cpx<T> twl[2 * MX];
   const int l = blockIdx.y;
-  if (st != nullptr && !st[l].active) return;
   const int tid = threadIdx.x;
-  for (int i = tid; i < 2 * MX; i += 256) twl[i] = twx[i];   // twiddles of the row length, staged in LDS
   const int slot = tid / TR, t = tid % TR;
   const long long rows = (long long)g.c * g.nz * g.ny;
   const long long row = (long long)blockIdx.x * RPW + slot;
   const bool valid = row < rows;
   const long long roff = (long long)l * field_elems(g) + row * (2 * MX);
+  if (st != nullptr && !st[l].active) {
+    // a load that is not refined still gets its zero start written (x was not zeroed)
+    if (mode == XF_IRX && fold.xzero && valid) {
+      cpx<T>* x2 = reinterpret_cast<cpx<T>*>(pdir + roff);
+#pragma unroll
+      for (int i = 0; i < P; ++i) x2[t + TR * i] = cpx<T>{0, 0};
+    }
+    return;
+  }
+  for (int i = tid; i < 2 * MX; i += 256) twl[i] = twx[i];   // twiddles of the row length, staged in LDS
 
   cpx<T> v[P];
   if (mode == XF_CG) {
@@ -199,13 +220,28 @@ __global__ __launch_bounds__(256) void k_xfwd(const Geo g, const int mode, const
   } else if (mode == XF_IRX) {
     cpx<T>* x2 = reinterpret_cast<cpx<T>*>(pdir + roff);
     const float2* d2 = reinterpret_cast<const float2*>(dsrc + roff);
+    // pending inner steps of this load: d + alpha p_newest (+ alpha2 p_older), in FP32
+    const int np = fold.sti != nullptr ? fold.sti[l].pending : 0;
+    const float al = np > 0 ? static_cast<float>(fold.sti[l].alpha) : 0.0f;
+    const float al2 = np == 2 ? static_cast<float>(fold.sti[l].alpha2) : 0.0f;
+    const bool nb1 = np > 0 && fold.pb != nullptr && fold.sti[l].pbuf != 0;
+    const float2* pn2 = np > 0 ? reinterpret_cast<const float2*>((nb1 ? fold.pb : fold.pa) + roff) : nullptr;
+    const float2* po2 = np == 2 ? reinterpret_cast<const float2*>((nb1 ? fold.pa : fold.pb) + roff) : nullptr;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const int n = t + TR * i;
       cpx<T> xv{0, 0};
       if (valid) {
-        const cpx<T> xo = x2[n];
-        const float2 dv = d2[n];
+        const cpx<T> xo = fold.xzero ? cpx<T>{0, 0} : x2[n];
+        float2 dv = d2[n];
+        if (np > 0) {
+          const float2 q = pn2[n];
+          dv = float2{dv.x + al * q.x, dv.y + al * q.y};
+          if (np == 2) {
+            const float2 q2 = po2[n];
+            dv = float2{dv.x + al2 * q2.x, dv.y + al2 * q2.y};
+          }
+        }
         xv = cpx<T>{xo.x + static_cast<T>(dv.x), xo.y + static_cast<T>(dv.y)};
         x2[n] = xv;
       }

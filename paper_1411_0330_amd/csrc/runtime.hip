@@ -850,11 +850,11 @@ cpx<T>* paired_spectrum(lsh_ctx* ctx, int l0) {
 // Forward passes on load slots [l0, l0+nload): x (mode), y, z (+Gamma and inverse z), y inverse.
 template <typename T>
 lsh_status forward_part(lsh_ctx* ctx, int l0, int nload, int xmode, const T* src, T* pdir, T* xacc,
-                        const float* dsrc, const LoadState* st, bool gamma) {
+                        const float* dsrc, const LoadState* st, bool gamma, const IrxFold& fold = IrxFold{}) {
   const Geo& g = ctx->geo;
   cpx<T>* sm = Sel<T>::sm(ctx) + (long long)l0 * main_cpx(g);
   cpx<T>* sn = Sel<T>::sn(ctx) + (long long)l0 * nyq_cpx(g);
-  XfwdArgs<T> xa{g, xmode, src, pdir, xacc, dsrc, sm, sn, Sel<T>::tw(ctx, 0), st};
+  XfwdArgs<T> xa{g, xmode, src, pdir, xacc, dsrc, sm, sn, Sel<T>::tw(ctx, 0), st, fold};
   // algorithmic bytes per launch (loads still iterating x per-load traffic)
   const double nl = std::min(ctx->nact, nload);
   const double cvs = (double)ctx->F * sizeof(T);
@@ -1055,8 +1055,9 @@ bool any_guess(const lsh_ctx* ctx, int nload) {
 // operator application q = L x gives r = b - q, and the solver scalars start
 // from ||r||^2 with the tolerance relative to ||b|| (SC_INITG); without r,
 // only ||b||^2 is formed and x keeps the guesses.
-lsh_status guess_init(lsh_ctx* ctx, int nload, double* x, double* r, LoadState* st, double tol) {
-  if (!any_guess(ctx, nload)) return cg_init<double>(ctx, nload, x, r, st, tol);
+lsh_status guess_init(lsh_ctx* ctx, int nload, double* x, double* r, LoadState* st, double tol,
+                      bool zero_x = true) {
+  if (!any_guess(ctx, nload)) return cg_init<double>(ctx, nload, zero_x ? x : nullptr, r, st, tol);
   const Geo& g = ctx->geo;
   const int nb = ew_blocks(g.nvox);
   const uint8_t* gflag = ctx->ptr<uint8_t>(ctx->off.guess);
@@ -1163,7 +1164,7 @@ lsh_status run_iteration(lsh_ctx* ctx, int slot, long long key, F&& enqueue) {
 // graph per parity; the unfused step and the persistent loop use p alone.
 template <typename T>
 lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, T* pb, LoadState* st, size_t st_off, int maxit,
-                   std::vector<LoadState>& hst) {
+                   std::vector<LoadState>& hst, bool flush = true) {
   const int period = check_period(ctx, nload);
   T* q = reinterpret_cast<T*>(Sel<T>::sm(ctx));
   STCHK(read_states(ctx, st_off, nload, hst));
@@ -1222,7 +1223,8 @@ lsh_status cg_loop(lsh_ctx* ctx, int nload, T* x, T* r, T* p, T* pb, LoadState* 
     }
   }
   ctx->xf_first = false;
-  return cg_flush<T>(ctx, nload, x, p, ctx->cg_fused ? pb : nullptr, st);
+  // without flush the caller applies the pending steps (the mixed path's refinement pass)
+  return flush ? cg_flush<T>(ctx, nload, x, p, ctx->cg_fused ? pb : nullptr, st) : LSH_OK;
 }
 
 // Fixed-point schemes on tau in place: basic (XI_BASIC) or Eyre--Milton (XI_EM).
@@ -2045,7 +2047,11 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
     float* d = ctx->ptr<float>(ctx->off.d32);
     float* r = ctx->ptr<float>(ctx->off.r32);
     float* p = ctx->ptr<float>(ctx->off.p32);
-    STCHK(guess_init(ctx, nload, x64, nullptr, sto, tol));  // x64 = 0 or the guess, outer ||b||^2
+    // x64 = 0 or the guess, outer ||b||^2.  Without guesses the first
+    // refinement pass writes x64 = d (zero for the loads it does not refine),
+    // so x64 is not zeroed here.
+    bool xzero = !any_guess(ctx, nload);
+    STCHK(guess_init(ctx, nload, x64, nullptr, sto, tol, !xzero));
     STCHK(cg_init<float>(ctx, nload, d, r, sti, 1e-4));      // d = 0, r = b
     STCHK(read_states(ctx, ctx->off.st_out, nload, hst));
     double eta = 1e-4;
@@ -2062,7 +2068,9 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
         // inner FP32 solve, then refresh the residual in FP64 (x64 += d inside)
         {
           TraceRange tr_in("lsh_solve: inner FP32 CG");
-          STCHK(cg_loop<float>(ctx, nload, d, r, p, ctx->ptr<float>(ctx->off.p32b), sti, ctx->off.st_in, budget, hin));
+          // pending x updates stay for the refinement pass to apply
+          STCHK(cg_loop<float>(ctx, nload, d, r, p, ctx->ptr<float>(ctx->off.p32b), sti, ctx->off.st_in, budget, hin,
+                               false));
         }
         STCHK(read_states(ctx, ctx->off.st_in, nload, hin));
         int used = 0;
@@ -2083,7 +2091,10 @@ lsh_status lsh_solve(lsh_ctx* ctx, int solver, int nload, const double* loads, d
       for (auto& sv : hst) ctx->nact += sv.active != 0;
       {
         TraceRange tr_ref("lsh_solve: FP64 refinement residual");
-        STCHK(forward_part<double>(ctx, 0, nload, XF_IRX, nullptr, x64, nullptr, d, sto, true));
+        // x64 += d plus the inner solve's pending steps (x64 = that, on the first pass from zero)
+        const IrxFold fold{p, ctx->cg_fused ? ctx->ptr<float>(ctx->off.p32b) : nullptr, sti, xzero ? 1 : 0};
+        STCHK(forward_part<double>(ctx, 0, nload, XF_IRX, nullptr, x64, nullptr, d, sto, true, fold));
+        xzero = false;
         int np = 0;
         STCHK(inverse_x<double>(ctx, 0, nload, XI_IRRES, x64, nullptr, r, sto, ctx->ptr<double>(ctx->off.partials),
                                 &np));
